@@ -1,0 +1,155 @@
+"""Seeded synthetic inputs for the coupled Navier-Stokes + Cahn-Hilliard step.
+
+This module is shared by the CPU oracle tests, the GPU tests and the benchmark.
+It only *draws* inputs; it contains none of the method's arithmetic (no
+dealiasing rule, no projection, no time stepping).  Every generator returns
+plain float64 host arrays in physical space with layout ``[z][y][x]`` (x
+fastest) on the triply periodic box ``[0, 2*pi)^3``.
+
+Inputs stand in for the paper's drop-laden turbulence (Sec. 4): a random-phase
+solenoidal velocity with energy spectrum E(k) ~ k^4 exp(-2 (k/k0)^2) and
+spherical drops with the equilibrium tanh interface profile of Sec. 2.1.1
+(equation ``width``).  The velocity is made solenoidal by taking the curl of a
+random vector potential, which is input synthesis, not the method's Leray
+projection.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+def grid_coords(n: int, length: float = TWO_PI) -> np.ndarray:
+    """Uniform collocation points x_j = j L / n, j = 0..n-1."""
+    return np.arange(n, dtype=np.float64) * (length / n)
+
+
+def _int_wavenumbers(n: int):
+    kz = np.fft.fftfreq(n, 1.0 / n)
+    ky = np.fft.fftfreq(n, 1.0 / n)
+    kx = np.fft.rfftfreq(n, 1.0 / n)
+    return np.meshgrid(kz, ky, kx, indexing="ij")
+
+
+def random_velocity(n: int, rng: np.random.Generator, k0: float = 4.0,
+                    u_rms: float = 1.0, kmax: float | None = None) -> np.ndarray:
+    """Random-phase solenoidal velocity, shape (3, n, n, n), float64.
+
+    A white-noise vector potential A is given the shell amplitude
+    |A(k)| ~ exp(-(k/k0)^2) (random phases from the noise), u = curl A is
+    formed spectrally, modes with |k| > kmax (default n/3 - 1, a sphere) are
+    dropped, and the field is scaled so that sqrt(<|u|^2>/3) = u_rms.
+    """
+    if kmax is None:
+        kmax = n / 3.0 - 1.0
+    KZ, KY, KX = _int_wavenumbers(n)
+    kmag = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    noise = rng.standard_normal((3, n, n, n))
+    a_hat = np.fft.rfftn(noise, axes=(1, 2, 3))
+    mag = np.abs(a_hat)
+    mag[mag == 0.0] = 1.0
+    amp = np.exp(-(kmag / k0) ** 2)
+    amp[kmag > kmax] = 0.0
+    amp[kmag == 0.0] = 0.0
+    a_hat = a_hat / mag * amp
+    ax, ay, az = a_hat[0], a_hat[1], a_hat[2]
+    # curl in Fourier space: (i k) x A, components ordered (x, y, z)
+    ux = 1j * (KY * az - KZ * ay)
+    uy = 1j * (KZ * ax - KX * az)
+    uz = 1j * (KX * ay - KY * ax)
+    u = np.stack([np.fft.irfftn(c, s=(n, n, n), axes=(0, 1, 2))
+                  for c in (ux, uy, uz)])
+    rms = math.sqrt(float(np.mean(u * u)))
+    if rms > 0.0:
+        u *= u_rms / rms
+    return u
+
+
+def drop_centres(rng: np.random.Generator, ndrops: int, radius: float,
+                 ch: float, length: float = TWO_PI, max_tries: int = 200000):
+    """Seeded rejection sampling of non-overlapping drop centres.
+
+    Two centres are accepted when their minimum-image distance is at least
+    2 R + 8 sqrt(2) Ch, so interfaces stay several widths apart.
+    """
+    gap = 2.0 * radius + 8.0 * math.sqrt(2.0) * ch
+    centres: list[np.ndarray] = []
+    tries = 0
+    while len(centres) < ndrops:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place %d drops of radius %g" % (ndrops, radius))
+        c = rng.uniform(0.0, length, size=3)
+        ok = True
+        for d in centres:
+            delta = np.abs(c - d)
+            delta = np.minimum(delta, length - delta)
+            if float(np.sqrt(np.sum(delta ** 2))) < gap:
+                ok = False
+                break
+        if ok:
+            centres.append(c)
+    return np.array(centres)
+
+
+def drops_phi(n: int, centres: np.ndarray, radius: float, ch: float,
+              length: float = TWO_PI) -> np.ndarray:
+    """Phase field of spherical drops, +1 inside, -1 outside.
+
+    phi = max_i tanh((R - d_i) / (sqrt(2) Ch)), d_i the minimum-image
+    distance to centre i (equilibrium profile of Sec. 2.1.1).
+    """
+    x = grid_coords(n, length)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    phi = np.full((n, n, n), -1.0)
+    w = math.sqrt(2.0) * ch
+    for c in np.atleast_2d(centres):
+        dz = np.abs(Z - c[2]); dz = np.minimum(dz, length - dz)
+        dy = np.abs(Y - c[1]); dy = np.minimum(dy, length - dy)
+        dx = np.abs(X - c[0]); dx = np.minimum(dx, length - dx)
+        d = np.sqrt(dx * dx + dy * dy + dz * dz)
+        phi = np.maximum(phi, np.tanh((radius - d) / w))
+    return phi
+
+
+# ---------------------------------------------------------------------------
+# named workloads (box)
+# ---------------------------------------------------------------------------
+
+def box_case(name: str):
+    """Return (params dict, u (3,n,n,n), phi (n,n,n)) for a named box workload.
+
+    ``single_drop_32``: 32^3, Re=100, We=1, Ch=0.05, Pe=1/Ch, dt=1e-3, one
+    centred drop of radius 0.8, seed 1.
+    ``drops16_128``: 128^3, Re=300, We=1, Ch=0.025, Pe=1/Ch, dt=5e-4, 16 drops
+    of radius 0.4 at seeded non-overlapping centres, seed 2.
+    Smaller variants (``drops4_48``, ``drops2_64``) keep the second recipe on
+    grids the oracle steps in well under a second.
+    """
+    if name == "single_drop_32":
+        n, seed = 32, 1
+        p = dict(n=n, re=100.0, we=1.0, ch=0.05, pe=20.0, dt=1e-3)
+        rng = np.random.default_rng(seed)
+        u = random_velocity(n, rng, k0=4.0)
+        c = np.array([[math.pi, math.pi, math.pi]])
+        phi = drops_phi(n, c, 0.8, p["ch"])
+        return p, u, phi
+    recipes = {
+        "drops16_128": (128, 2, 16, 0.4, 300.0, 1.0, 0.025, 5e-4),
+        "drops2_64": (64, 12, 2, 0.6, 300.0, 1.0, 0.05, 5e-4),
+        "drops4_48": (48, 11, 4, 0.5, 200.0, 2.0, 0.06, 5e-4),
+        "drops3_96": (96, 13, 3, 0.5, 300.0, 1.0, 0.04, 5e-4),
+        "drops2_256": (256, 14, 2, 0.5, 300.0, 1.0, 0.02, 2.5e-4),
+    }
+    if name not in recipes:
+        raise KeyError(name)
+    n, seed, nd, r, re, we, ch, dt = recipes[name]
+    p = dict(n=n, re=re, we=we, ch=ch, pe=1.0 / ch, dt=dt)
+    rng = np.random.default_rng(seed)
+    u = random_velocity(n, rng, k0=4.0)
+    c = drop_centres(rng, nd, r, ch)
+    phi = drops_phi(n, c, r, ch)
+    return p, u, phi

@@ -1,0 +1,367 @@
+"""Pins of the box oracle against facts fixed by the mathematics or the paper.
+
+Each test checks the oracle against something other than itself: brute-force
+sums on tiny grids, closed forms of trigonometric fields, exact invariants,
+or exact solutions of linear problems.  These run on the CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import box
+from paper_2406_01322_amd import synth
+
+
+def _grid(n):
+    x = 2.0 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return X, Y, Z
+
+
+def _signed(k, n):
+    return k if k < n / 2 else k - n
+
+
+# ---------------------------------------------------------------- index maps
+
+def test_wavenumber_maps_small():
+    kz, ky, kx = box.wavenumbers(8)
+    assert list(kz) == [0, 1, 2, 3, -4, -3, -2, -1]
+    assert list(ky) == list(kz)
+    assert list(kx) == [0, 1, 2, 3, 4]
+
+
+@pytest.mark.parametrize("n,K", [(8, 2), (12, 3), (32, 10), (48, 15), (64, 21), (96, 31), (128, 42), (256, 85)])
+def test_cutoff_values_and_retained_counts(n, K):
+    assert box.cutoff(n) == K
+    D = box.dealias_mask(n)
+    assert int(D.sum()) == (2 * K + 1) ** 2 * (K + 1)
+    # alias-free for quadratic products, and no larger K is
+    assert n - 2 * K > K and not (n - 2 * (K + 1) > K + 1)
+
+
+# ---------------------------------------------------------------- transforms
+
+@pytest.mark.parametrize("n", [4, 6, 8, 12])
+def test_forward_matches_naive_dft(n):
+    rng = np.random.default_rng(100 + n)
+    f = rng.standard_normal((n, n, n))
+    X, Y, Z = _grid(n)
+    got = box.fwd(f)
+    want = np.zeros_like(got)
+    for a in range(n):
+        kz = _signed(a, n)
+        for b in range(n):
+            ky = _signed(b, n)
+            for c in range(n // 2 + 1):
+                want[a, b, c] = np.sum(f * np.exp(-1j * (c * X + ky * Y + kz * Z))) / n ** 3
+    assert np.max(np.abs(got - want)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [6, 8, 12])
+def test_inverse_single_mode_closed_form(n):
+    X, Y, Z = _grid(n)
+    rng = np.random.default_rng(7)
+    for (kz, ky, kx) in [(1, -2, 1), (0, 1, 2), (-1, 0, 1), (2, 2, 0)]:
+        a = complex(rng.standard_normal(), rng.standard_normal())
+        fh = np.zeros((n, n, n // 2 + 1), complex)
+        fh[kz % n, ky % n, kx] = a
+        if kx == 0:      # the half spectrum at kx = 0 needs the conjugate partner
+            fh[(-kz) % n, (-ky) % n, 0] = np.conj(a)
+        got = box.inv(fh, n)
+        want = 2.0 * np.real(a * np.exp(1j * (kx * X + ky * Y + kz * Z)))
+        assert np.max(np.abs(got - want)) < 1e-13
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_spectral_derivative_of_single_mode(axis):
+    n = 16
+    X, Y, Z = _grid(n)
+    k = (3, -2, 4)
+    theta = 0.37
+    arg = k[0] * X + k[1] * Y + k[2] * Z + theta
+    f = np.cos(arg)
+    want = -k[axis] * np.sin(arg)
+    got = box.inv(box.deriv(box.fwd(f), axis), n)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [12, 16])
+def test_dealiased_product_equals_bruteforce_convolution(n):
+    """fwd(a b) restricted to the band equals the exact convolution of the
+    band-limited spectra (no aliasing), for N where K = floor((N-1)/3)."""
+    K = box.cutoff(n)
+    rng = np.random.default_rng(n)
+    D = box.dealias_mask(n)
+    a = box.inv(box.fwd(rng.standard_normal((n, n, n))) * D, n)
+    b = box.inv(box.fwd(rng.standard_normal((n, n, n))) * D, n)
+    ah = np.fft.fftn(a, norm="forward")           # full spectra
+    bh = np.fft.fftn(b, norm="forward")
+    modes = [(p, q, r) for p in range(-K, K + 1) for q in range(-K, K + 1) for r in range(-K, K + 1)]
+    got = box.fwd(a * b)
+    for (kz, ky, kx) in [(0, 0, 0), (1, -2, 3), (K, K, K), (-K, 0, K), (2, K, 1), (-1, -K, 0)]:
+        s = 0.0
+        for (pz, py, px) in modes:
+            qz, qy, qx = kz - pz, ky - py, kx - px
+            if max(abs(qz), abs(qy), abs(qx)) > K:
+                continue
+            s += ah[pz % n, py % n, px % n] * bh[qz % n, qy % n, qx % n]
+        assert abs(got[kz % n, ky % n, kx] - s) < 1e-13
+
+
+def test_naive_third_rule_would_alias_at_12():
+    """At N = 12 the naive cut-off N//3 = 4 lets a product alias into the band,
+    which the rule K = floor((N-1)/3) = 3 prevents."""
+    n, Kbad = 12, 4
+    X, Y, Z = _grid(n)
+    a = np.cos(Kbad * X)
+    prod = box.fwd(a * a)       # exact: 1/2 + cos(8x)/2; cos(8x) aliases to k = -4
+    assert abs(prod[0, 0, 4]) > 0.2   # aliased energy sits at kx = 4 = Kbad
+    assert box.cutoff(n) < 4
+
+
+# ---------------------------------------------------------------- projection
+
+def test_projection_invariants():
+    n = 16
+    rng = np.random.default_rng(3)
+    D = box.dealias_mask(n)
+    v = box.fwd(rng.standard_normal((3, n, n, n))) * D
+    pv = box.project(v)
+    KX, KY, KZ = box.kgrid(n)
+    kmag = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    div = np.abs(KX * pv[0] + KY * pv[1] + KZ * pv[2])
+    vmag = np.sqrt(np.sum(np.abs(pv) ** 2, axis=0))
+    ok = kmag > 0
+    assert np.max(div[ok] / (kmag[ok] * np.maximum(vmag[ok], 1e-300))) < 1e-15
+    assert np.max(np.abs(box.project(pv) - pv)) < 1e-15          # idempotent
+    psi = box.fwd(rng.standard_normal((n, n, n))) * D
+    grad = np.stack([box.deriv(psi, a) for a in range(3)])
+    assert np.max(np.abs(box.project(grad))) < 1e-14              # kills gradients
+
+
+# ---------------------------------------------------------------- nonlinear terms (closed forms)
+
+def test_convective_term_closed_form():
+    """u = (sin y, sin z, sin x) is solenoidal and u.grad(u) = (sin z cos y, sin x cos z, sin y cos x)."""
+    n = 16
+    X, Y, Z = _grid(n)
+    prm = box.Params(n=n, re=100.0, we=1.0, ch=0.1, pe=10.0, dt=1e-3)
+    u = np.stack([np.sin(Y), np.sin(Z), np.sin(X)])
+    phi = -np.ones((n, n, n))
+    st = box.init_state(u, phi, prm)
+    S, Sphi, _ = box.nonlinear_terms(st["uh"], st["ph"], prm)
+    got = box.inv(S, n)
+    want = -np.stack([np.sin(Z) * np.cos(Y), np.sin(X) * np.cos(Z), np.sin(Y) * np.cos(X)])
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+def test_korteweg_force_closed_form():
+    """phi = 0.5 (sin x + sin y): div(|g|^2 I - g g) = 0.25 (cos x sin y, sin x cos y, 0)."""
+    n = 16
+    X, Y, Z = _grid(n)
+    prm = box.Params(n=n, re=100.0, we=2.0, ch=0.1, pe=10.0, dt=1e-3)
+    u = np.zeros((3, n, n, n))
+    phi = 0.5 * (np.sin(X) + np.sin(Y))
+    st = box.init_state(u, phi, prm)
+    S, _, _ = box.nonlinear_terms(st["uh"], st["ph"], prm)
+    got = box.inv(S, n)
+    c = 3.0 / math.sqrt(8.0) * prm.ch / prm.we
+    want = 0.25 * c * np.stack([np.cos(X) * np.sin(Y), np.sin(X) * np.cos(Y), 0 * X])
+    assert np.max(np.abs(got - want)) < 1e-14
+
+
+def test_phase_field_rhs_closed_form():
+    """u = (sin y, sin z, sin x), phi = a cos x:
+    S_phi = -u.grad(phi) + lap(phi^3)/Pe - (1 + s Ch^2)/Pe lap(phi), with
+    phi^3 = a^3 (3 cos x + cos 3x)/4, evaluated by hand."""
+    n = 16
+    a = 0.7
+    X, Y, Z = _grid(n)
+    prm = box.Params(n=n, re=100.0, we=1.0, ch=0.1, pe=5.0, dt=1e-3, s=3.0)
+    u = np.stack([np.sin(Y), np.sin(Z), np.sin(X)])
+    phi = a * np.cos(X)
+    st = box.init_state(u, phi, prm)
+    _, Sphi, _ = box.nonlinear_terms(st["uh"], st["ph"], prm)
+    got = box.inv(Sphi, n)
+    adv = np.sin(Y) * (-a * np.sin(X))
+    lap_cube = a ** 3 * (-3.0 * np.cos(X) - 9.0 * np.cos(3 * X)) / 4.0
+    lap_phi = -a * np.cos(X)
+    want = -adv + lap_cube / prm.pe - (1.0 + 3.0 * prm.ch ** 2) / prm.pe * lap_phi
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+def test_planar_interface_is_ch_equilibrium():
+    """Two planar tanh interfaces (equation ``width``) make mu = phi^3 - phi - Ch^2 lap phi
+    vanish up to the band truncation of the profile and the exponentially small overlap of the
+    two tails, so one CH step with u = 0 barely moves phi.  Were the bulk term's sign flipped,
+    lap(mu)/Pe would be the size of lap(2 (phi^3 - phi))/Pe, three orders larger."""
+    n = 64
+    ch = 0.2
+    X, Y, Z = _grid(n)
+    w = math.sqrt(2.0) * ch
+    phi = np.tanh((Z - np.pi / 2) / w) - np.tanh((Z - 3 * np.pi / 2) / w) - 1.0
+    prm = box.Params(n=n, re=100.0, we=1.0, ch=ch, pe=1.0, dt=1e-3, s=1.0)
+    st = box.init_state(np.zeros((3, n, n, n)), phi, prm)
+    st1 = box.step(st, prm)
+    rate = np.max(np.abs(box.inv(st1["ph"] - st["ph"], n))) / prm.dt
+    bad = np.max(np.abs(box.inv(box.deriv(box.deriv(box.fwd(2.0 * (phi ** 3 - phi)), 2), 2), n))) / prm.pe
+    assert rate < 1e-3 * bad
+    assert rate < 0.01
+
+
+def test_laplace_pressure_jump_of_spherical_drop():
+    """The Korteweg force with coefficient 3/sqrt(8) Ch/We gives surface tension 1/We:
+    a resting spherical drop has the Laplace jump p_in - p_out = 2 sigma / R = 2 / (We R).
+    The pressure solves lap p = div S with S the oracle's nonlinear term at u = 0."""
+    n = 64
+    ch, we, R = 0.12, 2.0, 1.5
+    prm = box.Params(n=n, re=100.0, we=we, ch=ch, pe=10.0, dt=1e-3)
+    c = np.array([[np.pi, np.pi, np.pi]])
+    phi = synth.drops_phi(n, c, R, ch)
+    st = box.init_state(np.zeros((3, n, n, n)), phi, prm)
+    S, _, _ = box.nonlinear_terms(st["uh"], st["ph"], prm)
+    KX, KY, KZ = box.kgrid(n)
+    k2 = KX ** 2 + KY ** 2 + KZ ** 2
+    k2[0, 0, 0] = 1.0
+    divS = 1j * (KX * S[0] + KY * S[1] + KZ * S[2])
+    p = box.inv(-divS / k2, n)
+    jump = p[n // 2, n // 2, n // 2] - p[0, 0, 0]
+    assert abs(jump - 2.0 / (we * R)) < 0.01 * 2.0 / (we * R)
+
+
+# ---------------------------------------------------------------- linear parts: exact discrete and continuous solutions
+
+def test_viscous_shear_mode_decay():
+    """u = (sin 3z, 0, 0), phi = -1: the nonlinear terms vanish, each step multiplies the mode by
+    the Crank-Nicolson factor, and after 10 steps the amplitude is within the CN error bound of
+    exp(-nu k^2 t)."""
+    n, k = 16, 3
+    X, Y, Z = _grid(n)
+    prm = box.Params(n=n, re=100.0, we=1.0, ch=0.1, pe=10.0, dt=1e-3)
+    u = np.stack([np.sin(k * Z), 0 * Z, 0 * Z])
+    st = box.init_state(u, -np.ones((n, n, n)), prm)
+    a0 = st["uh"][0, k, 0, 0]
+    x = prm.dt * k * k / prm.re
+    for m in range(1, 11):
+        st = box.step(st, prm)
+        ratio = st["uh"][0, k, 0, 0] / a0
+        assert abs(ratio - ((1 - x / 2) / (1 + x / 2)) ** m) < 1e-15
+    exact = math.exp(-k * k / prm.re * 10 * prm.dt)
+    assert abs(ratio.real - exact) <= 10 * x ** 3 / 12 + 1e-15
+
+
+def test_spinodal_growth_matches_continuous_rate():
+    """phi = 1e-6 cos(k.x) about phi = 0 with u = 0 grows at sigma = (k^2 - Ch^2 k^4)/Pe
+    (linearised CH); with s = 0 and small dt the discrete rate is within O(dt) of it."""
+    n = 16
+    X, Y, Z = _grid(n)
+    ch, pe = 0.1, 1.0
+    prm = box.Params(n=n, re=1.0, we=1.0, ch=ch, pe=pe, dt=1e-5, s=1e-30)
+    phi = 1e-6 * np.cos(3 * X + 2 * Y)
+    st = box.init_state(np.zeros((3, n, n, n)), phi, prm)
+    a0 = st["ph"][0, 2, 3].real
+    nst = 200
+    st = box.run(st, prm, nst)
+    rate = math.log(st["ph"][0, 2, 3].real / a0) / (nst * prm.dt)
+    k2 = 13.0
+    sigma = (k2 - ch * ch * k2 * k2) / pe
+    assert abs(rate - sigma) < 2.0 * sigma * sigma * prm.dt + 1e-3 * sigma
+    # a mode beyond the 2/3 band is removed at initialisation
+    phi = 1e-6 * np.cos(7 * X)
+    st = box.init_state(np.zeros((3, n, n, n)), phi, prm)
+    assert st["ph"][0, 0, 7] == 0.0  # outside the band at N=16 (K=5): removed by the mask
+
+
+def test_ab2_ie_characteristic_root():
+    """Default s: the measured per-step amplification of a linear CH mode equals the dominant
+    root of (1 + dt L) z^2 - (1 + 1.5 dt E) z + 0.5 dt E = 0 (AB2 on E, implicit Euler on L)."""
+    n = 16
+    X, Y, Z = _grid(n)
+    prm = box.Params(n=n, re=1.0, we=1.0, ch=0.05, pe=20.0, dt=1e-3)
+    s = prm.split_s()
+    phi = 1e-6 * np.cos(4 * X)
+    st = box.init_state(np.zeros((3, n, n, n)), phi, prm)
+    amps = [st["ph"][0, 0, 4].real]
+    for _ in range(40):
+        st = box.step(st, prm)
+        amps.append(st["ph"][0, 0, 4].real)
+    k2 = 16.0
+    L = prm.ch ** 2 / prm.pe * (k2 * k2 + s * k2)
+    E = (1.0 + s * prm.ch ** 2) / prm.pe * k2
+    roots = np.roots([1.0 + prm.dt * L, -(1.0 + 1.5 * prm.dt * E), 0.5 * prm.dt * E])
+    zmax = max(roots, key=abs).real
+    assert abs(amps[-1] / amps[-2] - zmax) < 1e-9
+
+
+# ---------------------------------------------------------------- invariants over steps
+
+def test_step_invariants_single_drop_32():
+    p, u, phi = synth.box_case("single_drop_32")
+    prm = box.Params(**p)
+    st = box.init_state(u, phi, prm)
+    mean0 = st["ph"][0, 0, 0]
+    for _ in range(5):
+        _, _, s0 = box.nonlinear_terms(st["uh"], st["ph"], prm)
+        assert abs(s0) < 1e-13
+        st = box.step(st, prm)
+        assert st["ph"][0, 0, 0] == mean0                      # bitwise
+        d = box.diagnostics(st, prm.n)
+        assert d["max_div"] < 1e-15 and d["finite"]
+    D = box.dealias_mask(prm.n)
+    assert np.all(st["uh"][:, ~D] == 0) and np.all(st["ph"][~D] == 0)
+
+
+def test_helmholtz_manufactured_solution():
+    n = 16
+    X, Y, Z = _grid(n)
+    lam = 2.5
+    f = np.sin(2 * X) * np.cos(3 * Y) + 0.3 * np.cos(Z - X)
+    # (lap - lam) f computed by hand
+    g = -(13 + lam) * np.sin(2 * X) * np.cos(3 * Y) - (2 + lam) * 0.3 * np.cos(Z - X)
+    got = box.inv(box.solve_helmholtz(box.fwd(g), lam), n)
+    assert np.max(np.abs(got - f)) < 1e-14
+    # lam = 0: the k = 0 mode is dropped
+    g0 = 1.0 - 13.0 * np.sin(2 * X) * np.cos(3 * Y)
+    got0 = box.inv(box.solve_helmholtz(box.fwd(g0), 0.0), n)
+    assert np.max(np.abs(got0 - np.sin(2 * X) * np.cos(3 * Y))) < 1e-14
+
+
+def test_divergence_and_convective_forms_agree():
+    """Under the 2/3 rule with div u = 0, the convective form used here and the divergence form
+    d_j(u_i u_j) give the same projected term to rounding (both products are alias-free)."""
+    p, u, phi = synth.box_case("single_drop_32")
+    prm = box.Params(**p)
+    n = prm.n
+    st = box.init_state(u, phi, prm)
+    D = box.dealias_mask(n)
+    uu = box.inv(st["uh"], n)
+    KX, KY, KZ = box.kgrid(n)
+    kv = (KX, KY, KZ)
+    div_form = np.stack([sum(1j * kv[j] * box.fwd(uu[i] * uu[j]) * D for j in range(3)) for i in range(3)])
+    conv = np.stack([sum(uu[j] * box.inv(1j * kv[j] * st["uh"][i], n) for j in range(3)) for i in range(3)])
+    conv_form = np.stack([box.fwd(conv[i]) * D for i in range(3)])
+    a = box.project(div_form)
+    b = box.project(conv_form)
+    assert np.max(np.abs(a - b)) < 1e-14 * max(1.0, np.max(np.abs(a)))
+
+
+def test_ns_ab2_cn_under_frozen_capillary_forcing():
+    """phi = 0.5 (sin x + sin 2y) frozen (Pe huge, s ~ 0) and u(0) = 0: the projected Korteweg
+    force is, by hand, F = c (0.6 cos x sin 2y, -0.3 sin x cos 2y, 0) with c = (3/sqrt8) Ch/We,
+    and u solves du/dt = F - nu k^2 u (k^2 = 5), i.e. u(t) = F (1 - exp(-nu k^2 t)) / (nu k^2),
+    up to O(dt^2) and the O(t |F|) self-advection."""
+    n = 16
+    X, Y, Z = _grid(n)
+    prm = box.Params(n=n, re=10.0, we=1.0, ch=0.1, pe=1e15, dt=1e-3, s=1e-30)
+    phi = 0.5 * (np.sin(X) + np.sin(2 * Y))
+    st = box.init_state(np.zeros((3, n, n, n)), phi, prm)
+    st = box.run(st, prm, 10)
+    t = 10 * prm.dt
+    c = 3.0 / math.sqrt(8.0) * prm.ch / prm.we
+    F = c * np.stack([0.6 * np.cos(X) * np.sin(2 * Y), -0.3 * np.sin(X) * np.cos(2 * Y), 0 * X])
+    nu_k2 = 5.0 / prm.re
+    want = F * (1.0 - math.exp(-nu_k2 * t)) / nu_k2
+    got = box.inv(st["uh"], n)
+    assert np.max(np.abs(got - want)) < 1e-4 * np.max(np.abs(want))
