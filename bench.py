@@ -1,0 +1,172 @@
+"""Throughput of the coupled NS + CH pseudo-spectral step on one MI355X.
+
+Workload: triply periodic box, 128^3 Fourier grid, 16 drops of radius 0.4 at
+seeded non-overlapping centres, random-phase solenoidal velocity with
+E(k) ~ k^4 exp(-2 (k/4)^2), u_rms = 1; Re = 300, We = 1, Ch = 0.025,
+Pe = 1/Ch, dt = 5e-4 (seed 2).  One "step" is one full time step (all
+transforms, products, RHS assembly, projection and implicit updates).
+
+`value` is the MIXED path (FP32 transforms and products, FP64 state, RHS
+assembly, projection and update) in grid-points x time-steps per second; the
+plain FP64 path is reported beside it.  The dominant kernel's HBM roofline is
+measured live with HIP events on the library's stream; `cpu_baseline` times
+the FP64 oracle on the host on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-points·timesteps/s for NS+CH step (FP64 vs mixed) + % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+STAGES = ["y_inverse", "x_products", "y_forward", "z_update"]
+KERNELS = {"y_inverse": "k_lines<inverse>", "x_products": "k_xstep", "y_forward": "k_lines<forward>",
+           "z_update": "k_zstep"}
+
+
+def band(n):
+    K = (n - 1) // 3
+    C, H = 2 * K + 1, K + 1
+    return K, C, H, C * H, C * C * H
+
+
+def stage_bytes(n, cplx_bytes):
+    """Algorithmic HBM bytes of one launch of each stage kernel: every array the
+    kernel must read or write, counted once, at its stored (retained-band) size."""
+    K, C, H, Q, M = band(n)
+    t = cplx_bytes
+    nq, nnh = n * Q, n * n * H
+    return {
+        "y_inverse": (5 * nq + 6 * nnh) * t,
+        "x_products": (6 * nnh + 8 * nnh) * t,
+        "y_forward": (8 * nnh + 8 * nq) * t,
+        "z_update": (8 * nq + 5 * nq) * t + 4 * 4 * M * 16,  # + state and history read and written, FP64
+    }
+
+
+def step_model_bytes(n, mixed):
+    """Whole-step byte model: every method-defined intermediate written once and read
+    once, spectral arrays at their retained size (7 inverse outputs, 8 products,
+    8 forward inputs; state read twice and written once, history read and written,
+    8 RHS fields written and read)."""
+    P = n ** 3
+    M = band(n)[4]
+    w_phys = 4 if mixed else 8
+    w_rhs = 8 if mixed else 16
+    return w_phys * 30 * P + 16 * 2 * 20 * M + w_rhs * 2 * 16 * M
+
+
+def run_gpu(precision, n, p, u, phi, steps, warmup):
+    import torch
+    from paper_2406_01322_amd.psms import Solver
+    s = Solver(n, p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision)
+    s.init_state(torch.from_numpy(u).cuda(), torch.from_numpy(phi).cuda())
+    if warmup > 0:
+        s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = s.stage_times(steps)          # the timed steps, HIP events around each kernel
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = s.diagnostics()
+    if d["nonfinite"] or not (d["max_div"] < 1e-8):
+        raise RuntimeError("%s run produced a bad state: %s" % (precision, d))
+    wall = t1 - t0
+    return dict(wall=wall, ms_per_step=1e3 * wall / steps, value=n ** 3 * steps / wall,
+                stage_ms=dict(zip(STAGES, ms)), diag=d)
+
+
+def cpu_baseline(n, p, u, phi, budget_s=20.0):
+    """The FP64 oracle on the host: init, then as many steps as fit in ~budget_s."""
+    import numpy as np  # noqa: F401
+    from oracle import box
+    prm = box.Params(**p)
+    st = box.init_state(u, phi, prm)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        st = box.step(st, prm)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= 20:
+            break
+    return dict(value=n ** 3 * steps / el, unit="grid-points*timesteps/s", cores=1, kind="oracle",
+                sample="%d FP64 oracle steps of the %d^3 workload after init (numpy pocketfft, "
+                       "single-threaded), %.1f s" % (steps, n, el))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr, flush=True)
+        sys.exit(2)
+    import torch
+    from paper_2406_01322_amd import synth
+
+    name = "drops16_128"
+    p, u, phi = synth.box_case(name)
+    n = p["n"]
+    precs = [args.only] if args.only else ["fp64", "mixed"]
+    res = {}
+    for prec in precs:
+        res[prec] = run_gpu(prec, n, p, u, phi, args.steps, args.warmup)
+        print("[bench] %s: %.4f ms/step, stages %s" % (prec, res[prec]["ms_per_step"],
+              {k: round(v, 4) for k, v in res[prec]["stage_ms"].items()}), file=sys.stderr, flush=True)
+    head = "mixed" if "mixed" in res else "fp64"
+    r = res[head]
+    cb = 8 if head == "mixed" else 16
+    sb = stage_bytes(n, cb)
+    dom = max(r["stage_ms"], key=lambda k: r["stage_ms"][k])
+    achieved = sb[dom] / (r["stage_ms"][dom] * 1e-3) / 1e9
+    step_bytes = step_model_bytes(n, head == "mixed")
+    out = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "grid-points*timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "periodic box 128^3, 16 drops R=0.4, Re=300, We=1, Ch=0.025, Pe=40, dt=5e-4, seed 2",
+                   "n": n, "precision": head,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": sb[dom]},
+        "stage_ms": r["stage_ms"],
+        "stage_gbs": {k: sb[k] / (r["stage_ms"][k] * 1e-3) / 1e9 for k in STAGES},
+        "step_model": {"bytes_per_step": step_bytes,
+                       "frac_of_hbm": step_bytes * r["value"] / n ** 3 / (HBM_PEAK_GBS * 1e9)},
+    }
+    if "fp64" in res and "mixed" in res:
+        out["fp64"] = {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
+                       "stage_ms": res["fp64"]["stage_ms"]}
+        out["speedup_mixed_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, p, u, phi)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,584 @@
+// Host side of the psms C ABI: parameter validation, workspace carving, FFT
+// plans and twiddle tables, and the sequencing of the step's kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/psms.h"
+#include "box_kernels.hpp"
+
+using psms::BoxGeom;
+using psms::cpx;
+using psms::FftPlan;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(PSMS_E_LAUNCH, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Radix plans: E = 8 for 2^m, E = 12 for 3 * 2^m.
+bool make_plan(int n, FftPlan* pl, int* E) {
+  std::vector<int> r;
+  switch (n) {
+    case 8: r = {8}; *E = 8; break;
+    case 16: r = {4, 4}; *E = 8; break;
+    case 32: r = {8, 4}; *E = 8; break;
+    case 64: r = {8, 8}; *E = 8; break;
+    case 128: r = {8, 4, 4}; *E = 8; break;
+    case 256: r = {8, 8, 4}; *E = 8; break;
+    case 512: r = {8, 8, 8}; *E = 8; break;
+    case 12: r = {3, 4}; *E = 12; break;
+    case 24: r = {3, 4, 2}; *E = 12; break;
+    case 48: r = {3, 4, 4}; *E = 12; break;
+    case 96: r = {3, 4, 4, 2}; *E = 12; break;
+    case 192: r = {3, 4, 4, 4}; *E = 12; break;
+    case 384: r = {3, 4, 4, 4, 2}; *E = 12; break;
+    default: return false;
+  }
+  std::memset(pl, 0, sizeof(*pl));
+  pl->n = n;
+  pl->nstage = int(r.size());
+  for (size_t i = 0; i < r.size(); ++i) pl->radix[i] = r[i];
+  pl->tpl = n / *E;
+  return true;
+}
+
+// Row pairs per workgroup of the fused x stage: 8 fields x P pairs x tpl
+// threads <= 256, P | n/2.
+int xstep_pairs(int n, int tpl) {
+  int P = 256 / (8 * tpl);
+  if (P < 1) P = 1;
+  while ((n / 2) % P) --P;
+  return P;
+}
+
+struct Layout {
+  size_t state, hist, bufa, bufb, tw64, tw32, diag, diag_out, total;
+  size_t bufa_bytes, bufb_bytes;
+};
+
+constexpr int kDiagBlocks = 1024;
+
+BoxGeom make_geom(int n) {
+  BoxGeom g;
+  g.n = n;
+  g.K = (n - 1) / 3;
+  g.C = 2 * g.K + 1;
+  g.H = g.K + 1;
+  g.Q = (long long)g.C * g.H;
+  g.M = g.Q * g.C;
+  return g;
+}
+
+Layout make_layout(const psms_params& p) {
+  const BoxGeom g = make_geom(p.n);
+  const size_t n = size_t(p.n), nh = n / 2 + 1;
+  const size_t tp = (p.precision == PSMS_MIXED) ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  const size_t full64 = n * n * nh * sizeof(cpx<double>);
+  const size_t y = 6 * n * n * size_t(g.H) * tp, w = 8 * n * size_t(g.Q) * tp;
+  const size_t x = 8 * n * n * size_t(g.H) * tp, gz = 5 * n * size_t(g.Q) * tp;
+  Layout L{};
+  L.bufa_bytes = std::max(std::max(y, w), full64);
+  L.bufb_bytes = std::max(std::max(x, gz), full64);
+  size_t off = 0;
+  L.state = off; off = align256(off + 4 * size_t(g.M) * sizeof(cpx<double>));
+  L.hist = off; off = align256(off + 4 * size_t(g.M) * sizeof(cpx<double>));
+  L.bufa = off; off = align256(off + L.bufa_bytes);
+  L.bufb = off; off = align256(off + L.bufb_bytes);
+  L.tw64 = off; off = align256(off + n * sizeof(cpx<double>));
+  L.tw32 = off; off = align256(off + n * sizeof(cpx<float>));
+  L.diag = off; off = align256(off + 4 * kDiagBlocks * sizeof(double));
+  L.diag_out = off; off = align256(off + 8 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int validate(const psms_params* p) {
+  if (!p) return fail(PSMS_E_INVAL, "params is NULL");
+  if (p->geometry == PSMS_CHANNEL) return fail(PSMS_E_NOTSUP, "channel geometry is not implemented by this library");
+  if (p->geometry != PSMS_BOX) return fail(PSMS_E_INVAL, "geometry must be PSMS_BOX");
+  FftPlan pl;
+  int E;
+  if (!make_plan(p->n, &pl, &E))
+    return fail(PSMS_E_INVAL, "n must be one of 8,12,16,24,32,48,64,96,128,192,256,384,512");
+  if (p->precision != PSMS_FP64 && p->precision != PSMS_MIXED) return fail(PSMS_E_INVAL, "precision must be FP64 or MIXED");
+  if (p->reserved != 0) return fail(PSMS_E_INVAL, "reserved must be 0");
+  const double v[5] = {p->re, p->we, p->ch, p->pe, p->dt};
+  const char* nm[5] = {"re", "we", "ch", "pe", "dt"};
+  for (int i = 0; i < 5; ++i)
+    if (!(v[i] > 0.0) || !std::isfinite(v[i])) return fail(PSMS_E_INVAL, std::string(nm[i]) + " must be finite and > 0");
+  if (!std::isfinite(p->s)) return fail(PSMS_E_INVAL, "s must be finite");
+  return PSMS_OK;
+}
+
+}  // namespace
+
+struct psms_ctx {
+  psms_params p;
+  BoxGeom g;
+  FftPlan plan;
+  int E;
+  int xP;
+  double s;
+  hipStream_t stream;
+  Layout lay;
+  char* ws;
+  cpx<double>* state;
+  cpx<double>* hist;
+  void* bufa;
+  void* bufb;
+  cpx<double>* tw64;
+  cpx<float>* tw32;
+  double* diag;
+  double* diag_out;
+  int have_state;
+  int g_valid;  // the z-inverse of the current state sits in bufb
+  int nstep;
+};
+
+namespace {
+
+psms::StepCoef step_coef(const psms_ctx* c) {
+  psms::StepCoef sc;
+  const psms_params& p = c->p;
+  sc.dt = p.dt;
+  sc.nu = 1.0 / p.re;
+  sc.ch2_pe = p.ch * p.ch / p.pe;
+  sc.s = c->s;
+  sc.inv_pe = 1.0 / p.pe;
+  sc.e_coef = (1.0 + c->s * p.ch * p.ch) / p.pe;
+  const double n = double(p.n);
+  sc.inv_n3 = 1.0 / (n * n * n);
+  sc.ab1 = (c->nstep == 0) ? 1 : 0;
+  return sc;
+}
+
+// z-inverse of the current state into bufb (the input of the next step).
+template <typename T>
+hipError_t prologue(psms_ctx* c) {
+  const cpx<T>* tw = std::is_same<T, double>::value ? reinterpret_cast<const cpx<T>*>(c->tw64)
+                                                     : reinterpret_cast<const cpx<T>*>(c->tw32);
+  psms::StepCoef sc = step_coef(c);
+  return psms::launch_zstep<T>(c->E, nullptr, c->state, c->hist, static_cast<cpx<T>*>(c->bufb), tw, c->plan, c->g, sc,
+                               0, c->stream);
+}
+
+template <typename T>
+hipError_t one_step(psms_ctx* c, hipEvent_t* ev = nullptr) {
+  const cpx<T>* tw = std::is_same<T, double>::value ? reinterpret_cast<const cpx<T>*>(c->tw64)
+                                                     : reinterpret_cast<const cpx<T>*>(c->tw32);
+  const BoxGeom& g = c->g;
+  const int n = g.n;
+  hipError_t e;
+  if (ev && (e = hipEventRecord(ev[0], c->stream)) != hipSuccess) return e;
+  // y-inverse: G [5][n][C][H] -> Y [6][n][n][H]; output 4 is i ky phi
+  psms::LineArgs ya{};
+  ya.pl = c->plan;
+  ya.n_in = g.C;
+  ya.n_out = n;
+  ya.inner = g.H;
+  ya.nlines = (long long)n * g.H;
+  ya.in_fstride = (long long)n * g.Q;
+  ya.out_fstride = (long long)n * n * g.H;
+  const unsigned fm[6] = {0, 1, 2, 3, 3, 4};
+  ya.fmap = 0;
+  for (int i = 0; i < 6; ++i) ya.fmap |= fm[i] << (4 * i);
+  ya.dmask = 1 << 4;
+  ya.scale = 1.0;
+  e = psms::launch_lines<T>(c->E, +1, static_cast<const cpx<T>*>(c->bufb), static_cast<cpx<T>*>(c->bufa), tw, ya, 6,
+                            c->stream);
+  if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], c->stream)) != hipSuccess) return e;
+  // x stage with products: Y -> X [8][n][n][H]
+  const double csig = 3.0 / std::sqrt(8.0) * c->p.ch / c->p.we;
+  e = psms::launch_xstep<T>(c->E, static_cast<const cpx<T>*>(c->bufa), static_cast<cpx<T>*>(c->bufb), tw, c->plan, g,
+                            csig, c->xP, c->stream);
+  if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[2], c->stream)) != hipSuccess) return e;
+  // y-forward with truncation: X -> W [8][n][C][H]
+  psms::LineArgs yf{};
+  yf.pl = c->plan;
+  yf.n_in = n;
+  yf.n_out = g.C;
+  yf.inner = g.H;
+  yf.nlines = (long long)n * g.H;
+  yf.in_fstride = (long long)n * n * g.H;
+  yf.out_fstride = (long long)n * g.Q;
+  yf.fmap = 0;
+  for (unsigned i = 0; i < 8; ++i) yf.fmap |= i << (4 * i);
+  yf.dmask = 0;
+  yf.scale = 1.0;
+  e = psms::launch_lines<T>(c->E, -1, static_cast<const cpx<T>*>(c->bufb), static_cast<cpx<T>*>(c->bufa), tw, yf, 8,
+                            c->stream);
+  if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[3], c->stream)) != hipSuccess) return e;
+  // z-forward + update + z-inverse: W -> state, hist, G
+  psms::StepCoef sc = step_coef(c);
+  e = psms::launch_zstep<T>(c->E, static_cast<const cpx<T>*>(c->bufa), c->state, c->hist,
+                            static_cast<cpx<T>*>(c->bufb), tw, c->plan, g, sc, 1, c->stream);
+  if (e != hipSuccess) return e;
+  if (ev) e = hipEventRecord(ev[4], c->stream);
+  return e;
+}
+
+// Forward transform of nf real FP64 fields into the compact band (state layout).
+hipError_t forward_to_band(psms_ctx* c, const double* d_in, cpx<double>* d_out, int nf) {
+  const BoxGeom& g = c->g;
+  const int n = g.n;
+  hipError_t e;
+  for (int f = 0; f < nf; ++f) {
+    psms::RowArgs ra{};
+    ra.pl = c->plan;
+    ra.nrows = (long long)n * n;
+    ra.n_in = n;
+    ra.n_out = g.H;
+    ra.in_fstride = 0;
+    ra.out_fstride = 0;
+    ra.scale = 1.0;
+    e = psms::launch_rows<double>(c->E, -1, d_in + (size_t)f * n * n * n, c->bufa, c->tw64, ra, 1, c->stream);
+    if (e != hipSuccess) return e;
+    psms::LineArgs ly{};
+    ly.pl = c->plan;
+    ly.n_in = n;
+    ly.n_out = g.C;
+    ly.inner = g.H;
+    ly.nlines = (long long)n * g.H;
+    ly.fmap = 0;
+    ly.scale = 1.0;
+    e = psms::launch_lines<double>(c->E, -1, static_cast<const cpx<double>*>(c->bufa),
+                                   static_cast<cpx<double>*>(c->bufb), c->tw64, ly, 1, c->stream);
+    if (e != hipSuccess) return e;
+    psms::LineArgs lz{};
+    lz.pl = c->plan;
+    lz.n_in = n;
+    lz.n_out = g.C;
+    lz.inner = g.Q;
+    lz.nlines = g.Q;
+    lz.fmap = 0;
+    lz.scale = 1.0 / (double(n) * n * n);
+    e = psms::launch_lines<double>(c->E, -1, static_cast<const cpx<double>*>(c->bufb), d_out + (size_t)f * g.M,
+                                   c->tw64, lz, 1, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t transform_fields(psms_ctx* c, int dir, int nf, const void* d_in, void* d_out, uint32_t flags) {
+  const cpx<T>* tw = std::is_same<T, double>::value ? reinterpret_cast<const cpx<T>*>(c->tw64)
+                                                     : reinterpret_cast<const cpx<T>*>(c->tw32);
+  const BoxGeom& g = c->g;
+  const int n = g.n, nh = n / 2 + 1;
+  const size_t nfull = size_t(n) * n * nh, nphys = size_t(n) * n * n;
+  const int dealias = (flags & PSMS_DEALIAS) ? 1 : 0;
+  const int axis = (flags & PSMS_DERIV_X) ? 0 : (flags & PSMS_DERIV_Y) ? 1 : (flags & PSMS_DERIV_Z) ? 2 : -1;
+  cpx<T>* A = static_cast<cpx<T>*>(c->bufa);
+  cpx<T>* B = static_cast<cpx<T>*>(c->bufb);
+  psms::LineArgs ly{};
+  ly.pl = c->plan;
+  ly.n_in = n;
+  ly.n_out = n;
+  ly.inner = nh;
+  ly.nlines = (long long)n * nh;
+  ly.scale = 1.0;
+  psms::LineArgs lz = ly;
+  lz.inner = (long long)n * nh;
+  lz.nlines = (long long)n * nh;
+  psms::RowArgs ra{};
+  ra.pl = c->plan;
+  ra.nrows = (long long)n * n;
+  ra.n_in = nh;
+  ra.n_out = nh;
+  ra.scale = 1.0;
+  hipError_t e;
+  for (int f = 0; f < nf; ++f) {
+    if (dir > 0) {
+      const T* src = static_cast<const T*>(d_in) + f * nphys;
+      cpx<T>* dst = static_cast<cpx<T>*>(d_out) + f * nfull;
+      ra.n_in = n;
+      if ((e = psms::launch_rows<T>(c->E, -1, src, A, tw, ra, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_lines<T>(c->E, -1, A, B, tw, ly, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_lines<T>(c->E, -1, B, A, tw, lz, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_spec_finish<T>(A, dst, g, 1, dealias, axis, 1.0 / (double(n) * n * n), c->stream)) !=
+          hipSuccess)
+        return e;
+    } else {
+      const cpx<T>* src = static_cast<const cpx<T>*>(d_in) + f * nfull;
+      T* dst = static_cast<T*>(d_out) + f * nphys;
+      if ((e = psms::launch_spec_finish<T>(src, A, g, 1, dealias, axis, 1.0, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_lines<T>(c->E, +1, A, B, tw, lz, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_lines<T>(c->E, +1, B, A, tw, ly, 1, c->stream)) != hipSuccess) return e;
+      ra.n_in = nh;
+      ra.n_out = n;
+      if ((e = psms::launch_rows<T>(c->E, +1, A, dst, tw, ra, 1, c->stream)) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* psms_last_error(void) { return g_err.c_str(); }
+const char* psms_version(void) { return "psms 0.1 (gfx950)"; }
+
+int psms_workspace_bytes(const psms_params* p, size_t* bytes) {
+  int r = validate(p);
+  if (r) return r;
+  if (!bytes) return fail(PSMS_E_INVAL, "bytes is NULL");
+  *bytes = make_layout(*p).total;
+  return PSMS_OK;
+}
+
+int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t bytes, void* stream) {
+  if (!out) return fail(PSMS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int r = validate(p);
+  if (r) return r;
+  const Layout lay = make_layout(*p);
+  if (!d_workspace) return fail(PSMS_E_WORKSPACE, "workspace is NULL");
+  if (!aligned(d_workspace)) return fail(PSMS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < lay.total)
+    return fail(PSMS_E_WORKSPACE, "workspace too small: need " + std::to_string(lay.total) + " bytes, got " +
+                                      std::to_string(bytes));
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PSMS_E_DEVICE, "no HIP device available");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(PSMS_E_DEVICE, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(PSMS_E_DEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(PSMS_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+
+  psms_ctx* c = new psms_ctx();
+  c->p = *p;
+  c->g = make_geom(p->n);
+  make_plan(p->n, &c->plan, &c->E);
+  c->xP = xstep_pairs(p->n, c->plan.tpl);
+  c->s = (p->s > 0.0) ? p->s : std::sqrt(4.0 * p->pe / (p->ch * p->ch * p->dt));
+  c->stream = static_cast<hipStream_t>(stream);
+  c->lay = lay;
+  c->ws = static_cast<char*>(d_workspace);
+  c->state = reinterpret_cast<cpx<double>*>(c->ws + lay.state);
+  c->hist = reinterpret_cast<cpx<double>*>(c->ws + lay.hist);
+  c->bufa = c->ws + lay.bufa;
+  c->bufb = c->ws + lay.bufb;
+  c->tw64 = reinterpret_cast<cpx<double>*>(c->ws + lay.tw64);
+  c->tw32 = reinterpret_cast<cpx<float>*>(c->ws + lay.tw32);
+  c->diag = reinterpret_cast<double*>(c->ws + lay.diag);
+  c->diag_out = reinterpret_cast<double*>(c->ws + lay.diag_out);
+
+  // Twiddles exp(-2 pi i m / n) in FP64, rounded once to FP32 for MIXED.
+  const int n = p->n;
+  std::vector<cpx<double>> t64(n);
+  std::vector<cpx<float>> t32(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * double(m) / double(n);
+    t64[m] = cpx<double>{std::cos(a), std::sin(a)};
+    t32[m] = cpx<float>{float(t64[m].re), float(t64[m].im)};
+  }
+  hipError_t e = hipMemcpyAsync(c->tw64, t64.data(), n * sizeof(cpx<double>), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->tw32, t32.data(), n * sizeof(cpx<float>), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "twiddle upload");
+  }
+  *out = c;
+  return PSMS_OK;
+}
+
+int psms_destroy(psms_ctx* c) {
+  delete c;
+  return PSMS_OK;
+}
+
+int64_t psms_band_modes(const psms_ctx* c) { return c ? int64_t(c->g.M) : 0; }
+
+int psms_init_state(psms_ctx* c, const double* d_u, const double* d_phi) {
+  if (!c || !d_u || !d_phi) return fail(PSMS_E_INVAL, "NULL argument");
+  hipError_t e = forward_to_band(c, d_u, c->state, 3);
+  if (e == hipSuccess) e = forward_to_band(c, d_phi, c->state + 3 * c->g.M, 1);
+  if (e == hipSuccess) e = psms::launch_project(c->state, c->g, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->hist, 0, 4 * size_t(c->g.M) * sizeof(cpx<double>), c->stream);
+  if (e != hipSuccess) return hip_fail(e, "init_state");
+  c->nstep = 0;
+  c->have_state = 1;
+  c->g_valid = 0;
+  psms_diag d;
+  int r = psms_diagnostics(c, &d);
+  if (r) return r;
+  if (d.nonfinite) {
+    c->have_state = 0;
+    return fail(PSMS_E_NONFINITE, "non-finite value in the initial fields");
+  }
+  return PSMS_OK;
+}
+
+int psms_set_state(psms_ctx* c, const double* d_uhat, const double* d_phihat, const double* d_hist, int32_t nstep) {
+  if (!c || !d_uhat || !d_phihat) return fail(PSMS_E_INVAL, "NULL argument");
+  if (nstep < 0) return fail(PSMS_E_INVAL, "nstep must be >= 0");
+  if (nstep > 0 && !d_hist) return fail(PSMS_E_INVAL, "nstep > 0 needs the history");
+  const BoxGeom& g = c->g;
+  hipError_t e = psms::launch_compact<double>(reinterpret_cast<const cpx<double>*>(d_uhat), c->state, g, 3, c->stream);
+  if (e == hipSuccess)
+    e = psms::launch_compact<double>(reinterpret_cast<const cpx<double>*>(d_phihat), c->state + 3 * g.M, g, 1,
+                                     c->stream);
+  if (e == hipSuccess) {
+    if (d_hist) e = psms::launch_compact<double>(reinterpret_cast<const cpx<double>*>(d_hist), c->hist, g, 4, c->stream);
+    else e = hipMemsetAsync(c->hist, 0, 4 * size_t(g.M) * sizeof(cpx<double>), c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "set_state");
+  c->nstep = nstep;
+  c->have_state = 1;
+  c->g_valid = 0;
+  return PSMS_OK;
+}
+
+int psms_get_state(psms_ctx* c, double* d_uhat, double* d_phihat, double* d_hist) {
+  if (!c || !d_uhat || !d_phihat) return fail(PSMS_E_INVAL, "NULL argument");
+  if (!c->have_state) return fail(PSMS_E_STATE, "no state: call psms_init_state or psms_set_state first");
+  const BoxGeom& g = c->g;
+  hipError_t e = psms::launch_expand<double>(c->state, reinterpret_cast<cpx<double>*>(d_uhat), g, 3, c->stream);
+  if (e == hipSuccess)
+    e = psms::launch_expand<double>(c->state + 3 * g.M, reinterpret_cast<cpx<double>*>(d_phihat), g, 1, c->stream);
+  if (e == hipSuccess && d_hist)
+    e = psms::launch_expand<double>(c->hist, reinterpret_cast<cpx<double>*>(d_hist), g, 4, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "get_state");
+  return PSMS_OK;
+}
+
+int psms_step(psms_ctx* c, int32_t nsteps) {
+  if (!c) return fail(PSMS_E_INVAL, "NULL context");
+  if (nsteps < 0) return fail(PSMS_E_INVAL, "nsteps must be >= 0");
+  if (!c->have_state) return fail(PSMS_E_STATE, "step before init_state / set_state");
+  const bool mixed = c->p.precision == PSMS_MIXED;
+  hipError_t e = hipSuccess;
+  if (!c->g_valid && nsteps > 0) {
+    e = mixed ? prologue<float>(c) : prologue<double>(c);
+    if (e != hipSuccess) return hip_fail(e, "step prologue");
+    c->g_valid = 1;
+  }
+  for (int i = 0; i < nsteps; ++i) {
+    e = mixed ? one_step<float>(c) : one_step<double>(c);
+    if (e != hipSuccess) {
+      c->g_valid = 0;
+      return hip_fail(e, "step");
+    }
+    c->nstep += 1;
+  }
+  return PSMS_OK;
+}
+
+int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms) {
+  if (!c || !h_ms) return fail(PSMS_E_INVAL, "NULL argument");
+  if (nsteps < 1) return fail(PSMS_E_INVAL, "nsteps must be >= 1");
+  if (!c->have_state) return fail(PSMS_E_STATE, "step before init_state / set_state");
+  const bool mixed = c->p.precision == PSMS_MIXED;
+  hipError_t e = hipSuccess;
+  if (!c->g_valid) {
+    e = mixed ? prologue<float>(c) : prologue<double>(c);
+    if (e != hipSuccess) return hip_fail(e, "step prologue");
+    c->g_valid = 1;
+  }
+  std::vector<hipEvent_t> ev(5 * size_t(nsteps));
+  size_t made = 0;
+  for (; made < ev.size(); ++made)
+    if ((e = hipEventCreate(&ev[made])) != hipSuccess) break;
+  double acc[4] = {0, 0, 0, 0};
+  for (int i = 0; e == hipSuccess && i < nsteps; ++i) {
+    e = mixed ? one_step<float>(c, &ev[5 * i]) : one_step<double>(c, &ev[5 * i]);
+    if (e == hipSuccess) c->nstep += 1;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  for (int i = 0; e == hipSuccess && i < nsteps; ++i) {
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[5 * i + k], ev[5 * i + k + 1]);
+      acc[k] += ms;
+    }
+  }
+  for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+  if (e != hipSuccess) {
+    c->g_valid = 0;
+    return hip_fail(e, "stage_times");
+  }
+  for (int k = 0; k < 4; ++k) h_ms[k] = acc[k] / nsteps;
+  return PSMS_OK;
+}
+
+int psms_transform(psms_ctx* c, int32_t dir, int32_t nfield, const void* d_in, void* d_out, uint32_t flags) {
+  if (!c) return fail(PSMS_E_INVAL, "NULL context");
+  if (nfield == 0) return PSMS_OK;
+  if (!d_in || !d_out) return fail(PSMS_E_INVAL, "NULL argument");
+  if (dir != 1 && dir != -1) return fail(PSMS_E_INVAL, "dir must be +1 or -1");
+  if (nfield < 0) return fail(PSMS_E_INVAL, "nfield must be >= 0");
+  if (flags & ~uint32_t(15)) return fail(PSMS_E_INVAL, "unknown flag");
+  const uint32_t d = flags & 14u;
+  if (d && (d & (d - 1))) return fail(PSMS_E_INVAL, "at most one derivative flag");
+  c->g_valid = 0;  // the scratch holding the next step's input is reused
+  hipError_t e = (c->p.precision == PSMS_MIXED) ? transform_fields<float>(c, dir, nfield, d_in, d_out, flags)
+                                                : transform_fields<double>(c, dir, nfield, d_in, d_out, flags);
+  if (e != hipSuccess) return hip_fail(e, "transform");
+  return PSMS_OK;
+}
+
+int psms_solve_helmholtz(psms_ctx* c, int32_t nfield, const double* h_lambda, const double* d_rhs, double* d_out) {
+  if (!c || !h_lambda || !d_rhs || !d_out) return fail(PSMS_E_INVAL, "NULL argument");
+  if (nfield < 0) return fail(PSMS_E_INVAL, "nfield must be >= 0");
+  const BoxGeom& g = c->g;
+  const size_t per = size_t(g.n) * g.n * (g.n / 2 + 1);
+  for (int f = 0; f < nfield; ++f) {
+    if (!(h_lambda[f] >= 0.0) || !std::isfinite(h_lambda[f])) return fail(PSMS_E_INVAL, "lambda must be finite and >= 0");
+  }
+  for (int f = 0; f < nfield; ++f) {
+    hipError_t e = psms::launch_helmholtz_box(reinterpret_cast<const cpx<double>*>(d_rhs) + f * per,
+                                              reinterpret_cast<cpx<double>*>(d_out) + f * per, g, h_lambda[f],
+                                              c->stream);
+    if (e != hipSuccess) return hip_fail(e, "solve_helmholtz");
+  }
+  return PSMS_OK;
+}
+
+int psms_diagnostics(psms_ctx* c, psms_diag* h_out) {
+  if (!c || !h_out) return fail(PSMS_E_INVAL, "NULL argument");
+  if (!c->have_state) return fail(PSMS_E_STATE, "no state");
+  hipError_t e = psms::launch_diag(c->state, c->g, c->diag, kDiagBlocks, c->diag_out, c->stream);
+  double h[5];
+  if (e == hipSuccess) e = hipMemcpyAsync(h, c->diag_out, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics");
+  h_out->mean_phi = h[0];
+  h_out->ke = h[1];
+  h_out->grad2 = h[2];
+  h_out->max_div = h[3];
+  h_out->nonfinite = int32_t(h[4]);
+  h_out->nstep = c->nstep;
+  return PSMS_OK;
+}
+
+int psms_index_maps(psms_ctx* c, int32_t* d_out) {
+  if (!c || !d_out) return fail(PSMS_E_INVAL, "NULL argument");
+  hipError_t e = psms::launch_index_maps(d_out, c->g, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "index_maps");
+  return PSMS_OK;
+}
+
+}  // extern "C"

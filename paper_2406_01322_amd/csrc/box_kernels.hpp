@@ -1,0 +1,80 @@
+// Kernel argument blocks and host launchers for the periodic-box step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_core.hpp"
+
+namespace psms {
+
+// Geometry of the retained band on an n^3 box: K = floor((n-1)/3),
+// C = 2K+1 slots along y and z, H = K+1 along x, Q = C*H lines along z,
+// M = C*Q modes per field.
+struct BoxGeom {
+  int n, K, C, H;
+  long long Q, M;
+};
+
+// Coefficients of the IMEX update (Sec. 2.2).
+struct StepCoef {
+  double dt;       // time step
+  double nu;       // 1 / Re
+  double ch2_pe;   // Ch^2 / Pe
+  double s;        // CH splitting coefficient
+  double inv_pe;   // 1 / Pe
+  double e_coef;   // (1 + s Ch^2) / Pe
+  double inv_n3;   // forward normalisation 1 / n^3
+  int ab1;         // 1: Adams-Bashforth order 1 (first step)
+};
+
+struct LineArgs {
+  FftPlan pl;
+  int n_in, n_out;
+  long long inner, nlines;
+  long long in_fstride, out_fstride;
+  unsigned fmap;   // input field of output field f in bits 4f..4f+3
+  int dmask;
+  double scale;
+};
+
+struct RowArgs {
+  FftPlan pl;
+  long long nrows;
+  int n_in, n_out;
+  long long in_fstride, out_fstride;
+  double scale;
+};
+
+// Lines per workgroup for the strided-axis kernels (about 256 threads).
+inline int line_tile(int tpl) { return tpl >= 256 ? 1 : 256 / tpl; }
+// Row pairs per workgroup for the generic real-row kernels.
+inline int row_pairs(int tpl) { return tpl >= 256 ? 1 : 256 / tpl; }
+
+template <typename T>
+hipError_t launch_lines(int E, int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, const LineArgs& a,
+                        int nfield, hipStream_t st);
+template <typename T>
+hipError_t launch_rows(int E, int dir, const void* in, void* out, const cpx<T>* tw, const RowArgs& a, int nfield,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_xstep(int E, const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, const FftPlan& pl,
+                        const BoxGeom& g, double csig, int P, hipStream_t st);
+template <typename T>
+hipError_t launch_zstep(int E, const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout,
+                        const cpx<T>* tw, const FftPlan& pl, const BoxGeom& g, const StepCoef& sc, int do_update,
+                        hipStream_t st);
+template <typename T>
+hipError_t launch_expand(const cpx<T>* cmp, cpx<T>* full, const BoxGeom& g, int nf, hipStream_t st);
+template <typename T>
+hipError_t launch_compact(const cpx<T>* full, cpx<T>* cmp, const BoxGeom& g, int nf, hipStream_t st);
+hipError_t launch_project(cpx<double>* u, const BoxGeom& g, hipStream_t st);
+template <typename T>
+hipError_t launch_spec_finish(const cpx<T>* in, cpx<T>* out, const BoxGeom& g, int nf, int dealias, int axis,
+                              double scale, hipStream_t st);
+hipError_t launch_helmholtz_box(const cpx<double>* rhs, cpx<double>* out, const BoxGeom& g, double lam,
+                                hipStream_t st);
+hipError_t launch_index_maps(int* out, const BoxGeom& g, hipStream_t st);
+hipError_t launch_diag(const cpx<double>* state, const BoxGeom& g, double* part, int max_blocks, double* out,
+                       hipStream_t st);
+
+}  // namespace psms
