@@ -85,6 +85,33 @@ def run_gpu(precision, n, p, u, phi, steps, warmup):
                 stage_ms=dict(zip(STAGES, ms)), diag=d)
 
 
+def mixed_error(n, p, u, phi, nsteps=(1, 20)):
+    """Per-field rel-L2 of the MIXED state against the FP64 GPU state (the FP64 path is
+    held to 1e-12 of the FP64 oracle by the parity tests), after each count in nsteps."""
+    import torch
+    from paper_2406_01322_amd.psms import Solver
+    out = {}
+    ss = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver(n, p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=prec)
+        s.init_state(torch.from_numpy(u).cuda(), torch.from_numpy(phi).cuda())
+        ss[prec] = s
+    done = 0
+    for k in nsteps:
+        for s in ss.values():
+            s.step(k - done)
+        done = k
+        a = ss["fp64"].get_state()
+        b = ss["mixed"].get_state()
+        torch.cuda.synchronize()
+        rel = {}
+        for name, x, y in (("u", a[0][0], b[0][0]), ("v", a[0][1], b[0][1]), ("w", a[0][2], b[0][2]),
+                           ("phi", a[1], b[1])):
+            rel[name] = float(torch.linalg.norm(y - x) / torch.linalg.norm(x))
+        out["after_%d_steps" % k] = rel
+    return out
+
+
 def cpu_baseline(n, p, u, phi, budget_s=20.0):
     """The FP64 oracle on the host: init, then as many steps as fit in ~budget_s."""
     import numpy as np  # noqa: F401
@@ -163,6 +190,8 @@ def main():
         out["fp64"] = {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
                        "stage_ms": res["fp64"]["stage_ms"]}
         out["speedup_mixed_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    if "fp64" in res and "mixed" in res:
+        out["mixed_vs_fp64_rel_l2"] = mixed_error(n, p, u, phi)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, p, u, phi)
     print(json.dumps(out), flush=True)

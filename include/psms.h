@@ -157,6 +157,79 @@ int psms_index_maps(psms_ctx* c, int32_t* d_out);
  * y-inverse, x stage with products, y-forward, z stage with the update. */
 int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms);
 
+/* ---------------------------------------------------------------------------
+ * Wall-normal (Chebyshev) operations of the channel, Sec. 2.2 and Sec. 3.2.
+ * z in [-1, 1] is sampled at the Chebyshev-Gauss-Lobatto points
+ * z_j = cos(pi j / nc), j = 0..nc (z_0 = +1), and f(z) = sum_n a_n T_n(z).
+ * Data are nlines complex lines (one per Fourier pair (kx, ky)), stored
+ * position-major: entry n of line l at [n][l] (nc+1 entries per line),
+ * complex interleaved.  nc must make 2 nc a supported FFT length
+ * (nc in {4,6,8,12,16,24,32,48,64,96,128}).  These calls are stateless:
+ * they run on `stream` (a hipStream_t, NULL for the default stream) and
+ * allocate nothing.
+ * ------------------------------------------------------------------------- */
+enum { PSMS_DIRICHLET = 1, PSMS_NEUMANN = 2 };
+
+/* Chebyshev transform as a DCT-I through the FFT of the 2 nc-point even
+ * extension (Sec. 3.2.1), applied to real and imaginary parts together.
+ * dir = +1: values f_j -> coefficients a_n = 2/(nc cbar_n) sum_j f_j
+ * cos(pi n j / nc) / cbar_j (cbar_0 = cbar_nc = 2, else 1); dir = -1:
+ * coefficients -> values f_j = sum_n a_n cos(pi n j / nc).
+ * precision PSMS_FP64: complex double data; PSMS_MIXED: complex float. */
+int psms_cheb_transform(int32_t nc, int64_t nlines, int32_t dir, int32_t precision, const void* d_in, void* d_out,
+                        void* stream);
+
+/* Coefficients of df/dz (FP64), by c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n,
+ * b_nc = 0 (c_0 = 2).  d_in and d_out must not overlap. */
+int psms_cheb_deriv(int32_t nc, int64_t nlines, const double* d_in, double* d_out, void* stream);
+
+/* The wall-normal Helmholtz problems of Sec. 2.2 ("a system of Helmholtz
+ * problems along the wall-normal direction for each (x, y) location"):
+ * (D^2 - beta_l) f = g on each line by the Chebyshev-tau method in FP64,
+ * rows n = 0..nc-2 of the equation (g entries n > nc-2 are ignored) and two
+ * boundary rows: bc = PSMS_DIRICHLET: f(+1), f(-1); PSMS_NEUMANN: f'(+1),
+ * f'(-1), given by d_bcval [nlines][2] complex (top, bottom), or zero if
+ * NULL.  d_beta [nlines] >= 0 (a Neumann problem needs beta > 0).  d_work:
+ * (nc+1) * nlines doubles of scratch.  d_rhs and d_out must not overlap. */
+int psms_cheb_helmholtz(int32_t nc, int64_t nlines, const double* d_beta, int32_t bc, const double* d_bcval,
+                        const double* d_rhs, double* d_out, double* d_work, void* stream);
+
+/* The implicit wall-normal solves of one channel time step for every
+ * (kx, ky) line (Sec. 2.2, items iv and v; eqs. omegaz, ww, omegadef,
+ * phisplit), k^2 = kx^2 + ky^2:
+ *   omega_z: (D^2 - (k^2 + beta_ns)) omega = g_om, omega(+-1) = 0;
+ *   w:       (D^2 - (k^2 + beta_ns)) psi = g_w, (D^2 - k^2) w = psi with
+ *            w(+-1) = w'(+-1) = 0, by the influence-matrix method (psi takes
+ *            the two homogeneous solutions with unit value at one wall);
+ *            w = 0 for k = 0;
+ *   phi:     (D^2 - (k^2 + beta_a)) xi = g_phi, (D^2 - (k^2 + beta_b)) phi = xi,
+ *            both with zero normal derivative at the walls (no-flux);
+ *   u, v:    u = i (kx w' + ky omega)/k^2, v = i (ky w' - kx omega)/k^2
+ *            (zero for k = 0: the mean flow is a separate Dirichlet problem).
+ * All arrays [nc+1][nlines] complex double except d_kx, d_ky [nlines].
+ * d_work: psms_wall_workspace_bytes bytes, 256-byte aligned. */
+typedef struct psms_wall_args {
+  int32_t nc;
+  int32_t reserved;
+  int64_t nlines;
+  const double* d_kx;
+  const double* d_ky;
+  double beta_ns; /* 2 Re / dt for Crank-Nicolson */
+  double beta_a;  /* the two factors of the implicit CH operator */
+  double beta_b;
+  const double* d_g_om;
+  const double* d_g_w;
+  const double* d_g_phi;
+  double* d_om;
+  double* d_w;
+  double* d_phi;
+  double* d_u;
+  double* d_v;
+} psms_wall_args;
+
+int psms_wall_workspace_bytes(int32_t nc, int64_t nlines, size_t* bytes);
+int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* stream);
+
 /* Number of retained modes per field, (2K+1)^2 (K+1). */
 int64_t psms_band_modes(const psms_ctx* c);
 

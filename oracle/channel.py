@@ -1,0 +1,160 @@
+"""Plain FP64 CPU oracle for the wall-normal (Chebyshev) operations of the channel.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module; only the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use it.  It shares no code with the HIP implementation.
+
+The paper represents every quantity along the wall-normal direction z in [-1, 1]
+by Chebyshev polynomials on a grid refined near the walls (Sec. 2.2), obtains
+the Chebyshev transform as a DCT-I (Sec. 3.2.1), and reduces the implicit
+parts of the velocity-vorticity and Cahn-Hilliard equations to independent 1-D
+Helmholtz problems per Fourier pair (kx, ky) (Sec. 2.2, eqs. omegaz, ww,
+phisplit; Sec. 3.2.2).  This module writes those operations out densely:
+
+* collocation at the Chebyshev-Gauss-Lobatto points z_j = cos(pi j / nc),
+  j = 0..nc (the paper's stretched grid, read as CGL);
+* f(z) = sum_n a_n T_n(z); transforms by explicit cosine sums;
+* derivative of a coefficient vector by numpy's Chebyshev derivative;
+* Helmholtz problems (D^2 - beta) f = g by the Chebyshev-tau method: the
+  equations for n = 0..nc-2 plus two boundary rows, assembled from the
+  explicit second-derivative formula and solved by a dense LU (numpy);
+* the fourth-order wall-normal velocity problem by the influence-matrix
+  method; u and v from continuity and the definition of omega_z (eq. omegadef).
+"""
+from __future__ import annotations
+
+import numpy as np
+from numpy.polynomial import chebyshev as npcheb
+
+
+def cgl(nc: int) -> np.ndarray:
+    """Chebyshev-Gauss-Lobatto points z_j = cos(pi j / nc), j = 0..nc (z_0 = +1)."""
+    return np.cos(np.pi * np.arange(nc + 1) / nc)
+
+
+def _cbar(nc: int) -> np.ndarray:
+    c = np.ones(nc + 1)
+    c[0] = 2.0
+    c[-1] = 2.0
+    return c
+
+
+def values_to_coeffs(f: np.ndarray, axis: int = 0) -> np.ndarray:
+    """a_n = 2/(nc cbar_n) sum_j f_j cos(pi n j / nc) / cbar_j (cbar_0 = cbar_nc = 2)."""
+    f = np.moveaxis(np.asarray(f), axis, 0)
+    nc = f.shape[0] - 1
+    n = np.arange(nc + 1)
+    cb = _cbar(nc)
+    Cm = np.cos(np.pi * np.outer(n, n) / nc) / cb[None, :]
+    a = (2.0 / (nc * cb))[:, None] * (Cm @ f.reshape(nc + 1, -1))
+    return np.moveaxis(a.reshape(f.shape), 0, axis)
+
+
+def coeffs_to_values(a: np.ndarray, axis: int = 0) -> np.ndarray:
+    """f_j = sum_n a_n T_n(z_j) = sum_n a_n cos(pi n j / nc)."""
+    a = np.moveaxis(np.asarray(a), axis, 0)
+    nc = a.shape[0] - 1
+    n = np.arange(nc + 1)
+    Cm = np.cos(np.pi * np.outer(n, n) / nc)
+    f = Cm @ a.reshape(nc + 1, -1)
+    return np.moveaxis(f.reshape(a.shape), 0, axis)
+
+
+def deriv(a: np.ndarray, axis: int = 0) -> np.ndarray:
+    """Coefficients of df/dz (same length, last entry zero)."""
+    a = np.moveaxis(np.asarray(a), axis, 0)
+    d = npcheb.chebder(a, axis=0)
+    out = np.zeros_like(a)
+    out[: d.shape[0]] = d
+    return np.moveaxis(out, 0, axis)
+
+
+def d2_matrix(nc: int) -> np.ndarray:
+    """(D^2 a)_n = (1/c_n) sum_{p >= n+2, p+n even} p (p^2 - n^2) a_p, c_0 = 2, c_n = 1."""
+    D2 = np.zeros((nc + 1, nc + 1))
+    for n in range(nc + 1):
+        cn = 2.0 if n == 0 else 1.0
+        for p in range(n + 2, nc + 1, 2):
+            D2[n, p] = p * (p * p - n * n) / cn
+    return D2
+
+
+def bc_rows(nc: int, kind: str):
+    """Rows evaluating f(+1), f(-1) (Dirichlet) or f'(+1), f'(-1) (Neumann)."""
+    n = np.arange(nc + 1, dtype=float)
+    if kind == "dirichlet":
+        return np.ones(nc + 1), (-1.0) ** n
+    if kind == "neumann":
+        return n * n, (-1.0) ** (n + 1) * n * n
+    raise ValueError(kind)
+
+
+def helmholtz(g: np.ndarray, beta: float, kind: str = "dirichlet", top=0.0, bottom=0.0) -> np.ndarray:
+    """Chebyshev-tau solution of (D^2 - beta) f = g on [-1, 1] with
+    f(+1) = top, f(-1) = bottom (Dirichlet) or f'(+1) = top, f'(-1) = bottom
+    (Neumann).  g holds nc+1 Chebyshev coefficients (entries n > nc-2 are
+    dropped, as the tau method does).  Dense LU."""
+    g = np.asarray(g)
+    nc = g.shape[0] - 1
+    A = d2_matrix(nc) - beta * np.eye(nc + 1)
+    rt, rb = bc_rows(nc, kind)
+    A[nc - 1] = rt
+    A[nc] = rb
+    rhs = np.array(g, dtype=complex)
+    rhs[nc - 1] = top
+    rhs[nc] = bottom
+    return np.linalg.solve(A, rhs)
+
+
+def wall_values(a: np.ndarray):
+    """(f(+1), f(-1), f'(+1), f'(-1)) of a coefficient vector."""
+    nc = a.shape[0] - 1
+    n = np.arange(nc + 1, dtype=float)
+    return (np.sum(a), np.sum((-1.0) ** n * a), np.sum(n * n * a), np.sum((-1.0) ** (n + 1) * n * n * a))
+
+
+def wall_normal_solve(g_om, g_w, g_phi, kx, ky, beta_ns, beta_a, beta_b):
+    """The implicit wall-normal solves of one (kx, ky) pair (Sec. 2.2, items iv and v).
+
+    omega_z: (D^2 - beta_ns) omega = g_om,  omega(+-1) = 0.
+    w:       (D^2 - beta_ns) psi = g_w, (D^2 - k^2) w = psi, w(+-1) = w'(+-1) = 0
+             (k^2 = kx^2 + ky^2); psi has no boundary values of its own, so
+             psi = psi_p + c+ psi_+ + c- psi_- with homogeneous solutions taking
+             unit values at one wall, and c+- chosen so that w'(+-1) = 0
+             (influence matrix).  For k = 0, w = 0 (continuity).
+    phi:     (D^2 - beta_a) xi = g_phi, (D^2 - beta_b) phi = xi, both with zero
+             normal derivative at the walls (no-flux: phi' = phi''' = 0).
+    u, v:    from continuity and eq. omegadef:
+             u = i (kx w' + ky omega) / k^2,  v = i (ky w' - kx omega) / k^2
+             (for k = 0 they are left to the mean-flow solve and returned as 0).
+    Returns dict(omega, w, phi, u, v) of coefficient vectors.
+    """
+    nc = len(g_om) - 1
+    k2 = float(kx * kx + ky * ky)
+    om = helmholtz(g_om, beta_ns, "dirichlet")
+    if k2 == 0.0:
+        w = np.zeros(nc + 1, complex)
+    else:
+        zero = np.zeros(nc + 1)
+        psi_p = helmholtz(g_w, beta_ns, "dirichlet")
+        w_p = helmholtz(psi_p, k2, "dirichlet")
+        psi_t = helmholtz(zero, beta_ns, "dirichlet", 1.0, 0.0)
+        w_t = helmholtz(psi_t, k2, "dirichlet")
+        psi_b = helmholtz(zero, beta_ns, "dirichlet", 0.0, 1.0)
+        w_b = helmholtz(psi_b, k2, "dirichlet")
+        _, _, dpt, dpb = wall_values(w_p)
+        _, _, dtt, dtb = wall_values(w_t)
+        _, _, dbt, dbb = wall_values(w_b)
+        M = np.array([[dtt, dbt], [dtb, dbb]])
+        c = np.linalg.solve(M, -np.array([dpt, dpb]))
+        w = w_p + c[0] * w_t + c[1] * w_b
+    xi = helmholtz(g_phi, beta_a, "neumann")
+    phi = helmholtz(xi, beta_b, "neumann")
+    if k2 == 0.0:
+        u = np.zeros(nc + 1, complex)
+        v = np.zeros(nc + 1, complex)
+    else:
+        dw = deriv(w)
+        u = 1j * (kx * dw + ky * om) / k2
+        v = 1j * (ky * dw - kx * om) / k2
+    return dict(omega=om, w=w, phi=phi, u=u, v=v)

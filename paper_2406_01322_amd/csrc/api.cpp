@@ -10,10 +10,10 @@
 
 #include "../../include/psms.h"
 #include "box_kernels.hpp"
+#include "channel_kernels.hpp"
 
 using psms::BoxGeom;
 using psms::cpx;
-using psms::FftPlan;
 
 namespace {
 
@@ -29,42 +29,6 @@ int hip_fail(hipError_t e, const char* where) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// Radix plans: E = 8 for 2^m, E = 12 for 3 * 2^m.
-bool make_plan(int n, FftPlan* pl, int* E) {
-  std::vector<int> r;
-  switch (n) {
-    case 8: r = {8}; *E = 8; break;
-    case 16: r = {4, 4}; *E = 8; break;
-    case 32: r = {8, 4}; *E = 8; break;
-    case 64: r = {8, 8}; *E = 8; break;
-    case 128: r = {8, 4, 4}; *E = 8; break;
-    case 256: r = {8, 8, 4}; *E = 8; break;
-    case 512: r = {8, 8, 8}; *E = 8; break;
-    case 12: r = {3, 4}; *E = 12; break;
-    case 24: r = {3, 4, 2}; *E = 12; break;
-    case 48: r = {3, 4, 4}; *E = 12; break;
-    case 96: r = {3, 4, 4, 2}; *E = 12; break;
-    case 192: r = {3, 4, 4, 4}; *E = 12; break;
-    case 384: r = {3, 4, 4, 4, 2}; *E = 12; break;
-    default: return false;
-  }
-  std::memset(pl, 0, sizeof(*pl));
-  pl->n = n;
-  pl->nstage = int(r.size());
-  for (size_t i = 0; i < r.size(); ++i) pl->radix[i] = r[i];
-  pl->tpl = n / *E;
-  return true;
-}
-
-// Row pairs per workgroup of the fused x stage: 8 fields x P pairs x tpl
-// threads <= 256, P | n/2.
-int xstep_pairs(int n, int tpl) {
-  int P = 256 / (8 * tpl);
-  if (P < 1) P = 1;
-  while ((n / 2) % P) --P;
-  return P;
-}
 
 struct Layout {
   size_t state, hist, bufa, bufb, tw64, tw32, diag, diag_out, total;
@@ -111,10 +75,8 @@ int validate(const psms_params* p) {
   if (!p) return fail(PSMS_E_INVAL, "params is NULL");
   if (p->geometry == PSMS_CHANNEL) return fail(PSMS_E_NOTSUP, "channel geometry is not implemented by this library");
   if (p->geometry != PSMS_BOX) return fail(PSMS_E_INVAL, "geometry must be PSMS_BOX");
-  FftPlan pl;
-  int E;
-  if (!make_plan(p->n, &pl, &E))
-    return fail(PSMS_E_INVAL, "n must be one of 8,12,16,24,32,48,64,96,128,192,256,384,512");
+  if (!psms::supported_n(p->n))
+    return fail(PSMS_E_INVAL, "n must be one of 8,12,16,24,32,48,64,96,128,192,256");
   if (p->precision != PSMS_FP64 && p->precision != PSMS_MIXED) return fail(PSMS_E_INVAL, "precision must be FP64 or MIXED");
   if (p->reserved != 0) return fail(PSMS_E_INVAL, "reserved must be 0");
   const double v[5] = {p->re, p->we, p->ch, p->pe, p->dt};
@@ -130,9 +92,6 @@ int validate(const psms_params* p) {
 struct psms_ctx {
   psms_params p;
   BoxGeom g;
-  FftPlan plan;
-  int E;
-  int xP;
   double s;
   hipStream_t stream;
   Layout lay;
@@ -173,8 +132,8 @@ hipError_t prologue(psms_ctx* c) {
   const cpx<T>* tw = std::is_same<T, double>::value ? reinterpret_cast<const cpx<T>*>(c->tw64)
                                                      : reinterpret_cast<const cpx<T>*>(c->tw32);
   psms::StepCoef sc = step_coef(c);
-  return psms::launch_zstep<T>(c->E, nullptr, c->state, c->hist, static_cast<cpx<T>*>(c->bufb), tw, c->plan, c->g, sc,
-                               0, c->stream);
+  return psms::launch_zstep<T>(c->g.n, nullptr, c->state, c->hist, static_cast<cpx<T>*>(c->bufb), tw, sc, 0,
+                               c->stream);
 }
 
 template <typename T>
@@ -187,7 +146,6 @@ hipError_t one_step(psms_ctx* c, hipEvent_t* ev = nullptr) {
   if (ev && (e = hipEventRecord(ev[0], c->stream)) != hipSuccess) return e;
   // y-inverse: G [5][n][C][H] -> Y [6][n][n][H]; output 4 is i ky phi
   psms::LineArgs ya{};
-  ya.pl = c->plan;
   ya.n_in = g.C;
   ya.n_out = n;
   ya.inner = g.H;
@@ -199,19 +157,18 @@ hipError_t one_step(psms_ctx* c, hipEvent_t* ev = nullptr) {
   for (int i = 0; i < 6; ++i) ya.fmap |= fm[i] << (4 * i);
   ya.dmask = 1 << 4;
   ya.scale = 1.0;
-  e = psms::launch_lines<T>(c->E, +1, static_cast<const cpx<T>*>(c->bufb), static_cast<cpx<T>*>(c->bufa), tw, ya, 6,
+  e = psms::launch_lines<T>(n, +1, static_cast<const cpx<T>*>(c->bufb), static_cast<cpx<T>*>(c->bufa), tw, ya, 6,
                             c->stream);
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], c->stream)) != hipSuccess) return e;
   // x stage with products: Y -> X [8][n][n][H]
   const double csig = 3.0 / std::sqrt(8.0) * c->p.ch / c->p.we;
-  e = psms::launch_xstep<T>(c->E, static_cast<const cpx<T>*>(c->bufa), static_cast<cpx<T>*>(c->bufb), tw, c->plan, g,
-                            csig, c->xP, c->stream);
+  e = psms::launch_xstep<T>(n, static_cast<const cpx<T>*>(c->bufa), static_cast<cpx<T>*>(c->bufb), tw, csig,
+                            c->stream);
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], c->stream)) != hipSuccess) return e;
   // y-forward with truncation: X -> W [8][n][C][H]
   psms::LineArgs yf{};
-  yf.pl = c->plan;
   yf.n_in = n;
   yf.n_out = g.C;
   yf.inner = g.H;
@@ -222,14 +179,14 @@ hipError_t one_step(psms_ctx* c, hipEvent_t* ev = nullptr) {
   for (unsigned i = 0; i < 8; ++i) yf.fmap |= i << (4 * i);
   yf.dmask = 0;
   yf.scale = 1.0;
-  e = psms::launch_lines<T>(c->E, -1, static_cast<const cpx<T>*>(c->bufb), static_cast<cpx<T>*>(c->bufa), tw, yf, 8,
+  e = psms::launch_lines<T>(n, -1, static_cast<const cpx<T>*>(c->bufb), static_cast<cpx<T>*>(c->bufa), tw, yf, 8,
                             c->stream);
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[3], c->stream)) != hipSuccess) return e;
   // z-forward + update + z-inverse: W -> state, hist, G
   psms::StepCoef sc = step_coef(c);
-  e = psms::launch_zstep<T>(c->E, static_cast<const cpx<T>*>(c->bufa), c->state, c->hist,
-                            static_cast<cpx<T>*>(c->bufb), tw, c->plan, g, sc, 1, c->stream);
+  e = psms::launch_zstep<T>(n, static_cast<const cpx<T>*>(c->bufa), c->state, c->hist,
+                            static_cast<cpx<T>*>(c->bufb), tw, sc, 1, c->stream);
   if (e != hipSuccess) return e;
   if (ev) e = hipEventRecord(ev[4], c->stream);
   return e;
@@ -242,35 +199,32 @@ hipError_t forward_to_band(psms_ctx* c, const double* d_in, cpx<double>* d_out, 
   hipError_t e;
   for (int f = 0; f < nf; ++f) {
     psms::RowArgs ra{};
-    ra.pl = c->plan;
     ra.nrows = (long long)n * n;
     ra.n_in = n;
     ra.n_out = g.H;
     ra.in_fstride = 0;
     ra.out_fstride = 0;
     ra.scale = 1.0;
-    e = psms::launch_rows<double>(c->E, -1, d_in + (size_t)f * n * n * n, c->bufa, c->tw64, ra, 1, c->stream);
+    e = psms::launch_rows<double>(n, -1, d_in + (size_t)f * n * n * n, c->bufa, c->tw64, ra, 1, c->stream);
     if (e != hipSuccess) return e;
     psms::LineArgs ly{};
-    ly.pl = c->plan;
     ly.n_in = n;
     ly.n_out = g.C;
     ly.inner = g.H;
     ly.nlines = (long long)n * g.H;
     ly.fmap = 0;
     ly.scale = 1.0;
-    e = psms::launch_lines<double>(c->E, -1, static_cast<const cpx<double>*>(c->bufa),
+    e = psms::launch_lines<double>(n, -1, static_cast<const cpx<double>*>(c->bufa),
                                    static_cast<cpx<double>*>(c->bufb), c->tw64, ly, 1, c->stream);
     if (e != hipSuccess) return e;
     psms::LineArgs lz{};
-    lz.pl = c->plan;
     lz.n_in = n;
     lz.n_out = g.C;
     lz.inner = g.Q;
     lz.nlines = g.Q;
     lz.fmap = 0;
     lz.scale = 1.0 / (double(n) * n * n);
-    e = psms::launch_lines<double>(c->E, -1, static_cast<const cpx<double>*>(c->bufb), d_out + (size_t)f * g.M,
+    e = psms::launch_lines<double>(n, -1, static_cast<const cpx<double>*>(c->bufb), d_out + (size_t)f * g.M,
                                    c->tw64, lz, 1, c->stream);
     if (e != hipSuccess) return e;
   }
@@ -289,7 +243,6 @@ hipError_t transform_fields(psms_ctx* c, int dir, int nf, const void* d_in, void
   cpx<T>* A = static_cast<cpx<T>*>(c->bufa);
   cpx<T>* B = static_cast<cpx<T>*>(c->bufb);
   psms::LineArgs ly{};
-  ly.pl = c->plan;
   ly.n_in = n;
   ly.n_out = n;
   ly.inner = nh;
@@ -299,7 +252,6 @@ hipError_t transform_fields(psms_ctx* c, int dir, int nf, const void* d_in, void
   lz.inner = (long long)n * nh;
   lz.nlines = (long long)n * nh;
   psms::RowArgs ra{};
-  ra.pl = c->plan;
   ra.nrows = (long long)n * n;
   ra.n_in = nh;
   ra.n_out = nh;
@@ -310,9 +262,9 @@ hipError_t transform_fields(psms_ctx* c, int dir, int nf, const void* d_in, void
       const T* src = static_cast<const T*>(d_in) + f * nphys;
       cpx<T>* dst = static_cast<cpx<T>*>(d_out) + f * nfull;
       ra.n_in = n;
-      if ((e = psms::launch_rows<T>(c->E, -1, src, A, tw, ra, 1, c->stream)) != hipSuccess) return e;
-      if ((e = psms::launch_lines<T>(c->E, -1, A, B, tw, ly, 1, c->stream)) != hipSuccess) return e;
-      if ((e = psms::launch_lines<T>(c->E, -1, B, A, tw, lz, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_rows<T>(n, -1, src, A, tw, ra, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_lines<T>(n, -1, A, B, tw, ly, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_lines<T>(n, -1, B, A, tw, lz, 1, c->stream)) != hipSuccess) return e;
       if ((e = psms::launch_spec_finish<T>(A, dst, g, 1, dealias, axis, 1.0 / (double(n) * n * n), c->stream)) !=
           hipSuccess)
         return e;
@@ -320,11 +272,11 @@ hipError_t transform_fields(psms_ctx* c, int dir, int nf, const void* d_in, void
       const cpx<T>* src = static_cast<const cpx<T>*>(d_in) + f * nfull;
       T* dst = static_cast<T*>(d_out) + f * nphys;
       if ((e = psms::launch_spec_finish<T>(src, A, g, 1, dealias, axis, 1.0, c->stream)) != hipSuccess) return e;
-      if ((e = psms::launch_lines<T>(c->E, +1, A, B, tw, lz, 1, c->stream)) != hipSuccess) return e;
-      if ((e = psms::launch_lines<T>(c->E, +1, B, A, tw, ly, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_lines<T>(n, +1, A, B, tw, lz, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_lines<T>(n, +1, B, A, tw, ly, 1, c->stream)) != hipSuccess) return e;
       ra.n_in = nh;
       ra.n_out = n;
-      if ((e = psms::launch_rows<T>(c->E, +1, A, dst, tw, ra, 1, c->stream)) != hipSuccess) return e;
+      if ((e = psms::launch_rows<T>(n, +1, A, dst, tw, ra, 1, c->stream)) != hipSuccess) return e;
     }
   }
   return hipSuccess;
@@ -370,8 +322,6 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
   psms_ctx* c = new psms_ctx();
   c->p = *p;
   c->g = make_geom(p->n);
-  make_plan(p->n, &c->plan, &c->E);
-  c->xP = xstep_pairs(p->n, c->plan.tpl);
   c->s = (p->s > 0.0) ? p->s : std::sqrt(4.0 * p->pe / (p->ch * p->ch * p->dt));
   c->stream = static_cast<hipStream_t>(stream);
   c->lay = lay;
@@ -578,6 +528,133 @@ int psms_index_maps(psms_ctx* c, int32_t* d_out) {
   if (!c || !d_out) return fail(PSMS_E_INVAL, "NULL argument");
   hipError_t e = psms::launch_index_maps(d_out, c->g, c->stream);
   if (e != hipSuccess) return hip_fail(e, "index_maps");
+  return PSMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// wall-normal (Chebyshev) operations
+// ---------------------------------------------------------------------------
+
+int psms_cheb_transform(int32_t nc, int64_t nlines, int32_t dir, int32_t precision, const void* d_in, void* d_out,
+                        void* stream) {
+  if (!psms::supported_nc(nc)) return fail(PSMS_E_INVAL, "nc must be one of 4,6,8,12,16,24,32,48,64,96,128");
+  if (nlines < 0 || (dir != 1 && dir != -1)) return fail(PSMS_E_INVAL, "bad nlines or dir");
+  if (precision != PSMS_FP64 && precision != PSMS_MIXED) return fail(PSMS_E_INVAL, "bad precision");
+  if (nlines == 0) return PSMS_OK;
+  if (!d_in || !d_out) return fail(PSMS_E_INVAL, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = (precision == PSMS_FP64)
+                     ? psms::launch_dct<double>(nc, static_cast<const cpx<double>*>(d_in),
+                                                static_cast<cpx<double>*>(d_out), nlines, dir, st)
+                     : psms::launch_dct<float>(nc, static_cast<const cpx<float>*>(d_in),
+                                               static_cast<cpx<float>*>(d_out), nlines, dir, st);
+  if (e != hipSuccess) return hip_fail(e, "cheb_transform");
+  return PSMS_OK;
+}
+
+int psms_cheb_deriv(int32_t nc, int64_t nlines, const double* d_in, double* d_out, void* stream) {
+  if (nc < 2 || nlines < 0) return fail(PSMS_E_INVAL, "bad nc or nlines");
+  if (nlines == 0) return PSMS_OK;
+  if (!d_in || !d_out) return fail(PSMS_E_INVAL, "NULL argument");
+  if (d_in == d_out) return fail(PSMS_E_INVAL, "d_in and d_out must not overlap");
+  hipError_t e = psms::launch_chebd(reinterpret_cast<const cpx<double>*>(d_in), reinterpret_cast<cpx<double>*>(d_out),
+                                    nc, nlines, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "cheb_deriv");
+  return PSMS_OK;
+}
+
+int psms_cheb_helmholtz(int32_t nc, int64_t nlines, const double* d_beta, int32_t bc, const double* d_bcval,
+                        const double* d_rhs, double* d_out, double* d_work, void* stream) {
+  if (nc < 4 || nlines < 0) return fail(PSMS_E_INVAL, "bad nc or nlines");
+  if (bc != PSMS_DIRICHLET && bc != PSMS_NEUMANN) return fail(PSMS_E_INVAL, "bc must be DIRICHLET or NEUMANN");
+  if (nlines == 0) return PSMS_OK;
+  if (!d_beta || !d_rhs || !d_out || !d_work) return fail(PSMS_E_INVAL, "NULL argument");
+  if (d_rhs == d_out) return fail(PSMS_E_INVAL, "d_rhs and d_out must not overlap");
+  hipError_t e = psms::launch_helm(reinterpret_cast<const cpx<double>*>(d_rhs), reinterpret_cast<cpx<double>*>(d_out),
+                                   d_work, nc, nlines, d_beta, 0.0, nullptr, nullptr, bc == PSMS_NEUMANN ? 1 : 0,
+                                   reinterpret_cast<const cpx<double>*>(d_bcval), cpx<double>{0.0, 0.0},
+                                   cpx<double>{0.0, 0.0}, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "cheb_helmholtz");
+  return PSMS_OK;
+}
+
+namespace {
+struct WallLayout {
+  size_t line, psi, wt, psit, wb, psib, xi, dw, xw, total;
+};
+WallLayout wall_layout(int nc, long long nlines) {
+  WallLayout L{};
+  const size_t arr = align256(size_t(nc + 1) * size_t(nlines) * sizeof(cpx<double>));
+  size_t off = 0;
+  L.psi = off; off += arr;
+  L.wt = off; off += arr;
+  L.psit = off; off += arr;
+  L.wb = off; off += arr;
+  L.psib = off; off += arr;
+  L.xi = off; off += arr;
+  L.dw = off; off += arr;
+  L.xw = off; off += align256(size_t(nc + 1) * size_t(nlines) * sizeof(double));
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+int psms_wall_workspace_bytes(int32_t nc, int64_t nlines, size_t* bytes) {
+  if (nc < 4 || nlines < 0 || !bytes) return fail(PSMS_E_INVAL, "bad argument");
+  *bytes = wall_layout(nc, nlines).total;
+  return PSMS_OK;
+}
+
+int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* stream) {
+  if (!a) return fail(PSMS_E_INVAL, "NULL args");
+  const int nc = a->nc;
+  const long long nl = a->nlines;
+  if (nc < 4 || nl < 0 || a->reserved != 0) return fail(PSMS_E_INVAL, "bad nc, nlines or reserved");
+  if (!(a->beta_ns >= 0.0) || !(a->beta_a > 0.0) || !(a->beta_b > 0.0))
+    return fail(PSMS_E_INVAL, "beta_ns must be >= 0 and beta_a, beta_b > 0");
+  if (nl == 0) return PSMS_OK;
+  if (!a->d_kx || !a->d_ky || !a->d_g_om || !a->d_g_w || !a->d_g_phi || !a->d_om || !a->d_w || !a->d_phi ||
+      !a->d_u || !a->d_v)
+    return fail(PSMS_E_INVAL, "NULL argument");
+  const WallLayout L = wall_layout(nc, nl);
+  if (!d_work || !aligned(d_work)) return fail(PSMS_E_WORKSPACE, "workspace NULL or misaligned");
+  if (bytes < L.total) return fail(PSMS_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+  char* w = static_cast<char*>(d_work);
+  auto C = [&](size_t off) { return reinterpret_cast<cpx<double>*>(w + off); };
+  auto CC = [](const double* p) { return reinterpret_cast<const cpx<double>*>(p); };
+  auto CM = [](double* p) { return reinterpret_cast<cpx<double>*>(p); };
+  double* xw = reinterpret_cast<double*>(w + L.xw);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const cpx<double> z0 = {0.0, 0.0}, one = {1.0, 0.0};
+  hipError_t e;
+#define PSMS_TRY(x) \
+  if ((e = (x)) != hipSuccess) return hip_fail(e, "wall_solve")
+  // omega_z
+  PSMS_TRY(psms::launch_helm(CC(a->d_g_om), CM(a->d_om), xw, nc, nl, nullptr, a->beta_ns, a->d_kx, a->d_ky, 0,
+                             nullptr, z0, z0, st));
+  // w: particular and homogeneous solutions, then the influence-matrix combination
+  PSMS_TRY(psms::launch_helm(CC(a->d_g_w), C(L.psi), xw, nc, nl, nullptr, a->beta_ns, a->d_kx, a->d_ky, 0, nullptr,
+                             z0, z0, st));
+  PSMS_TRY(psms::launch_helm(C(L.psi), CM(a->d_w), xw, nc, nl, nullptr, 0.0, a->d_kx, a->d_ky, 0, nullptr, z0, z0,
+                             st));
+  PSMS_TRY(psms::launch_helm(nullptr, C(L.psit), xw, nc, nl, nullptr, a->beta_ns, a->d_kx, a->d_ky, 0, nullptr, one,
+                             z0, st));
+  PSMS_TRY(psms::launch_helm(C(L.psit), C(L.wt), xw, nc, nl, nullptr, 0.0, a->d_kx, a->d_ky, 0, nullptr, z0, z0,
+                             st));
+  PSMS_TRY(psms::launch_helm(nullptr, C(L.psib), xw, nc, nl, nullptr, a->beta_ns, a->d_kx, a->d_ky, 0, nullptr, z0,
+                             one, st));
+  PSMS_TRY(psms::launch_helm(C(L.psib), C(L.wb), xw, nc, nl, nullptr, 0.0, a->d_kx, a->d_ky, 0, nullptr, z0, z0,
+                             st));
+  PSMS_TRY(psms::launch_influence(CM(a->d_w), C(L.wt), C(L.wb), nc, nl, a->d_kx, a->d_ky, st));
+  // phi: two Neumann problems
+  PSMS_TRY(psms::launch_helm(CC(a->d_g_phi), C(L.xi), xw, nc, nl, nullptr, a->beta_a, a->d_kx, a->d_ky, 1, nullptr,
+                             z0, z0, st));
+  PSMS_TRY(psms::launch_helm(C(L.xi), CM(a->d_phi), xw, nc, nl, nullptr, a->beta_b, a->d_kx, a->d_ky, 1, nullptr, z0,
+                             z0, st));
+  // u, v
+  PSMS_TRY(psms::launch_chebd(CM(a->d_w), C(L.dw), nc, nl, st));
+  PSMS_TRY(psms::launch_uv(CM(a->d_om), C(L.dw), CM(a->d_u), CM(a->d_v), nc, nl, a->d_kx, a->d_ky, st));
+#undef PSMS_TRY
   return PSMS_OK;
 }
 

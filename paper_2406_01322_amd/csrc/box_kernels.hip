@@ -2,15 +2,15 @@
 //
 // The step of Sec. 2.2 (steps ii-v) is executed as four kernels per time step,
 // all on the caller's stream:
-//   k_lines  <inverse, y>  : y-inverse of u, v, w, phi, d_z phi, plus i k_y phi
-//   k_xstep                : x-inverse (7 fields) -> pointwise products
-//                            (Sec. 3.2.2, Hadamard products) -> x-forward (8)
-//   k_lines  <forward, y>  : y-forward with 2/3 truncation
-//   k_zstep                : z-forward, spectral RHS assembly, Leray projection,
-//                            CN/AB2 (NS) and IE/AB2 (CH) updates, then the
-//                            z-inverse of the new state for the next step.
+//   k_lines<+1>  y-inverse of u, v, w, phi, d_z phi, plus i k_y phi
+//   k_xstep      x-inverse (7 fields), the pointwise products (Sec. 3.2.2,
+//                Hadamard products) and the x-forward of the 8 products
+//   k_lines<-1>  y-forward with 2/3 truncation
+//   k_zstep      z-forward, spectral RHS assembly, Leray projection, CN/AB2
+//                (NS) and IE/AB2 (CH) updates, then the z-inverse of the new
+//                state for the next step.
 // Spectral data is stored only inside the retained band |k_i| <= K =
-// floor((N-1)/3), so the pruned transforms never touch discarded modes.
+// floor((N-1)/3), so the transforms never read or write discarded modes.
 //
 // Layouts (complex values interleaved re, im):
 //   state, history : [4][C kz][C ky][H kx] double   (C = 2K+1, H = K+1)
@@ -18,378 +18,426 @@
 //   Y (y-inverse)  : [6][N z][N y][H kx]            (u, v, w, phi, d_y phi, d_z phi)
 //   X (x-forward)  : [8][N z][N y][H kx]            (T_xx T_yy T_zz T_xy T_xz T_yz, a, c)
 //   W (y-forward)  : [8][N z][C ky][H kx]
+//
+// Every kernel is instantiated per transform length N (compile time) so that
+// all index arithmetic folds to constants.
 #include <hip/hip_runtime.h>
 
 #include "box_kernels.hpp"
-#include "fft_core.hpp"
+#include "fft_engine.hpp"
 
 namespace psms {
 
 template <typename T>
 __device__ __forceinline__ cpx<T> to_cpx(cpx<double> v) { return {T(v.re), T(v.im)}; }
-template <typename T>
-__device__ __forceinline__ cpx<double> to_dbl(cpx<T> v) { return {double(v.re), double(v.im)}; }
+
+template <int N>
+struct Tile {
+  static constexpr int E = Plan<N>::E;
+  static constexpr int TT = N / E;                    // threads per line
+  static constexpr int L = (256 / TT) > 0 ? 256 / TT : 1;  // lines per workgroup
+  static constexpr int K = (N - 1) / 3;
+  static constexpr int C = 2 * K + 1;
+  static constexpr int H = K + 1;
+};
 
 // ---------------------------------------------------------------------------
-// batched transforms along a strided axis (y or z)
-//   element (line l = o * inner + i, position a) at ((o * cnt + a) * inner + i)
-//   S = -1: forward, output band of n_out slots; S = +1: inverse, input band
-//   of n_in slots zero-padded to n.  Output field f = blockIdx.y reads input
-//   field (fmap >> 4f) & 15; bit f of dmask multiplies by i k along the axis.
+// batched transforms along a strided axis (y or z): L lines per workgroup,
+// lanes line-fastest, LDS element (pos, line) at pos * (L+1) + line.
+// S = -1 forward (output band of n_out slots), S = +1 inverse (input band of
+// n_in slots, zero-padded).  Output field f reads input field (fmap >> 4f)&15;
+// bit f of dmask multiplies by i k along the axis.
 // ---------------------------------------------------------------------------
-template <typename T, int E, int S>
-__global__ void __launch_bounds__(512) k_lines(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+template <typename T, int N, int S>
+__global__ void __launch_bounds__(256) k_lines(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                                const cpx<T>* __restrict__ tw_g, LineArgs a) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int n = a.pl.n;
-  cpx<T>* buf = tw + n;
-  const int tpl = a.pl.tpl;
-  const int L = blockDim.x / tpl;
-  const int lp = L + 1;
+  using G = Tile<N>;
+  constexpr int E = G::E, L = G::L, LP = L + 1;
+  constexpr int RI = first_radix<N, S>(), RO = last_radix<N, S>();
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> lds[2][N * LP];
   const int tid = threadIdx.x;
-  const int line = tid % L, lane = tid / L;
-  for (int i = tid; i < n; i += blockDim.x) tw[i] = tw_g[i];
+  const int line = tid % L, t = tid / L;
+  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
 
   const int fo = blockIdx.y;
   const cpx<T>* src = in + (long long)((a.fmap >> (4 * fo)) & 15) * a.in_fstride;
   cpx<T>* dst = out + (long long)fo * a.out_fstride;
   const bool deriv = (a.dmask >> fo) & 1;
-  const long long l0 = (long long)blockIdx.x * L;
+  const long long gl = (long long)blockIdx.x * L + line;
+  const bool valid = gl < a.nlines;
+  const long long o = valid ? gl / a.inner : 0, i = valid ? gl % a.inner : 0;
 
-  for (int idx = tid; idx < n * L; idx += blockDim.x) {
-    const int p = idx / L, l = idx % L;
-    const long long gl = l0 + l;
-    cpx<T> v = {T(0), T(0)};
-    const int slot = band_slot(p, a.n_in, n);
-    if (gl < a.nlines && slot >= 0) {
-      const long long o = gl / a.inner, i = gl % a.inner;
-      v = src[(o * a.n_in + slot) * a.inner + i];
-      if (S > 0 && deriv) {
-        const T k = T(signed_k(p, n));
-        v = cpx<T>{-k * v.im, k * v.re};
+  cpx<T> v[E];
+#pragma unroll
+  for (int b = 0; b < E / RI; ++b) {
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int p = slot_pos<N, RI>(t, b, r);
+      const int s = band_slot(p, a.n_in, N);
+      cpx<T> x = {T(0), T(0)};
+      if (valid && s >= 0) {
+        x = src[(o * a.n_in + s) * a.inner + i];
+        if (S > 0 && deriv) {
+          const T k = T(signed_k(p, N));
+          x = cpx<T>{-k * x.im, k * x.re};
+        }
       }
+      v[b * RI + r] = x;
     }
-    buf[p * lp + l] = v;
   }
   __syncthreads();
-  fft_tile<E, S>(buf, lp, line, lane, true, a.pl, tw);
+  int par = 0;
+  fft_line<T, N, S>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
   const T sc = T(a.scale);
-  for (int idx = tid; idx < a.n_out * L; idx += blockDim.x) {
-    const int slot = idx / L, l = idx % L;
-    const long long gl = l0 + l;
-    if (gl >= a.nlines) continue;
-    const int p = full_pos(slot, a.n_out, n);
-    cpx<T> v = buf[p * lp + l];
-    if (S < 0 && deriv) {
-      const T k = T(signed_k(p, n));
-      v = cpx<T>{-k * v.im, k * v.re};
+#pragma unroll
+  for (int b = 0; b < E / RO; ++b) {
+#pragma unroll
+    for (int r = 0; r < RO; ++r) {
+      const int p = slot_pos<N, RO>(t, b, r);
+      const int s = band_slot(p, a.n_out, N);
+      if (valid && s >= 0) {
+        cpx<T> x = v[b * RO + r];
+        if (S < 0 && deriv) {
+          const T k = T(signed_k(p, N));
+          x = cpx<T>{-k * x.im, k * x.re};
+        }
+        dst[(o * a.n_out + s) * a.inner + i] = cpx<T>{sc * x.re, sc * x.im};
+      }
     }
-    v.re *= sc;
-    v.im *= sc;
-    const long long o = gl / a.inner, i = gl % a.inner;
-    dst[(o * a.n_out + slot) * a.inner + i] = v;
   }
 }
 
 // ---------------------------------------------------------------------------
 // real transforms along x (contiguous rows), two rows packed per complex FFT
+// (z = a + i b).  L row pairs per workgroup, lanes position-fastest, LDS
+// element (pos, pair) at pair * (N+1) + pos.
 // ---------------------------------------------------------------------------
-template <typename T, int E>
-__global__ void __launch_bounds__(512) k_rows_fwd(const T* __restrict__ in, cpx<T>* __restrict__ out,
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_rows_fwd(const T* __restrict__ in, cpx<T>* __restrict__ out,
                                                   const cpx<T>* __restrict__ tw_g, RowArgs a) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int n = a.pl.n;
-  cpx<T>* buf = tw + n;
-  const int tpl = a.pl.tpl;
-  const int P = blockDim.x / tpl;
-  const int lp = P + 1;
+  using G = Tile<N>;
+  constexpr int E = G::E, TT = G::TT, L = G::L, LP = N + 1;
+  constexpr int RI = first_radix<N, -1>(), RO = last_radix<N, -1>();
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> lds[2][L * LP];
   const int tid = threadIdx.x;
-  const int line = tid % P, lane = tid / P;
-  for (int i = tid; i < n; i += blockDim.x) tw[i] = tw_g[i];
+  const int t = tid % TT, line = tid / TT;
+  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
   const T* src = in + (long long)blockIdx.y * a.in_fstride;
   cpx<T>* dst = out + (long long)blockIdx.y * a.out_fstride;
-  const long long r0 = (long long)blockIdx.x * 2 * P;
-  for (int idx = tid; idx < n * P; idx += blockDim.x) {
-    const int p = idx % n, pr = idx / n;
-    const long long r = r0 + 2 * pr;
-    cpx<T> v = {T(0), T(0)};
-    if (r < a.nrows) {
-      v.re = src[r * n + p];
-      v.im = (r + 1 < a.nrows) ? src[(r + 1) * n + p] : T(0);
+  const long long r0 = ((long long)blockIdx.x * L + line) * 2;
+  const bool v0 = r0 < a.nrows, v1 = r0 + 1 < a.nrows;
+  cpx<T> v[E];
+#pragma unroll
+  for (int b = 0; b < E / RI; ++b)
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int p = slot_pos<N, RI>(t, b, r);
+      v[b * RI + r] = cpx<T>{v0 ? src[r0 * N + p] : T(0), v1 ? src[(r0 + 1) * N + p] : T(0)};
     }
-    buf[p * lp + pr] = v;
-  }
   __syncthreads();
-  fft_tile<E, -1>(buf, lp, line, lane, true, a.pl, tw);
+  int par = 0;
+  const IdxLineMajor idx{line * LP};
+  fft_line<T, N, -1>(v, lds[0], lds[1], par, t, idx, tw);
+  cpx<T>* Lb = par ? lds[1] : lds[0];
+#pragma unroll
+  for (int b = 0; b < E / RO; ++b)
+#pragma unroll
+    for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<N, RO>(t, b, r))] = v[b * RO + r];
+  __syncthreads();
   const T h = T(0.5) * T(a.scale);
-  for (int idx = tid; idx < a.n_out * P; idx += blockDim.x) {
-    const int k = idx % a.n_out, pr = idx / a.n_out;
-    const long long r = r0 + 2 * pr;
-    if (r >= a.nrows) continue;
-    const cpx<T> zk = buf[k * lp + pr];
-    const cpx<T> zm = buf[((n - k) % n) * lp + pr];
-    dst[r * a.n_out + k] = cpx<T>{h * (zk.re + zm.re), h * (zk.im - zm.im)};
-    if (r + 1 < a.nrows) dst[(r + 1) * a.n_out + k] = cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)};
+  for (int k = t; k < a.n_out; k += TT) {
+    const cpx<T> zk = Lb[idx(k)];
+    const cpx<T> zm = Lb[idx((N - k) % N)];
+    if (v0) dst[r0 * a.n_out + k] = cpx<T>{h * (zk.re + zm.re), h * (zk.im - zm.im)};
+    if (v1) dst[(r0 + 1) * a.n_out + k] = cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)};
   }
 }
 
-template <typename T, int E>
-__global__ void __launch_bounds__(512) k_rows_inv(const cpx<T>* __restrict__ in, T* __restrict__ out,
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in, T* __restrict__ out,
                                                   const cpx<T>* __restrict__ tw_g, RowArgs a) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int n = a.pl.n;
-  cpx<T>* buf = tw + n;
-  const int tpl = a.pl.tpl;
-  const int P = blockDim.x / tpl;
-  const int lp = P + 1;
+  using G = Tile<N>;
+  constexpr int E = G::E, TT = G::TT, L = G::L, LP = N + 1;
+  constexpr int RI = first_radix<N, 1>(), RO = last_radix<N, 1>();
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> lds[2][L * LP];
   const int tid = threadIdx.x;
-  const int line = tid % P, lane = tid / P;
-  for (int i = tid; i < n; i += blockDim.x) tw[i] = tw_g[i];
+  const int t = tid % TT, line = tid / TT;
+  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
   const cpx<T>* src = in + (long long)blockIdx.y * a.in_fstride;
   T* dst = out + (long long)blockIdx.y * a.out_fstride;
-  const long long r0 = (long long)blockIdx.x * 2 * P;
-  const int half = n / 2;
-  for (int idx = tid; idx < n * P; idx += blockDim.x) {
-    const int p = idx % n, pr = idx / n;
-    const long long r = r0 + 2 * pr;
-    const int k = (p <= half) ? p : n - p;  // source wavenumber
-    cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
-    if (r < a.nrows && k < a.n_in) {
-      A = src[r * a.n_in + k];
-      if (r + 1 < a.nrows) B = src[(r + 1) * a.n_in + k];
-      if (k == 0 || 2 * k == n) {  // real-valued entries of a real signal's spectrum
-        A.im = T(0);
-        B.im = T(0);
+  const long long r0 = ((long long)blockIdx.x * L + line) * 2;
+  const bool v0 = r0 < a.nrows, v1 = r0 + 1 < a.nrows;
+  cpx<T> v[E];
+#pragma unroll
+  for (int b = 0; b < E / RI; ++b)
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int p = slot_pos<N, RI>(t, b, r);
+      const int k = (p <= N / 2) ? p : N - p;
+      cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
+      if (k < a.n_in) {
+        if (v0) A = src[r0 * a.n_in + k];
+        if (v1) B = src[(r0 + 1) * a.n_in + k];
+        if (k == 0 || 2 * k == N) {  // entries that are real for a real signal
+          A.im = T(0);
+          B.im = T(0);
+        }
       }
+      v[b * RI + r] = (p <= N / 2) ? cpx<T>{A.re - B.im, A.im + B.re}   // A + i B
+                                   : cpx<T>{A.re + B.im, B.re - A.im};  // conj(A) + i conj(B)
     }
-    cpx<T> z;
-    if (p <= half) z = cpx<T>{A.re - B.im, A.im + B.re};   // A + i B
-    else z = cpx<T>{A.re + B.im, B.re - A.im};              // conj(A) + i conj(B)
-    buf[p * lp + pr] = z;
-  }
   __syncthreads();
-  fft_tile<E, +1>(buf, lp, line, lane, true, a.pl, tw);
+  int par = 0;
+  fft_line<T, N, 1>(v, lds[0], lds[1], par, t, IdxLineMajor{line * LP}, tw);
   const T sc = T(a.scale);
-  for (int idx = tid; idx < n * P; idx += blockDim.x) {
-    const int p = idx % n, pr = idx / n;
-    const long long r = r0 + 2 * pr;
-    if (r >= a.nrows) continue;
-    const cpx<T> z = buf[p * lp + pr];
-    dst[r * n + p] = sc * z.re;
-    if (r + 1 < a.nrows) dst[(r + 1) * n + p] = sc * z.im;
-  }
+#pragma unroll
+  for (int b = 0; b < E / RO; ++b)
+#pragma unroll
+    for (int r = 0; r < RO; ++r) {
+      const int p = slot_pos<N, RO>(t, b, r);
+      if (v0) dst[r0 * N + p] = sc * v[b * RO + r].re;
+      if (v1) dst[(r0 + 1) * N + p] = sc * v[b * RO + r].im;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// fused x stage of the step: x-inverse of 7 fields, products, x-forward of 8
-// Block: 2P consecutive rows (row = z N + y); LDS holds [8 fields][n][P pairs].
+// fused x stage of the step.  Each row pair (rows 2l, 2l+1 of the N^2 rows
+// z N + y) is one complex line.  The 7 physical fields stay in registers at
+// the positions the inverse leaves them, which are the positions the forward
+// transform starts from, so the products need no data exchange.
 // ---------------------------------------------------------------------------
-template <typename T, int E>
-__global__ void __launch_bounds__(512) k_xstep(const cpx<T>* __restrict__ yin, cpx<T>* __restrict__ xout,
-                                               const cpx<T>* __restrict__ tw_g, FftPlan pl, BoxGeom g,
-                                               double csig_d, int P) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int n = pl.n;
-  cpx<T>* buf = tw + n;
-  const int lp = P + 1;
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_xstep(const cpx<T>* __restrict__ yin, cpx<T>* __restrict__ xout,
+                                               const cpx<T>* __restrict__ tw_g, double csig_d) {
+  using G = Tile<N>;
+  constexpr int E = G::E, TT = G::TT, L = G::L, LP = N + 1, K = G::K, H = G::H;
+  constexpr int RI = first_radix<N, 1>();   // inverse starts with R[NST-1]
+  constexpr int RP = last_radix<N, 1>();    // inverse ends / forward starts with R[0]
+  constexpr int RO = last_radix<N, -1>();   // forward ends with R[NST-1]
+  constexpr long long ROWS = (long long)N * N;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> lds[2][L * LP];
   const int tid = threadIdx.x;
-  const int nl = 8 * P;
-  const int lid = tid % nl, lane = tid / nl;
-  const int f = lid / P, pair = lid % P;
-  const int H = g.H;
-  const long long rows = (long long)n * n;
-  const long long r0 = (long long)blockIdx.x * 2 * P;
-  for (int i = tid; i < n; i += blockDim.x) tw[i] = tw_g[i];
-
-  // 1) pack the 7 physical inputs: u v w phi dx_phi dy_phi dz_phi
-  for (int idx = tid; idx < 7 * P * H; idx += blockDim.x) {
-    const int k = idx % H;
-    const int rest = idx / H;
-    const int pr = rest % P, vf = rest / P;
-    const int fin = (vf <= 3) ? vf : vf - 1;   // vf 4 reads phi and multiplies by i kx
-    const long long r = r0 + 2 * pr;
-    const cpx<T>* src = yin + (long long)fin * rows * H;
-    cpx<T> A = src[r * H + k];
-    cpx<T> B = src[(r + 1) * H + k];
-    if (vf == 4) {
-      const T kx = T(k);
-      A = cpx<T>{-kx * A.im, kx * A.re};
-      B = cpx<T>{-kx * B.im, kx * B.re};
-    }
-    if (k == 0) {
-      A.im = T(0);
-      B.im = T(0);
-    }
-    cpx<T>* b = buf + (long long)vf * n * lp;
-    b[k * lp + pr] = cpx<T>{A.re - B.im, A.im + B.re};
-    if (k > 0) b[(n - k) * lp + pr] = cpx<T>{A.re + B.im, B.re - A.im};
-  }
-  const int nz = n - 2 * H + 1;  // positions H .. n-H hold zeros
-  for (int idx = tid; idx < 7 * P * nz; idx += blockDim.x) {
-    const int p = H + idx % nz;
-    const int rest = idx / nz;
-    const int pr = rest % P, vf = rest / P;
-    buf[((long long)vf * n + p) * lp + pr] = cpx<T>{T(0), T(0)};
-  }
+  const int t = tid % TT, line = tid / TT;
+  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
+  const long long r0 = ((long long)blockIdx.x * L + line) * 2;
+  const bool valid = r0 < ROWS;  // ROWS is even: both rows exist
+  const IdxLineMajor idx{line * LP};
+  int par = 0;
   __syncthreads();
-  fft_tile<E, +1>(buf + (long long)f * n * lp, lp, pair, lane, f < 7, pl, tw);
 
-  // 2) products at every point of the 2P rows (re: even row, im: odd row)
-  const T cs = T(csig_d);
-  for (int idx = tid; idx < n * P; idx += blockDim.x) {
-    const int p = idx / P, pr = idx % P;
-    cpx<T> q[7];
+  // x-inverse of u v w phi dx_phi dy_phi dz_phi
+  cpx<T> ph[7][E];
 #pragma unroll
-    for (int v = 0; v < 7; ++v) q[v] = buf[((long long)v * n + p) * lp + pr];
-    cpx<T> o[8];
+  for (int vf = 0; vf < 7; ++vf) {
+    const int fin = (vf <= 3) ? vf : vf - 1;   // vf 4 is i kx times phi
+    const cpx<T>* src = yin + (long long)fin * ROWS * H;
+    cpx<T> v[E];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const T u = c ? q[0].im : q[0].re, vv = c ? q[1].im : q[1].re, w = c ? q[2].im : q[2].re;
-      const T ph = c ? q[3].im : q[3].re;
-      const T gx = c ? q[4].im : q[4].re, gy = c ? q[5].im : q[5].re, gz = c ? q[6].im : q[6].re;
-      const T g2 = gx * gx + gy * gy + gz * gz;
-      T r[8];
-      r[0] = -u * u + cs * (g2 - gx * gx);
-      r[1] = -vv * vv + cs * (g2 - gy * gy);
-      r[2] = -w * w + cs * (g2 - gz * gz);
-      r[3] = -u * vv - cs * gx * gy;
-      r[4] = -u * w - cs * gx * gz;
-      r[5] = -vv * w - cs * gy * gz;
-      r[6] = u * gx + vv * gy + w * gz;
-      r[7] = ph * ph * ph;
+    for (int b = 0; b < E / RI; ++b)
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        if (c) o[v].im = r[v];
-        else o[v].re = r[v];
+      for (int r = 0; r < RI; ++r) {
+        const int p = slot_pos<N, RI>(t, b, r);
+        const int k = (p <= N / 2) ? p : N - p;
+        cpx<T> z = {T(0), T(0)};
+        if (valid && k <= K) {
+          cpx<T> A = src[r0 * H + k];
+          cpx<T> B = src[(r0 + 1) * H + k];
+          if (vf == 4) {
+            const T kx = T(k);
+            A = cpx<T>{-kx * A.im, kx * A.re};
+            B = cpx<T>{-kx * B.im, kx * B.re};
+          }
+          if (k == 0) {
+            A.im = T(0);
+            B.im = T(0);
+          }
+          z = (p <= N / 2) ? cpx<T>{A.re - B.im, A.im + B.re} : cpx<T>{A.re + B.im, B.re - A.im};
+        }
+        v[b * RI + r] = z;
       }
-    }
+    fft_line<T, N, 1>(v, lds[0], lds[1], par, t, idx, tw);
 #pragma unroll
-    for (int v = 0; v < 8; ++v) buf[((long long)v * n + p) * lp + pr] = o[v];
+    for (int e = 0; e < E; ++e) ph[vf][e] = v[e];
   }
-  __syncthreads();
-  fft_tile<E, -1>(buf + (long long)f * n * lp, lp, pair, lane, true, pl, tw);
 
-  // 3) unpack the retained kx = 0..K of both rows and store
+  // products and x-forward of each
+  const T cs = T(csig_d);
   const T h = T(0.5);
-  for (int idx = tid; idx < 8 * P * H; idx += blockDim.x) {
-    const int k = idx % H;
-    const int rest = idx / H;
-    const int pr = rest % P, vf = rest / P;
-    const long long r = r0 + 2 * pr;
-    const cpx<T>* b = buf + (long long)vf * n * lp;
-    const cpx<T> zk = b[k * lp + pr];
-    const cpx<T> zm = b[((n - k) % n) * lp + pr];
-    cpx<T>* dst = xout + (long long)vf * rows * H;
-    dst[r * H + k] = cpx<T>{h * (zk.re + zm.re), h * (zk.im - zm.im)};
-    dst[(r + 1) * H + k] = cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)};
+#pragma unroll 1
+  for (int f = 0; f < 8; ++f) {
+    cpx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      T res[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const T u = c ? ph[0][e].im : ph[0][e].re;
+        const T vv = c ? ph[1][e].im : ph[1][e].re;
+        const T w = c ? ph[2][e].im : ph[2][e].re;
+        const T p3 = c ? ph[3][e].im : ph[3][e].re;
+        const T gx = c ? ph[4][e].im : ph[4][e].re;
+        const T gy = c ? ph[5][e].im : ph[5][e].re;
+        const T gz = c ? ph[6][e].im : ph[6][e].re;
+        T x;
+        switch (f) {
+          case 0: x = -u * u + cs * (gy * gy + gz * gz); break;     // T_xx
+          case 1: x = -vv * vv + cs * (gx * gx + gz * gz); break;   // T_yy
+          case 2: x = -w * w + cs * (gx * gx + gy * gy); break;     // T_zz
+          case 3: x = -u * vv - cs * gx * gy; break;                // T_xy
+          case 4: x = -u * w - cs * gx * gz; break;                 // T_xz
+          case 5: x = -vv * w - cs * gy * gz; break;                // T_yz
+          case 6: x = u * gx + vv * gy + w * gz; break;             // u . grad phi
+          default: x = p3 * p3 * p3; break;                         // phi^3
+        }
+        res[c] = x;
+      }
+      v[e] = cpx<T>{res[0], res[1]};
+    }
+    static_assert(RP == first_radix<N, -1>(), "mirrored radix order");
+    fft_line<T, N, -1>(v, lds[0], lds[1], par, t, idx, tw);
+    cpx<T>* Lb = par ? lds[1] : lds[0];
+    par ^= 1;
+#pragma unroll
+    for (int b = 0; b < E / RO; ++b)
+#pragma unroll
+      for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<N, RO>(t, b, r))] = v[b * RO + r];
+    __syncthreads();
+    cpx<T>* dst = xout + (long long)f * ROWS * H;
+    for (int k = t; valid && k < H; k += TT) {
+      const cpx<T> zk = Lb[idx(k)];
+      const cpx<T> zm = Lb[idx((N - k) % N)];
+      dst[r0 * H + k] = cpx<T>{h * (zk.re + zm.re), h * (zk.im - zm.im)};
+      dst[(r0 + 1) * H + k] = cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)};
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // fused z stage: z-forward of the 8 products, RHS, projection, update, and the
-// z-inverse of the new state.  One line per (ky, kx) retained pair q.
+// z-inverse of the new state.  One line per retained (ky, kx) pair q; each
+// thread keeps the modes its forward transform leaves in registers, which are
+// the inputs its inverse transform starts from.
 // do_update = 0 only loads the state and performs the z-inverse (prologue).
 // ---------------------------------------------------------------------------
-template <typename T, int E>
-__global__ void __launch_bounds__(512) k_zstep(const cpx<T>* __restrict__ rhs, cpx<double>* __restrict__ state,
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_zstep(const cpx<T>* __restrict__ rhs, cpx<double>* __restrict__ state,
                                                cpx<double>* __restrict__ hist, cpx<T>* __restrict__ gout,
-                                               const cpx<T>* __restrict__ tw_g, FftPlan pl, BoxGeom g,
-                                               StepCoef sc, int do_update) {
-  constexpr int J = (2 * E + 2) / 3;
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int n = pl.n;
-  cpx<T>* buf = tw + n;
-  const int tpl = pl.tpl;
-  const int L = blockDim.x / tpl;
-  const int lp = L + 1;
+                                               const cpx<T>* __restrict__ tw_g, StepCoef sc, int do_update) {
+  using G = Tile<N>;
+  constexpr int E = G::E, L = G::L, LP = L + 1, K = G::K, C = G::C, H = G::H;
+  constexpr int Q = C * H;
+  constexpr long long M = (long long)C * Q;
+  constexpr int RF = first_radix<N, -1>();   // forward starts with R[0]
+  constexpr int RL = last_radix<N, -1>();    // forward ends / inverse starts with R[NST-1]
+  static_assert(RL == first_radix<N, 1>(), "mirrored radix order");
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> lds[2][N * LP];
   const int tid = threadIdx.x;
-  const int line = tid % L, lane = tid / L;
-  for (int i = tid; i < n; i += blockDim.x) tw[i] = tw_g[i];
-
-  const int K = g.K, C = g.C, H = g.H;
-  const long long Q = g.Q, M = g.M;
-  const long long q0 = (long long)blockIdx.x * L;
-  const long long q = q0 + line;
+  const int line = tid % L, t = tid / L;
+  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
+  const int q = blockIdx.x * L + line;
   const bool valid = q < Q;
-  const int iy = valid ? int(q / H) : 0, ix = valid ? int(q % H) : 0;
+  const int iy = valid ? q / H : 0, ix = valid ? q % H : 0;
   const double kx = double(ix);
   const double ky = double(iy <= K ? iy : iy - C);
+  const IdxPosMajor idx{LP, line};
+  int par = 0;
 
-  cpx<double> acc[4][J];
+  // band membership and wavenumber of the slots the forward leaves in registers
+  bool inb[E];
+  int slot[E];
+  double kz[E];
+#pragma unroll
+  for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int p = slot_pos<N, RL>(t, b, r);
+      const int s = band_slot(p, C, N);
+      inb[b * RL + r] = valid && s >= 0;
+      slot[b * RL + r] = s;
+      kz[b * RL + r] = double(signed_k(p, N));
+    }
+
+  cpx<double> acc[4][E];
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int j = 0; j < J; ++j) acc[c][j] = cpx<double>{0.0, 0.0};
+    for (int e = 0; e < E; ++e) acc[c][e] = cpx<double>{0.0, 0.0};
 
+  __syncthreads();
   if (do_update) {
-    for (int f = 0; f < 8; ++f) {
-      const cpx<T>* src = rhs + (long long)f * n * Q;
-      for (int idx = tid; idx < n * L; idx += blockDim.x) {
-        const int p = idx / L, l = idx % L;
-        const long long qq = q0 + l;
-        buf[p * lp + l] = (qq < Q) ? src[(long long)p * Q + qq] : cpx<T>{T(0), T(0)};
-      }
-      __syncthreads();
-      fft_tile<E, -1>(buf, lp, line, lane, true, pl, tw);
+    cpx<T> nx[E];
 #pragma unroll
-      for (int j = 0; j < J; ++j) {
-        const int m = lane + tpl * j;
-        if (m < C && valid) {
-          const cpx<T> t = buf[full_pos(m, C, n) * lp + line];
-          const cpx<double> v = {double(t.re) * sc.inv_n3, double(t.im) * sc.inv_n3};
-          const double kz = double(m <= K ? m : m - C);
-          // i k v
-          const cpx<double> ikx = {-kx * v.im, kx * v.re};
-          const cpx<double> iky = {-ky * v.im, ky * v.re};
-          const cpx<double> ikz = {-kz * v.im, kz * v.re};
-          if (f == 0) acc[0][j] = cadd(acc[0][j], ikx);                 // d_x T_xx
-          else if (f == 1) acc[1][j] = cadd(acc[1][j], iky);            // d_y T_yy
-          else if (f == 2) acc[2][j] = cadd(acc[2][j], ikz);            // d_z T_zz
+    for (int b = 0; b < E / RF; ++b)
+#pragma unroll
+      for (int r = 0; r < RF; ++r)
+        nx[b * RF + r] = valid ? rhs[(long long)slot_pos<N, RF>(t, b, r) * Q + q] : cpx<T>{T(0), T(0)};
+#pragma unroll 1
+    for (int f = 0; f < 8; ++f) {
+      cpx<T> v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = nx[e];
+      if (f < 7) {  // prefetch the next field while this one is transformed
+        const cpx<T>* src = rhs + (long long)(f + 1) * N * Q;
+#pragma unroll
+        for (int b = 0; b < E / RF; ++b)
+#pragma unroll
+          for (int r = 0; r < RF; ++r)
+            nx[b * RF + r] = valid ? src[(long long)slot_pos<N, RF>(t, b, r) * Q + q] : cpx<T>{T(0), T(0)};
+      }
+      fft_line<T, N, -1>(v, lds[0], lds[1], par, t, idx, tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (inb[e]) {
+          const cpx<double> w = {double(v[e].re) * sc.inv_n3, double(v[e].im) * sc.inv_n3};
+          const cpx<double> ikx = {-kx * w.im, kx * w.re};
+          const cpx<double> iky = {-ky * w.im, ky * w.re};
+          const cpx<double> ikz = {-kz[e] * w.im, kz[e] * w.re};
+          if (f == 0) acc[0][e] = cadd(acc[0][e], ikx);                 // d_x T_xx
+          else if (f == 1) acc[1][e] = cadd(acc[1][e], iky);            // d_y T_yy
+          else if (f == 2) acc[2][e] = cadd(acc[2][e], ikz);            // d_z T_zz
           else if (f == 3) {                                             // T_xy
-            acc[0][j] = cadd(acc[0][j], iky);
-            acc[1][j] = cadd(acc[1][j], ikx);
+            acc[0][e] = cadd(acc[0][e], iky);
+            acc[1][e] = cadd(acc[1][e], ikx);
           } else if (f == 4) {                                           // T_xz
-            acc[0][j] = cadd(acc[0][j], ikz);
-            acc[2][j] = cadd(acc[2][j], ikx);
+            acc[0][e] = cadd(acc[0][e], ikz);
+            acc[2][e] = cadd(acc[2][e], ikx);
           } else if (f == 5) {                                           // T_yz
-            acc[1][j] = cadd(acc[1][j], ikz);
-            acc[2][j] = cadd(acc[2][j], iky);
+            acc[1][e] = cadd(acc[1][e], ikz);
+            acc[2][e] = cadd(acc[2][e], iky);
           } else if (f == 6) {                                           // -u.grad(phi)
-            acc[3][j] = csub(acc[3][j], v);
+            acc[3][e] = csub(acc[3][e], w);
           } else {                                                       // lap(phi^3) / Pe
-            const double k2 = kx * kx + ky * ky + kz * kz;
-            acc[3][j].re -= k2 * sc.inv_pe * v.re;
-            acc[3][j].im -= k2 * sc.inv_pe * v.im;
+            const double k2 = kx * kx + ky * ky + kz[e] * kz[e];
+            acc[3][e].re -= k2 * sc.inv_pe * w.re;
+            acc[3][e].im -= k2 * sc.inv_pe * w.im;
           }
         }
       }
-      __syncthreads();
     }
-    // spectral update of the owned modes
+    // spectral update of the owned modes (FP64)
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int m = lane + tpl * j;
-      if (m < C && valid) {
-        const double kz = double(m <= K ? m : m - C);
-        const double k2 = kx * kx + ky * ky + kz * kz;
-        const long long id = (long long)m * Q + q;
-        cpx<double> Sx = acc[0][j], Sy = acc[1][j], Sz = acc[2][j], Sp = acc[3][j];
+    for (int e = 0; e < E; ++e) {
+      if (inb[e]) {
+        const double k2 = kx * kx + ky * ky + kz[e] * kz[e];
+        const long long id = (long long)slot[e] * Q + q;
+        cpx<double> Sx = acc[0][e], Sy = acc[1][e], Sz = acc[2][e], Sp = acc[3][e];
         const cpx<double> ph = state[3 * M + id];
         Sp.re += sc.e_coef * k2 * ph.re;
         Sp.im += sc.e_coef * k2 * ph.im;
         if (k2 == 0.0) {
           Sx = Sy = Sz = Sp = cpx<double>{0.0, 0.0};
-        } else {  // Leray projection, FP64
+        } else {  // Leray projection
           const double ir = 1.0 / k2;
-          const cpx<double> kd = {kx * Sx.re + ky * Sy.re + kz * Sz.re, kx * Sx.im + ky * Sy.im + kz * Sz.im};
+          const double kze = kz[e];
+          const cpx<double> kd = {kx * Sx.re + ky * Sy.re + kze * Sz.re, kx * Sx.im + ky * Sy.im + kze * Sz.im};
           Sx.re -= kx * kd.re * ir; Sx.im -= kx * kd.im * ir;
           Sy.re -= ky * kd.re * ir; Sy.im -= ky * kd.im * ir;
-          Sz.re -= kz * kd.re * ir; Sz.im -= kz * kd.im * ir;
+          Sz.re -= kze * kd.re * ir; Sz.im -= kze * kd.im * ir;
         }
         cpx<double> ex[4] = {Sx, Sy, Sz, Sp};
         if (!sc.ab1) {
@@ -409,62 +457,52 @@ __global__ void __launch_bounds__(512) k_zstep(const cpx<T>* __restrict__ rhs, c
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const cpx<double> u = state[c * M + id];
-          const cpx<double> un = {((1.0 - a) * u.re + sc.dt * ex[c].re) * ia, ((1.0 - a) * u.im + sc.dt * ex[c].im) * ia};
+          const cpx<double> un = {((1.0 - a) * u.re + sc.dt * ex[c].re) * ia,
+                                  ((1.0 - a) * u.im + sc.dt * ex[c].im) * ia};
           state[c * M + id] = un;
-          acc[c][j] = un;
+          acc[c][e] = un;
         }
         const double den = 1.0 / (1.0 + sc.dt * sc.ch2_pe * (k2 * k2 + sc.s * k2));
         const cpx<double> pn = {(ph.re + sc.dt * ex[3].re) * den, (ph.im + sc.dt * ex[3].im) * den};
         state[3 * M + id] = pn;
-        acc[3][j] = pn;
+        acc[3][e] = pn;
       }
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int m = lane + tpl * j;
-      if (m < C && valid) {
-        const long long id = (long long)m * Q + q;
+    for (int e = 0; e < E; ++e) {
+      if (inb[e]) {
+        const long long id = (long long)slot[e] * Q + q;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c][j] = state[c * M + id];
+        for (int c = 0; c < 4; ++c) acc[c][e] = state[c * M + id];
       }
     }
   }
 
   // z-inverse of u, v, w, phi and i kz phi
-  const int nz = n - C;
+#pragma unroll 1
   for (int gf = 0; gf < 5; ++gf) {
-    for (int idx = tid; idx < nz * L; idx += blockDim.x) {
-      const int p = K + 1 + idx / L, l = idx % L;
-      buf[p * lp + l] = cpx<T>{T(0), T(0)};
-    }
+    cpx<T> v[E];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int m = lane + tpl * j;
-      if (m < C) {
-        cpx<double> v = {0.0, 0.0};
-        if (valid) {
-          if (gf == 0) v = acc[0][j];
-          else if (gf == 1) v = acc[1][j];
-          else if (gf == 2) v = acc[2][j];
-          else if (gf == 3) v = acc[3][j];
-          else {
-            const double kz = double(m <= K ? m : m - C);
-            v = cpx<double>{-kz * acc[3][j].im, kz * acc[3][j].re};
-          }
-        }
-        buf[full_pos(m, C, n) * lp + line] = to_cpx<T>(v);
+    for (int e = 0; e < E; ++e) {
+      cpx<double> x = {0.0, 0.0};
+      if (inb[e]) {
+        if (gf == 0) x = acc[0][e];
+        else if (gf == 1) x = acc[1][e];
+        else if (gf == 2) x = acc[2][e];
+        else if (gf == 3) x = acc[3][e];
+        else x = cpx<double>{-kz[e] * acc[3][e].im, kz[e] * acc[3][e].re};
       }
+      v[e] = to_cpx<T>(x);
     }
-    __syncthreads();
-    fft_tile<E, +1>(buf, lp, line, lane, true, pl, tw);
-    cpx<T>* dst = gout + (long long)gf * n * Q;
-    for (int idx = tid; idx < n * L; idx += blockDim.x) {
-      const int p = idx / L, l = idx % L;
-      const long long qq = q0 + l;
-      if (qq < Q) dst[(long long)p * Q + qq] = buf[p * lp + l];
+    fft_line<T, N, 1>(v, lds[0], lds[1], par, t, idx, tw);
+    cpx<T>* dst = gout + (long long)gf * N * Q;
+    if (valid) {
+#pragma unroll
+      for (int b = 0; b < E / RF; ++b)
+#pragma unroll
+        for (int r = 0; r < RF; ++r) dst[(long long)slot_pos<N, RF>(t, b, r) * Q + q] = v[b * RF + r];
     }
-    __syncthreads();
   }
 }
 
@@ -663,82 +701,109 @@ __global__ void k_diag_final(const double* __restrict__ part, int nb, const cpx<
 }
 
 // ---------------------------------------------------------------------------
-// host-side launchers
+// host-side launchers (dispatch on the transform length)
 // ---------------------------------------------------------------------------
-namespace {
-template <typename K>
-void set_lds(K kern, size_t bytes) {
-  if (bytes > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+#define PSMS_FOR_EACH_N(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+bool supported_n(int n) {
+  switch (n) {
+#define PSMS_CASE(NN) case NN:
+    PSMS_FOR_EACH_N(PSMS_CASE)
+#undef PSMS_CASE
+    return true;
+    default:
+      return false;
+  }
 }
+
+namespace {
+
+template <typename T, int N>
+hipError_t lines_n(int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, const LineArgs& a, int nfield,
+                   hipStream_t st) {
+  using G = Tile<N>;
+  const dim3 grid(unsigned((a.nlines + G::L - 1) / G::L), unsigned(nfield));
+  const dim3 block(unsigned(G::L * G::TT));
+  if (dir < 0) k_lines<T, N, -1><<<grid, block, 0, st>>>(in, out, tw, a);
+  else k_lines<T, N, 1><<<grid, block, 0, st>>>(in, out, tw, a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t rows_n(int dir, const void* in, void* out, const cpx<T>* tw, const RowArgs& a, int nfield,
+                  hipStream_t st) {
+  using G = Tile<N>;
+  const long long pairs = (a.nrows + 1) / 2;
+  const dim3 grid(unsigned((pairs + G::L - 1) / G::L), unsigned(nfield));
+  const dim3 block(unsigned(G::L * G::TT));
+  if (dir < 0)
+    k_rows_fwd<T, N><<<grid, block, 0, st>>>(static_cast<const T*>(in), static_cast<cpx<T>*>(out), tw, a);
+  else
+    k_rows_inv<T, N><<<grid, block, 0, st>>>(static_cast<const cpx<T>*>(in), static_cast<T*>(out), tw, a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t xstep_n(const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, double csig, hipStream_t st) {
+  using G = Tile<N>;
+  const long long pairs = (long long)N * N / 2;
+  k_xstep<T, N><<<unsigned((pairs + G::L - 1) / G::L), unsigned(G::L * G::TT), 0, st>>>(yin, xout, tw, csig);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t zstep_n(const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout, const cpx<T>* tw,
+                   const StepCoef& sc, int do_update, hipStream_t st) {
+  using G = Tile<N>;
+  const int Q = G::C * G::H;
+  k_zstep<T, N><<<unsigned((Q + G::L - 1) / G::L), unsigned(G::L * G::TT), 0, st>>>(rhs, state, hist, gout, tw, sc,
+                                                                                    do_update);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 template <typename T>
-hipError_t launch_lines(int E, int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, const LineArgs& a,
+hipError_t launch_lines(int n, int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, const LineArgs& a,
                         int nfield, hipStream_t st) {
-  const int L = line_tile(a.pl.tpl);
-  const dim3 grid(unsigned((a.nlines + L - 1) / L), unsigned(nfield));
-  const dim3 block(unsigned(L * a.pl.tpl));
-  const size_t lds = sizeof(cpx<T>) * (size_t(a.pl.n) + size_t(a.pl.n) * (L + 1));
-  if (E == 8) {
-    if (dir < 0) { set_lds(k_lines<T, 8, -1>, lds); k_lines<T, 8, -1><<<grid, block, lds, st>>>(in, out, tw, a); }
-    else { set_lds(k_lines<T, 8, 1>, lds); k_lines<T, 8, 1><<<grid, block, lds, st>>>(in, out, tw, a); }
-  } else {
-    if (dir < 0) { set_lds(k_lines<T, 12, -1>, lds); k_lines<T, 12, -1><<<grid, block, lds, st>>>(in, out, tw, a); }
-    else { set_lds(k_lines<T, 12, 1>, lds); k_lines<T, 12, 1><<<grid, block, lds, st>>>(in, out, tw, a); }
+  switch (n) {
+#define PSMS_CASE(NN) case NN: return lines_n<T, NN>(dir, in, out, tw, a, nfield, st);
+    PSMS_FOR_EACH_N(PSMS_CASE)
+#undef PSMS_CASE
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_rows(int E, int dir, const void* in, void* out, const cpx<T>* tw, const RowArgs& a, int nfield,
+hipError_t launch_rows(int n, int dir, const void* in, void* out, const cpx<T>* tw, const RowArgs& a, int nfield,
                        hipStream_t st) {
-  const int P = row_pairs(a.pl.tpl);
-  const dim3 grid(unsigned((a.nrows + 2 * P - 1) / (2 * P)), unsigned(nfield));
-  const dim3 block(unsigned(P * a.pl.tpl));
-  const size_t lds = sizeof(cpx<T>) * (size_t(a.pl.n) + size_t(a.pl.n) * (P + 1));
-  if (dir < 0) {
-    const T* src = static_cast<const T*>(in);
-    cpx<T>* dst = static_cast<cpx<T>*>(out);
-    if (E == 8) { set_lds(k_rows_fwd<T, 8>, lds); k_rows_fwd<T, 8><<<grid, block, lds, st>>>(src, dst, tw, a); }
-    else { set_lds(k_rows_fwd<T, 12>, lds); k_rows_fwd<T, 12><<<grid, block, lds, st>>>(src, dst, tw, a); }
-  } else {
-    const cpx<T>* src = static_cast<const cpx<T>*>(in);
-    T* dst = static_cast<T*>(out);
-    if (E == 8) { set_lds(k_rows_inv<T, 8>, lds); k_rows_inv<T, 8><<<grid, block, lds, st>>>(src, dst, tw, a); }
-    else { set_lds(k_rows_inv<T, 12>, lds); k_rows_inv<T, 12><<<grid, block, lds, st>>>(src, dst, tw, a); }
+  switch (n) {
+#define PSMS_CASE(NN) case NN: return rows_n<T, NN>(dir, in, out, tw, a, nfield, st);
+    PSMS_FOR_EACH_N(PSMS_CASE)
+#undef PSMS_CASE
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_xstep(int E, const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, const FftPlan& pl,
-                        const BoxGeom& g, double csig, int P, hipStream_t st) {
-  const long long rows = (long long)pl.n * pl.n;
-  const dim3 grid(unsigned(rows / (2 * P)));
-  const dim3 block(unsigned(8 * P * pl.tpl));
-  const size_t lds = sizeof(cpx<T>) * (size_t(pl.n) + 8 * size_t(pl.n) * (P + 1));
-  if (E == 8) { set_lds(k_xstep<T, 8>, lds); k_xstep<T, 8><<<grid, block, lds, st>>>(yin, xout, tw, pl, g, csig, P); }
-  else { set_lds(k_xstep<T, 12>, lds); k_xstep<T, 12><<<grid, block, lds, st>>>(yin, xout, tw, pl, g, csig, P); }
-  return hipGetLastError();
+hipError_t launch_xstep(int n, const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, double csig, hipStream_t st) {
+  switch (n) {
+#define PSMS_CASE(NN) case NN: return xstep_n<T, NN>(yin, xout, tw, csig, st);
+    PSMS_FOR_EACH_N(PSMS_CASE)
+#undef PSMS_CASE
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_zstep(int E, const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout,
-                        const cpx<T>* tw, const FftPlan& pl, const BoxGeom& g, const StepCoef& sc, int do_update,
-                        hipStream_t st) {
-  const int L = line_tile(pl.tpl);
-  const dim3 grid(unsigned((g.Q + L - 1) / L));
-  const dim3 block(unsigned(L * pl.tpl));
-  const size_t lds = sizeof(cpx<T>) * (size_t(pl.n) + size_t(pl.n) * (L + 1));
-  if (E == 8) {
-    set_lds(k_zstep<T, 8>, lds);
-    k_zstep<T, 8><<<grid, block, lds, st>>>(rhs, state, hist, gout, tw, pl, g, sc, do_update);
-  } else {
-    set_lds(k_zstep<T, 12>, lds);
-    k_zstep<T, 12><<<grid, block, lds, st>>>(rhs, state, hist, gout, tw, pl, g, sc, do_update);
+hipError_t launch_zstep(int n, const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout,
+                        const cpx<T>* tw, const StepCoef& sc, int do_update, hipStream_t st) {
+  switch (n) {
+#define PSMS_CASE(NN) case NN: return zstep_n<T, NN>(rhs, state, hist, gout, tw, sc, do_update, st);
+    PSMS_FOR_EACH_N(PSMS_CASE)
+#undef PSMS_CASE
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 static unsigned grid_for(long long tot) {
@@ -797,16 +862,14 @@ template hipError_t launch_rows<double>(int, int, const void*, void*, const cpx<
                                         hipStream_t);
 template hipError_t launch_rows<float>(int, int, const void*, void*, const cpx<float>*, const RowArgs&, int,
                                        hipStream_t);
-template hipError_t launch_xstep<double>(int, const cpx<double>*, cpx<double>*, const cpx<double>*, const FftPlan&,
-                                         const BoxGeom&, double, int, hipStream_t);
-template hipError_t launch_xstep<float>(int, const cpx<float>*, cpx<float>*, const cpx<float>*, const FftPlan&,
-                                        const BoxGeom&, double, int, hipStream_t);
-template hipError_t launch_zstep<double>(int, const cpx<double>*, cpx<double>*, cpx<double>*, cpx<double>*,
-                                         const cpx<double>*, const FftPlan&, const BoxGeom&, const StepCoef&, int,
+template hipError_t launch_xstep<double>(int, const cpx<double>*, cpx<double>*, const cpx<double>*, double,
                                          hipStream_t);
-template hipError_t launch_zstep<float>(int, const cpx<float>*, cpx<double>*, cpx<double>*, cpx<float>*,
-                                        const cpx<float>*, const FftPlan&, const BoxGeom&, const StepCoef&, int,
+template hipError_t launch_xstep<float>(int, const cpx<float>*, cpx<float>*, const cpx<float>*, double,
                                         hipStream_t);
+template hipError_t launch_zstep<double>(int, const cpx<double>*, cpx<double>*, cpx<double>*, cpx<double>*,
+                                         const cpx<double>*, const StepCoef&, int, hipStream_t);
+template hipError_t launch_zstep<float>(int, const cpx<float>*, cpx<double>*, cpx<double>*, cpx<float>*,
+                                        const cpx<float>*, const StepCoef&, int, hipStream_t);
 template hipError_t launch_expand<double>(const cpx<double>*, cpx<double>*, const BoxGeom&, int, hipStream_t);
 template hipError_t launch_compact<double>(const cpx<double>*, cpx<double>*, const BoxGeom&, int, hipStream_t);
 template hipError_t launch_spec_finish<double>(const cpx<double>*, cpx<double>*, const BoxGeom&, int, int, int,

@@ -3,7 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "fft_core.hpp"
+#include "fft_engine.hpp"
 
 namespace psms {
 
@@ -27,42 +27,40 @@ struct StepCoef {
   int ab1;         // 1: Adams-Bashforth order 1 (first step)
 };
 
+// Batched transform along a strided axis: line l = o * inner + i holds
+// element a at ((o * cnt + a) * inner + i), cnt = n_in on input, n_out on
+// output (n: the full axis, 2K+1: the retained band).
 struct LineArgs {
-  FftPlan pl;
   int n_in, n_out;
   long long inner, nlines;
   long long in_fstride, out_fstride;
   unsigned fmap;   // input field of output field f in bits 4f..4f+3
-  int dmask;
+  int dmask;       // bit f: multiply output field f by i k along the axis
   double scale;
 };
 
+// Real transforms along x: rows of n reals <-> rows of `cnt` complex
+// (cnt = n/2+1 for the full half spectrum, K+1 for the band).
 struct RowArgs {
-  FftPlan pl;
   long long nrows;
   int n_in, n_out;
   long long in_fstride, out_fstride;
   double scale;
 };
 
-// Lines per workgroup for the strided-axis kernels (about 256 threads).
-inline int line_tile(int tpl) { return tpl >= 256 ? 1 : 256 / tpl; }
-// Row pairs per workgroup for the generic real-row kernels.
-inline int row_pairs(int tpl) { return tpl >= 256 ? 1 : 256 / tpl; }
+bool supported_n(int n);
 
 template <typename T>
-hipError_t launch_lines(int E, int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, const LineArgs& a,
+hipError_t launch_lines(int n, int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, const LineArgs& a,
                         int nfield, hipStream_t st);
 template <typename T>
-hipError_t launch_rows(int E, int dir, const void* in, void* out, const cpx<T>* tw, const RowArgs& a, int nfield,
+hipError_t launch_rows(int n, int dir, const void* in, void* out, const cpx<T>* tw, const RowArgs& a, int nfield,
                        hipStream_t st);
 template <typename T>
-hipError_t launch_xstep(int E, const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, const FftPlan& pl,
-                        const BoxGeom& g, double csig, int P, hipStream_t st);
+hipError_t launch_xstep(int n, const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, double csig, hipStream_t st);
 template <typename T>
-hipError_t launch_zstep(int E, const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout,
-                        const cpx<T>* tw, const FftPlan& pl, const BoxGeom& g, const StepCoef& sc, int do_update,
-                        hipStream_t st);
+hipError_t launch_zstep(int n, const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout,
+                        const cpx<T>* tw, const StepCoef& sc, int do_update, hipStream_t st);
 template <typename T>
 hipError_t launch_expand(const cpx<T>* cmp, cpx<T>* full, const BoxGeom& g, int nf, hipStream_t st);
 template <typename T>

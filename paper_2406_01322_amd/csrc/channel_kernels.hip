@@ -1,0 +1,338 @@
+// Wall-normal (Chebyshev) kernels of the channel: Sec. 2.2 and Sec. 3.2.
+//
+//  * k_dct: the Chebyshev transform as a DCT-I obtained from the FFT of the
+//    2 nc-point even extension of each line (Sec. 3.2.1), applied to the real
+//    and imaginary parts at once.  Lines are (kx, ky) pairs, stored
+//    position-major ([n][line]), so the lanes of a wavefront read consecutive
+//    lines and no transpose is needed.
+//  * k_chebd: derivative in coefficient space by the backward recurrence
+//    c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n.
+//  * k_helm: the Chebyshev-tau Helmholtz problem (D^2 - beta) f = g with two
+//    Dirichlet or Neumann boundary rows, in FP64.  Rewriting the tau rows with
+//    the integration recurrence turns each parity (even / odd n) into a
+//    tridiagonal system plus one boundary row; it is solved by one downward
+//    elimination sweep and two upward sweeps, one thread per (line, parity)
+//    (Sec. 3.2.2: "tridiagonal systems ... Gauss elimination along z").
+//  * k_influence, k_uv: the influence-matrix combination that enforces
+//    w' = 0 at the walls, and u, v from continuity and eq. omegadef.
+#include <hip/hip_runtime.h>
+
+#include "channel_kernels.hpp"
+#include "fft_engine.hpp"
+
+namespace psms {
+
+namespace {
+
+template <int N>
+struct CTile {
+  static constexpr int E = Plan<N>::E;
+  static constexpr int TT = N / E;
+  static constexpr int L = (256 / TT) > 0 ? 256 / TT : 1;
+};
+
+}  // namespace
+
+// dir = +1: values at the CGL points -> Chebyshev coefficients,
+//   a_n = G_n / (nc cbar_n),  G = FFT of the even extension of f;
+// dir = -1: coefficients -> values, f_j = FFT of the even extension of b with
+//   b_0 = a_0, b_nc = a_nc, b_n = a_n / 2.
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                             long long nlines, int dir) {
+  using G = CTile<N>;
+  constexpr int E = G::E, L = G::L, LP = L + 1, NC = N / 2;
+  constexpr int RI = first_radix<N, -1>(), RO = last_radix<N, -1>();
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> lds[2][N * LP];
+  const int tid = threadIdx.x;
+  const int line = tid % L, t = tid / L;
+  for (int i = tid; i < N; i += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * double(i) / double(N), &s, &c);
+    tw[i] = cpx<T>{T(c), T(s)};
+  }
+  const long long l = (long long)blockIdx.x * L + line;
+  const bool valid = l < nlines;
+  cpx<T> v[E];
+#pragma unroll
+  for (int b = 0; b < E / RI; ++b)
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int p = slot_pos<N, RI>(t, b, r);
+      const int j = (p <= NC) ? p : N - p;
+      cpx<T> x = {T(0), T(0)};
+      if (valid) {
+        x = in[(long long)j * nlines + l];
+        if (dir < 0 && j != 0 && j != NC) {
+          x.re *= T(0.5);
+          x.im *= T(0.5);
+        }
+      }
+      v[b * RI + r] = x;
+    }
+  __syncthreads();
+  int par = 0;
+  fft_line<T, N, -1>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
+  if (valid) {
+#pragma unroll
+    for (int b = 0; b < E / RO; ++b)
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        const int p = slot_pos<N, RO>(t, b, r);
+        if (p <= NC) {
+          cpx<T> x = v[b * RO + r];
+          if (dir > 0) {
+            const T sc = T(1.0 / (double(NC) * ((p == 0 || p == NC) ? 2.0 : 1.0)));
+            x.re *= sc;
+            x.im *= sc;
+          }
+          out[(long long)p * nlines + l] = x;
+        }
+      }
+  }
+}
+
+// Coefficients of d/dz, one thread per line: b_nc = 0,
+// c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n for n = nc .. 1 (c_0 = 2, else 1).
+__global__ void k_chebd(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ d, int nc, long long nlines) {
+  const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlines) return;
+  cpx<double> b1 = {0.0, 0.0};  // b_{n+1}
+  cpx<double> b0 = {0.0, 0.0};  // b_n
+  d[(long long)nc * nlines + l] = b0;
+  for (int n = nc; n >= 1; --n) {
+    const cpx<double> an = a[(long long)n * nlines + l];
+    const double inv_c = (n - 1 == 0) ? 0.5 : 1.0;
+    const cpx<double> bm = {(b1.re + 2.0 * n * an.re) * inv_c, (b1.im + 2.0 * n * an.im) * inv_c};
+    d[(long long)(n - 1) * nlines + l] = bm;
+    b1 = b0;
+    b0 = bm;
+  }
+}
+
+// Chebyshev-tau Helmholtz solve (D^2 - beta) f = g, one thread per (line,
+// parity).  For n >= 2 the tau rows are equivalent to
+//   A_n a_{n-2} + B_n a_n + C_n a_{n+2} = R_n,
+//   A_n = c_{n-2} beta / (4 n (n-1)),  B_n = -(1 + e_n beta / (2 (n^2 - 1))),
+//   C_n = e_{n+2} beta / (4 n (n+1)),
+//   R_n = -c_{n-2} g_{n-2} / (4 n (n-1)) + e_n g_n / (2 (n^2 - 1)) - e_{n+2} g_{n+2} / (4 n (n+1)),
+// e_m = 1 if m <= nc-2 else 0; the boundary rows split into one row per parity.
+// beta = beta_line[l] (if given) + beta_add + (kx_l^2 + ky_l^2 if kx given).
+// Boundary values: bcv[2l], bcv[2l+1] (top z=+1, bottom z=-1; if given)
+// plus the constants top_c, bot_c.  g may be NULL (zero).  xw: nc+1 doubles
+// per line of scratch.
+__global__ void k_helm(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f, double* __restrict__ xw,
+                       int nc, long long nlines, const double* __restrict__ beta_line, double beta_add,
+                       const double* __restrict__ kx, const double* __restrict__ ky, int neumann,
+                       const cpx<double>* __restrict__ bcv, cpx<double> top_c, cpx<double> bot_c) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * nlines) return;
+  const long long l = id % nlines;
+  const int p = int(id / nlines);             // parity
+  double be = beta_add;
+  if (beta_line) be += beta_line[l];
+  if (kx) be += kx[l] * kx[l] + ky[l] * ky[l];
+  cpx<double> top = top_c, bot = bot_c;
+  if (bcv) {
+    top = cadd(top, bcv[2 * l]);
+    bot = cadd(bot, bcv[2 * l + 1]);
+  }
+  // boundary row of this parity: sum_i w_i a_i = s
+  cpx<double> s;
+  if (!neumann) s = (p == 0) ? cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)}
+                             : cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)};
+  else s = (p == 0) ? cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)}
+                    : cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)};
+  const int m = (nc - p) / 2;                 // indices n_i = p + 2 i, i = 0..m
+  auto G = [&](int n) -> cpx<double> {
+    if (!g || n > nc - 2 || n < 0) return cpx<double>{0.0, 0.0};
+    return g[(long long)n * nlines + l];
+  };
+  // downward sweep: a_i = X_i a_{i-1} + Y_i
+  double Xn = 0.0;
+  cpx<double> Yn = {0.0, 0.0};
+  cpx<double> gm = G(p + 2 * m - 2), g0 = G(p + 2 * m), g2 = G(p + 2 * m + 2);
+  for (int i = m; i >= 1; --i) {
+    const int n = p + 2 * i;
+    const double dn = double(n);
+    const double cm2 = (n - 2 == 0) ? 2.0 : 1.0;
+    const double en = (n <= nc - 2) ? 1.0 : 0.0;
+    const double en2 = (n + 2 <= nc - 2) ? 1.0 : 0.0;
+    const double q1 = 1.0 / (4.0 * dn * (dn - 1.0));
+    const double q2 = 1.0 / (2.0 * (dn * dn - 1.0));
+    const double q3 = 1.0 / (4.0 * dn * (dn + 1.0));
+    const double A = cm2 * be * q1;
+    const double B = -(1.0 + en * be * q2);
+    const double C = en2 * be * q3;
+    const cpx<double> R = {-cm2 * gm.re * q1 + en * g0.re * q2 - en2 * g2.re * q3,
+                           -cm2 * gm.im * q1 + en * g0.im * q2 - en2 * g2.im * q3};
+    const double den = 1.0 / (B + C * Xn);
+    const double X = -A * den;
+    const cpx<double> Y = {(R.re - C * Yn.re) * den, (R.im - C * Yn.im) * den};
+    xw[(long long)n * nlines + l] = X;
+    f[(long long)n * nlines + l] = Y;
+    Xn = X;
+    Yn = Y;
+    g2 = g0;
+    g0 = gm;
+    gm = G(n - 4);
+  }
+  // upward sweep 1: a_i = P_i a_0 + Q_i, accumulate the boundary row
+  double P = 1.0, SP = 0.0;
+  cpx<double> Qv = {0.0, 0.0}, SQ = {0.0, 0.0};
+  for (int i = 0; i <= m; ++i) {
+    const int n = p + 2 * i;
+    if (i > 0) {
+      const double X = xw[(long long)n * nlines + l];
+      const cpx<double> Y = f[(long long)n * nlines + l];
+      P = X * P;
+      Qv = cpx<double>{X * Qv.re + Y.re, X * Qv.im + Y.im};
+    }
+    const double w = neumann ? double(n) * double(n) : 1.0;
+    SP += w * P;
+    SQ.re += w * Qv.re;
+    SQ.im += w * Qv.im;
+  }
+  // a_0, then upward sweep 2
+  cpx<double> a = {(s.re - SQ.re) / SP, (s.im - SQ.im) / SP};
+  f[(long long)p * nlines + l] = a;
+  for (int i = 1; i <= m; ++i) {
+    const int n = p + 2 * i;
+    const double X = xw[(long long)n * nlines + l];
+    const cpx<double> Y = f[(long long)n * nlines + l];
+    a = cpx<double>{X * a.re + Y.re, X * a.im + Y.im};
+    f[(long long)n * nlines + l] = a;
+  }
+}
+
+// w = w_p + c_t w_t + c_b w_b with (c_t, c_b) making w'(+1) = w'(-1) = 0;
+// w = 0 where kx = ky = 0.  Written over w_p.
+__global__ void k_influence(cpx<double>* __restrict__ wp, const cpx<double>* __restrict__ wt,
+                            const cpx<double>* __restrict__ wb, int nc, long long nlines,
+                            const double* __restrict__ kx, const double* __restrict__ ky) {
+  const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlines) return;
+  const bool mean = (kx[l] == 0.0 && ky[l] == 0.0);
+  cpx<double> dpt = {0, 0}, dpb = {0, 0};
+  double dtt = 0, dtb = 0, dbt = 0, dbb = 0;
+  for (int n = 0; n <= nc; ++n) {
+    const double w2 = double(n) * double(n);
+    const double sg = (n & 1) ? w2 : -w2;  // (-1)^(n+1) n^2
+    const long long o = (long long)n * nlines + l;
+    const cpx<double> a = wp[o];
+    dpt.re += w2 * a.re; dpt.im += w2 * a.im;
+    dpb.re += sg * a.re; dpb.im += sg * a.im;
+    dtt += w2 * wt[o].re; dtb += sg * wt[o].re;
+    dbt += w2 * wb[o].re; dbb += sg * wb[o].re;
+  }
+  // [dtt dbt; dtb dbb] (c_t, c_b) = -(dpt, dpb)
+  const double det = dtt * dbb - dbt * dtb;
+  const cpx<double> ct = {(-dpt.re * dbb + dbt * dpb.re) / det, (-dpt.im * dbb + dbt * dpb.im) / det};
+  const cpx<double> cb = {(-dtt * dpb.re + dtb * dpt.re) / det, (-dtt * dpb.im + dtb * dpt.im) / det};
+  for (int n = 0; n <= nc; ++n) {
+    const long long o = (long long)n * nlines + l;
+    cpx<double> w = {0.0, 0.0};
+    if (!mean) {
+      const cpx<double> a = wp[o];
+      const double t = wt[o].re, b = wb[o].re;
+      w = cpx<double>{a.re + ct.re * t + cb.re * b, a.im + ct.im * t + cb.im * b};
+    }
+    wp[o] = w;
+  }
+}
+
+// u = i (kx w' + ky omega) / k^2, v = i (ky w' - kx omega) / k^2 (0 where k = 0).
+__global__ void k_uv(const cpx<double>* __restrict__ om, const cpx<double>* __restrict__ dw, cpx<double>* __restrict__ u,
+                     cpx<double>* __restrict__ v, int nc, long long nlines, const double* __restrict__ kx,
+                     const double* __restrict__ ky) {
+  const long long tot = (long long)(nc + 1) * nlines;
+  for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < tot;
+       id += (long long)gridDim.x * blockDim.x) {
+    const long long l = id % nlines;
+    const double a = kx[l], b = ky[l];
+    const double k2 = a * a + b * b;
+    cpx<double> uu = {0.0, 0.0}, vv = {0.0, 0.0};
+    if (k2 != 0.0) {
+      const double ik = 1.0 / k2;
+      const cpx<double> o = om[id], d = dw[id];
+      const cpx<double> su = {a * d.re + b * o.re, a * d.im + b * o.im};
+      const cpx<double> sv = {b * d.re - a * o.re, b * d.im - a * o.im};
+      uu = cpx<double>{-su.im * ik, su.re * ik};
+      vv = cpx<double>{-sv.im * ik, sv.re * ik};
+    }
+    u[id] = uu;
+    v[id] = vv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define PSMS_FOR_EACH_2NC(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+bool supported_nc(int nc) {
+  switch (2 * nc) {
+#define PSMS_CASE(NN) case NN:
+    PSMS_FOR_EACH_2NC(PSMS_CASE)
+#undef PSMS_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+namespace {
+template <typename T, int N>
+hipError_t dct_n(const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st) {
+  using G = CTile<N>;
+  k_dct<T, N><<<unsigned((nlines + G::L - 1) / G::L), unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir);
+  return hipGetLastError();
+}
+unsigned blocks(long long n, int bs) {
+  long long b = (n + bs - 1) / bs;
+  return unsigned(b < 1 ? 1 : b);
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st) {
+  switch (2 * nc) {
+#define PSMS_CASE(NN) case NN: return dct_n<T, NN>(in, out, nlines, dir, st);
+    PSMS_FOR_EACH_2NC(PSMS_CASE)
+#undef PSMS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st) {
+  k_chebd<<<blocks(nlines, 128), 128, 0, st>>>(a, d, nc, nlines);
+  return hipGetLastError();
+}
+
+hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc, long long nlines,
+                       const double* beta_line, double beta_add, const double* kx, const double* ky, int neumann,
+                       const cpx<double>* bcv, cpx<double> top_c, cpx<double> bot_c, hipStream_t st) {
+  k_helm<<<blocks(2 * nlines, 128), 128, 0, st>>>(g, f, xw, nc, nlines, beta_line, beta_add, kx, ky, neumann, bcv,
+                                                   top_c, bot_c);
+  return hipGetLastError();
+}
+
+hipError_t launch_influence(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
+                            const double* kx, const double* ky, hipStream_t st) {
+  k_influence<<<blocks(nlines, 128), 128, 0, st>>>(wp, wt, wb, nc, nlines, kx, ky);
+  return hipGetLastError();
+}
+
+hipError_t launch_uv(const cpx<double>* om, const cpx<double>* dw, cpx<double>* u, cpx<double>* v, int nc,
+                     long long nlines, const double* kx, const double* ky, hipStream_t st) {
+  long long b = ((long long)(nc + 1) * nlines + 255) / 256;
+  if (b > 65536) b = 65536;
+  k_uv<<<unsigned(b < 1 ? 1 : b), 256, 0, st>>>(om, dw, u, v, nc, nlines, kx, ky);
+  return hipGetLastError();
+}
+
+template hipError_t launch_dct<double>(int, const cpx<double>*, cpx<double>*, long long, int, hipStream_t);
+template hipError_t launch_dct<float>(int, const cpx<float>*, cpx<float>*, long long, int, hipStream_t);
+
+}  // namespace psms

@@ -1,0 +1,24 @@
+// Launchers of the wall-normal (Chebyshev) kernels.  Lines are stored
+// position-major: coefficient / point n of line l at n * nlines + l.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_engine.hpp"
+
+namespace psms {
+
+bool supported_nc(int nc);
+
+template <typename T>
+hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st);
+hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st);
+hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc, long long nlines,
+                       const double* beta_line, double beta_add, const double* kx, const double* ky, int neumann,
+                       const cpx<double>* bcv, cpx<double> top_c, cpx<double> bot_c, hipStream_t st);
+hipError_t launch_influence(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
+                            const double* kx, const double* ky, hipStream_t st);
+hipError_t launch_uv(const cpx<double>* om, const cpx<double>* dw, cpx<double>* u, cpx<double>* v, int nc,
+                     long long nlines, const double* kx, const double* ky, hipStream_t st);
+
+}  // namespace psms

@@ -41,6 +41,17 @@ class Diag(ctypes.Structure):
                 ("max_div", ctypes.c_double), ("nonfinite", ctypes.c_int32), ("nstep", ctypes.c_int32)]
 
 
+class WallArgs(ctypes.Structure):
+    _fields_ = [("nc", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nlines", ctypes.c_int64),
+                ("d_kx", ctypes.c_void_p), ("d_ky", ctypes.c_void_p), ("beta_ns", ctypes.c_double),
+                ("beta_a", ctypes.c_double), ("beta_b", ctypes.c_double), ("d_g_om", ctypes.c_void_p),
+                ("d_g_w", ctypes.c_void_p), ("d_g_phi", ctypes.c_void_p), ("d_om", ctypes.c_void_p),
+                ("d_w", ctypes.c_void_p), ("d_phi", ctypes.c_void_p), ("d_u", ctypes.c_void_p),
+                ("d_v", ctypes.c_void_p)]
+
+
+DIRICHLET, NEUMANN = 1, 2
+
 _lib = None
 
 _SIGS = {
@@ -60,6 +71,16 @@ _SIGS = {
     "psms_index_maps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "psms_band_modes": (ctypes.c_int64, [ctypes.c_void_p]),
     "psms_stage_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "psms_cheb_transform": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "psms_cheb_deriv": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "psms_cheb_helmholtz": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "psms_wall_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "psms_wall_solve": (ctypes.c_int, [ctypes.POINTER(WallArgs), ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p]),
     "psms_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "psms_last_error": (ctypes.c_char_p, []),
     "psms_version": (ctypes.c_char_p, []),
@@ -227,3 +248,79 @@ class Solver:
         out = self.torch.empty((m, 4), dtype=self.torch.int32, device=self.device)
         _check(lib().psms_index_maps(self.ctx, _ptr(out)))
         return out
+
+
+# ---------------------------------------------------------------------------
+# wall-normal (Chebyshev) operations: stateless calls on torch's current stream
+# ---------------------------------------------------------------------------
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def cheb_transform(x, direction):
+    """DCT-I Chebyshev transform of lines x [nc+1, nlines] (complex128 or complex64, on the GPU).
+    direction +1: values at the CGL points -> coefficients; -1: coefficients -> values."""
+    import torch
+    x = x.contiguous()
+    prec = {torch.complex128: FP64, torch.complex64: MIXED}[x.dtype]
+    out = torch.empty_like(x)
+    nc = x.shape[0] - 1
+    nl = x.numel() // (nc + 1)
+    _check(lib().psms_cheb_transform(nc, nl, 1 if direction > 0 else -1, prec, _ptr(x), _ptr(out), _stream()))
+    return out
+
+
+def cheb_deriv(a):
+    """Coefficients of d/dz of a [nc+1, nlines] complex128."""
+    import torch
+    a = a.contiguous()
+    if a.dtype != torch.complex128:
+        raise ValueError("complex128 required")
+    out = torch.empty_like(a)
+    nc = a.shape[0] - 1
+    _check(lib().psms_cheb_deriv(nc, a.numel() // (nc + 1), _ptr(a), _ptr(out), _stream()))
+    return out
+
+
+def cheb_helmholtz(g, beta, bc="dirichlet", bcval=None):
+    """Chebyshev-tau solve of (D^2 - beta_l) f = g per line (FP64).  g [nc+1, nlines] complex128,
+    beta [nlines] float64, bcval [nlines, 2] complex128 (top, bottom) or None."""
+    import torch
+    g = g.contiguous()
+    if g.dtype != torch.complex128:
+        raise ValueError("complex128 required")
+    nc = g.shape[0] - 1
+    nl = g.numel() // (nc + 1)
+    beta = beta.to(dtype=torch.float64).contiguous()
+    out = torch.empty_like(g)
+    work = torch.empty((nc + 1) * max(nl, 1), dtype=torch.float64, device=g.device)
+    bv = None
+    if bcval is not None:
+        bcval = bcval.to(dtype=torch.complex128).contiguous()
+        bv = _ptr(bcval)
+    kind = {"dirichlet": DIRICHLET, "neumann": NEUMANN}[bc]
+    _check(lib().psms_cheb_helmholtz(nc, nl, _ptr(beta), kind, bv, _ptr(g), _ptr(out), _ptr(work), _stream()))
+    return out
+
+
+def wall_solve(kx, ky, beta_ns, beta_a, beta_b, g_om, g_w, g_phi):
+    """The implicit wall-normal solves of a channel step for every (kx, ky) line.
+    kx, ky [nlines] float64; g_* [nc+1, nlines] complex128.  Returns dict of
+    omega, w, phi, u, v coefficient arrays."""
+    import torch
+    nc = g_om.shape[0] - 1
+    nl = g_om.numel() // (nc + 1)
+    kx = kx.to(torch.float64).contiguous()
+    ky = ky.to(torch.float64).contiguous()
+    g = [t.contiguous() for t in (g_om, g_w, g_phi)]
+    outs = {k: torch.empty_like(g[0]) for k in ("omega", "w", "phi", "u", "v")}
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().psms_wall_workspace_bytes(nc, nl, ctypes.byref(nbytes)))
+    work = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=g_om.device)
+    a = WallArgs(nc, 0, nl, kx.data_ptr(), ky.data_ptr(), float(beta_ns), float(beta_a), float(beta_b),
+                 g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(), outs["omega"].data_ptr(), outs["w"].data_ptr(),
+                 outs["phi"].data_ptr(), outs["u"].data_ptr(), outs["v"].data_ptr())
+    _check(lib().psms_wall_solve(ctypes.byref(a), _ptr(work), int(nbytes.value), _stream()))
+    return outs
