@@ -230,6 +230,43 @@ typedef struct psms_wall_args {
 int psms_wall_workspace_bytes(int32_t nc, int64_t nlines, size_t* bytes);
 int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches of independent boxes of uneven size (each with its own N, Re, We,
+ * Ch, Pe, dt, s; one precision for the whole batch).  Boxes of equal N form a
+ * group; each stage kernel is launched once per group and advances all its
+ * boxes (blockIdx.z indexes a device table of box descriptors).  After the
+ * first (Adams-Bashforth 1) step, one step of all groups is captured in a
+ * hipGraph and replayed, so a step costs one graph launch.
+ * ------------------------------------------------------------------------- */
+typedef struct psms_batch psms_batch;
+
+/* Workspace for nbox boxes with parameters p[0..nbox-1] (host only). */
+int psms_batch_workspace_bytes(int32_t nbox, const psms_params* p, size_t* bytes);
+/* Create: validates every p[i], checks the device, carves the workspace.
+ * Graph replay needs a non-NULL stream (a stream that can be captured). */
+int psms_batch_create(psms_batch** out, int32_t nbox, const psms_params* p, void* d_workspace, size_t bytes,
+                      void* stream);
+/* psms_init_state / psms_get_state / psms_diagnostics of box `box`. */
+int psms_batch_init_state(psms_batch* b, int32_t box, const double* d_u, const double* d_phi);
+int psms_batch_get_state(psms_batch* b, int32_t box, double* d_uhat, double* d_phihat);
+int psms_batch_diagnostics(psms_batch* b, int32_t box, psms_diag* h_out);
+/* Advance every box by nsteps.  use_graph != 0 replays a captured graph for
+ * every step after the first (needs a non-NULL stream). */
+int psms_batch_step(psms_batch* b, int32_t nsteps, int32_t use_graph);
+/* Groups in ascending N: *h_ngroups, and per group its N and box count
+ * (h_n, h_count may be NULL; otherwise they hold *h_ngroups entries). */
+int psms_batch_groups(const psms_batch* b, int32_t* h_ngroups, int32_t* h_n, int32_t* h_count);
+/* Workgroup-size variant (0, 1, 2: 64, 128, 256 threads) of each stage of each
+ * group, h_variants[4 * group + stage]. */
+int psms_batch_set_variants(psms_batch* b, const int32_t* h_variants);
+/* Autotuner: times every variant of every stage of every group (reps
+ * launches each, HIP events on the batch stream) and keeps the fastest.
+ * Must run before any init_state (it zeroes the boxes' state and
+ * intermediates).  h_variants [4 * ngroups] (nullable) receives the choice,
+ * h_ms [4 * ngroups * 3] (nullable) the average ms of every variant. */
+int psms_batch_autotune(psms_batch* b, int32_t reps, int32_t* h_variants, double* h_ms);
+int psms_batch_destroy(psms_batch* b);
+
 /* Number of retained modes per field, (2K+1)^2 (K+1). */
 int64_t psms_band_modes(const psms_ctx* c);
 

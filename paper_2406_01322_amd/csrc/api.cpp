@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -31,7 +32,7 @@ int hip_fail(hipError_t e, const char* where) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t state, hist, bufa, bufb, tw64, tw32, diag, diag_out, total;
+  size_t state, hist, bufa, bufb, tw64, tw32, diag, diag_out, box, total;
   size_t bufa_bytes, bufb_bytes;
 };
 
@@ -67,6 +68,7 @@ Layout make_layout(const psms_params& p) {
   L.tw32 = off; off = align256(off + n * sizeof(cpx<float>));
   L.diag = off; off = align256(off + 4 * kDiagBlocks * sizeof(double));
   L.diag_out = off; off = align256(off + 8 * sizeof(double));
+  L.box = off; off = align256(off + sizeof(psms::BoxDev));
   L.total = off;
   return L;
 }
@@ -104,6 +106,10 @@ struct psms_ctx {
   cpx<float>* tw32;
   double* diag;
   double* diag_out;
+  psms::BoxDev* d_box;   // one-entry device descriptor table
+  psms::BoxDev h_box;    // its host copy
+  int box_ab1;           // ab1 value last written to d_box (-1: never)
+  int variant[4];        // workgroup-size variant per stage
   int have_state;
   int g_valid;  // the z-inverse of the current state sits in bufb
   int nstep;
@@ -126,68 +132,40 @@ psms::StepCoef step_coef(const psms_ctx* c) {
   return sc;
 }
 
+template <typename T>
+const cpx<T>* twiddles(const psms_ctx* c) {
+  return std::is_same<T, double>::value ? reinterpret_cast<const cpx<T>*>(c->tw64)
+                                        : reinterpret_cast<const cpx<T>*>(c->tw32);
+}
+
+// Make the device descriptor's Adams-Bashforth flag match the step count.
+hipError_t sync_box(psms_ctx* c) {
+  const int ab1 = (c->nstep == 0) ? 1 : 0;
+  if (c->box_ab1 == ab1) return hipSuccess;
+  c->h_box.sc = step_coef(c);
+  c->box_ab1 = ab1;
+  return hipMemcpyAsync(c->d_box, &c->h_box, sizeof(psms::BoxDev), hipMemcpyHostToDevice, c->stream);
+}
+
 // z-inverse of the current state into bufb (the input of the next step).
 template <typename T>
 hipError_t prologue(psms_ctx* c) {
-  const cpx<T>* tw = std::is_same<T, double>::value ? reinterpret_cast<const cpx<T>*>(c->tw64)
-                                                     : reinterpret_cast<const cpx<T>*>(c->tw32);
-  psms::StepCoef sc = step_coef(c);
-  return psms::launch_zstep<T>(c->g.n, nullptr, c->state, c->hist, static_cast<cpx<T>*>(c->bufb), tw, sc, 0,
-                               c->stream);
+  hipError_t e = sync_box(c);
+  if (e != hipSuccess) return e;
+  return psms::launch_step_stage<T>(c->g.n, 3, c->variant[3], c->d_box, 0, 1, twiddles<T>(c), 0, c->stream);
 }
 
+// One time step: y-inverse, x stage with products, y-forward, z stage with the
+// update.  `ev` (optional) receives an event before each stage and after the last.
 template <typename T>
 hipError_t one_step(psms_ctx* c, hipEvent_t* ev = nullptr) {
-  const cpx<T>* tw = std::is_same<T, double>::value ? reinterpret_cast<const cpx<T>*>(c->tw64)
-                                                     : reinterpret_cast<const cpx<T>*>(c->tw32);
-  const BoxGeom& g = c->g;
-  const int n = g.n;
-  hipError_t e;
-  if (ev && (e = hipEventRecord(ev[0], c->stream)) != hipSuccess) return e;
-  // y-inverse: G [5][n][C][H] -> Y [6][n][n][H]; output 4 is i ky phi
-  psms::LineArgs ya{};
-  ya.n_in = g.C;
-  ya.n_out = n;
-  ya.inner = g.H;
-  ya.nlines = (long long)n * g.H;
-  ya.in_fstride = (long long)n * g.Q;
-  ya.out_fstride = (long long)n * n * g.H;
-  const unsigned fm[6] = {0, 1, 2, 3, 3, 4};
-  ya.fmap = 0;
-  for (int i = 0; i < 6; ++i) ya.fmap |= fm[i] << (4 * i);
-  ya.dmask = 1 << 4;
-  ya.scale = 1.0;
-  e = psms::launch_lines<T>(n, +1, static_cast<const cpx<T>*>(c->bufb), static_cast<cpx<T>*>(c->bufa), tw, ya, 6,
-                            c->stream);
+  hipError_t e = sync_box(c);
   if (e != hipSuccess) return e;
-  if (ev && (e = hipEventRecord(ev[1], c->stream)) != hipSuccess) return e;
-  // x stage with products: Y -> X [8][n][n][H]
-  const double csig = 3.0 / std::sqrt(8.0) * c->p.ch / c->p.we;
-  e = psms::launch_xstep<T>(n, static_cast<const cpx<T>*>(c->bufa), static_cast<cpx<T>*>(c->bufb), tw, csig,
-                            c->stream);
-  if (e != hipSuccess) return e;
-  if (ev && (e = hipEventRecord(ev[2], c->stream)) != hipSuccess) return e;
-  // y-forward with truncation: X -> W [8][n][C][H]
-  psms::LineArgs yf{};
-  yf.n_in = n;
-  yf.n_out = g.C;
-  yf.inner = g.H;
-  yf.nlines = (long long)n * g.H;
-  yf.in_fstride = (long long)n * n * g.H;
-  yf.out_fstride = (long long)n * g.Q;
-  yf.fmap = 0;
-  for (unsigned i = 0; i < 8; ++i) yf.fmap |= i << (4 * i);
-  yf.dmask = 0;
-  yf.scale = 1.0;
-  e = psms::launch_lines<T>(n, -1, static_cast<const cpx<T>*>(c->bufb), static_cast<cpx<T>*>(c->bufa), tw, yf, 8,
-                            c->stream);
-  if (e != hipSuccess) return e;
-  if (ev && (e = hipEventRecord(ev[3], c->stream)) != hipSuccess) return e;
-  // z-forward + update + z-inverse: W -> state, hist, G
-  psms::StepCoef sc = step_coef(c);
-  e = psms::launch_zstep<T>(n, static_cast<const cpx<T>*>(c->bufa), c->state, c->hist,
-                            static_cast<cpx<T>*>(c->bufb), tw, sc, 1, c->stream);
-  if (e != hipSuccess) return e;
+  for (int stage = 0; stage < 4; ++stage) {
+    if (ev && (e = hipEventRecord(ev[stage], c->stream)) != hipSuccess) return e;
+    e = psms::launch_step_stage<T>(c->g.n, stage, c->variant[stage], c->d_box, 0, 1, twiddles<T>(c), 1, c->stream);
+    if (e != hipSuccess) return e;
+  }
   if (ev) e = hipEventRecord(ev[4], c->stream);
   return e;
 }
@@ -334,6 +312,15 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
   c->tw32 = reinterpret_cast<cpx<float>*>(c->ws + lay.tw32);
   c->diag = reinterpret_cast<double*>(c->ws + lay.diag);
   c->diag_out = reinterpret_cast<double*>(c->ws + lay.diag_out);
+  c->d_box = reinterpret_cast<psms::BoxDev*>(c->ws + lay.box);
+  c->h_box.bufa = c->bufa;
+  c->h_box.bufb = c->bufb;
+  c->h_box.state = c->state;
+  c->h_box.hist = c->hist;
+  c->h_box.sc = step_coef(c);
+  c->h_box.csig = 3.0 / std::sqrt(8.0) * p->ch / p->we;
+  c->box_ab1 = -1;
+  for (int i = 0; i < 4; ++i) c->variant[i] = 2;
 
   // Twiddles exp(-2 pi i m / n) in FP64, rounded once to FP32 for MIXED.
   const int n = p->n;
@@ -655,6 +642,313 @@ int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* s
   PSMS_TRY(psms::launch_chebd(CM(a->d_w), C(L.dw), nc, nl, st));
   PSMS_TRY(psms::launch_uv(CM(a->d_om), C(L.dw), CM(a->d_u), CM(a->d_v), nc, nl, a->d_kx, a->d_ky, st));
 #undef PSMS_TRY
+  return PSMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent boxes
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct psms_batch {
+  struct Group {
+    int n;
+    std::vector<int> members;
+    psms::BoxDev* d_table;
+    std::vector<psms::BoxDev> h_table;
+    int variant[4];
+  };
+  int nbox;
+  int prec;
+  hipStream_t stream;
+  std::vector<psms_ctx*> box;
+  std::vector<Group> groups;
+  std::vector<int> table_ab1;  // per box, value last written (-1: never)
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int graph_valid;
+};
+
+namespace {
+
+struct BatchLayout {
+  std::vector<size_t> box_off;
+  std::vector<size_t> box_bytes;
+  size_t tables;
+  size_t total;
+};
+
+int batch_layout(int32_t nbox, const psms_params* p, BatchLayout* L) {
+  if (nbox < 1 || !p) return fail(PSMS_E_INVAL, "nbox must be >= 1 and params non-NULL");
+  size_t off = 0;
+  L->box_off.assign(nbox, 0);
+  L->box_bytes.assign(nbox, 0);
+  for (int i = 0; i < nbox; ++i) {
+    int r = validate(&p[i]);
+    if (r) return r;
+    if (p[i].precision != p[0].precision) return fail(PSMS_E_INVAL, "all boxes of a batch share one precision");
+    L->box_off[i] = off;
+    L->box_bytes[i] = make_layout(p[i]).total;
+    off = align256(off + L->box_bytes[i]);
+  }
+  L->tables = off;
+  off = align256(off + size_t(nbox) * sizeof(psms::BoxDev));
+  L->total = off;
+  return PSMS_OK;
+}
+
+void batch_drop_graph(psms_batch* b) {
+  if (b->graph_valid) {
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+    b->graph_valid = 0;
+  }
+}
+
+// Write each group's descriptor table where a box's Adams-Bashforth flag changed.
+hipError_t batch_sync_tables(psms_batch* b) {
+  for (auto& g : b->groups) {
+    bool dirty = false;
+    for (size_t j = 0; j < g.members.size(); ++j) {
+      psms_ctx* c = b->box[g.members[j]];
+      const int ab1 = (c->nstep == 0) ? 1 : 0;
+      if (b->table_ab1[g.members[j]] != ab1) {
+        g.h_table[j].sc = step_coef(c);
+        b->table_ab1[g.members[j]] = ab1;
+        dirty = true;
+      }
+    }
+    if (dirty) {
+      hipError_t e = hipMemcpyAsync(g.d_table, g.h_table.data(), g.h_table.size() * sizeof(psms::BoxDev),
+                                    hipMemcpyHostToDevice, b->stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t batch_stage(psms_batch* b, int stage, int do_update) {
+  for (auto& g : b->groups) {
+    const psms_ctx* c0 = b->box[g.members[0]];
+    hipError_t e = psms::launch_step_stage<T>(g.n, stage, g.variant[stage], g.d_table, 0, int(g.members.size()),
+                                              twiddles<T>(c0), do_update, b->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t batch_one_step(psms_batch* b) {
+  for (int stage = 0; stage < 4; ++stage) {
+    hipError_t e = batch_stage<T>(b, stage, 1);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int psms_batch_workspace_bytes(int32_t nbox, const psms_params* p, size_t* bytes) {
+  if (!bytes) return fail(PSMS_E_INVAL, "bytes is NULL");
+  BatchLayout L;
+  int r = batch_layout(nbox, p, &L);
+  if (r) return r;
+  *bytes = L.total;
+  return PSMS_OK;
+}
+
+int psms_batch_create(psms_batch** out, int32_t nbox, const psms_params* p, void* d_workspace, size_t bytes,
+                      void* stream) {
+  if (!out) return fail(PSMS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  BatchLayout L;
+  int r = batch_layout(nbox, p, &L);
+  if (r) return r;
+  if (!d_workspace || !aligned(d_workspace)) return fail(PSMS_E_WORKSPACE, "workspace NULL or misaligned");
+  if (bytes < L.total) return fail(PSMS_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+  psms_batch* b = new psms_batch();
+  b->nbox = nbox;
+  b->prec = p[0].precision;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->graph_valid = 0;
+  char* ws = static_cast<char*>(d_workspace);
+  for (int i = 0; i < nbox; ++i) {
+    psms_ctx* c = nullptr;
+    r = psms_create(&c, &p[i], ws + L.box_off[i], L.box_bytes[i], stream);
+    if (r) {
+      for (psms_ctx* q : b->box) psms_destroy(q);
+      delete b;
+      return r;
+    }
+    b->box.push_back(c);
+  }
+  b->table_ab1.assign(nbox, -1);
+  // group by size, tables laid out contiguously per group
+  std::vector<int> order(nbox);
+  for (int i = 0; i < nbox; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p[x].n < p[y].n; });
+  psms::BoxDev* table = reinterpret_cast<psms::BoxDev*>(ws + L.tables);
+  size_t used = 0;
+  for (int idx : order) {
+    if (b->groups.empty() || b->groups.back().n != p[idx].n) {
+      psms_batch::Group g;
+      g.n = p[idx].n;
+      g.d_table = table + used;
+      for (int s = 0; s < 4; ++s) g.variant[s] = 2;
+      b->groups.push_back(g);
+    }
+    psms_batch::Group& g = b->groups.back();
+    g.members.push_back(idx);
+    g.h_table.push_back(b->box[idx]->h_box);
+    ++used;
+  }
+  hipError_t e = batch_sync_tables(b);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    for (psms_ctx* q : b->box) psms_destroy(q);
+    delete b;
+    return hip_fail(e, "batch_create");
+  }
+  *out = b;
+  return PSMS_OK;
+}
+
+int psms_batch_destroy(psms_batch* b) {
+  if (!b) return PSMS_OK;
+  batch_drop_graph(b);
+  for (psms_ctx* c : b->box) psms_destroy(c);
+  delete b;
+  return PSMS_OK;
+}
+
+int psms_batch_init_state(psms_batch* b, int32_t box, const double* d_u, const double* d_phi) {
+  if (!b || box < 0 || box >= b->nbox) return fail(PSMS_E_INVAL, "bad batch or box index");
+  return psms_init_state(b->box[box], d_u, d_phi);
+}
+
+int psms_batch_get_state(psms_batch* b, int32_t box, double* d_uhat, double* d_phihat) {
+  if (!b || box < 0 || box >= b->nbox) return fail(PSMS_E_INVAL, "bad batch or box index");
+  return psms_get_state(b->box[box], d_uhat, d_phihat, nullptr);
+}
+
+int psms_batch_diagnostics(psms_batch* b, int32_t box, psms_diag* h_out) {
+  if (!b || box < 0 || box >= b->nbox) return fail(PSMS_E_INVAL, "bad batch or box index");
+  return psms_diagnostics(b->box[box], h_out);
+}
+
+int psms_batch_step(psms_batch* b, int32_t nsteps, int32_t use_graph) {
+  if (!b || nsteps < 0) return fail(PSMS_E_INVAL, "bad batch or nsteps");
+  bool need_prologue = false;
+  for (psms_ctx* c : b->box) {
+    if (!c->have_state) return fail(PSMS_E_STATE, "a box of the batch has no state");
+    if (!c->g_valid) need_prologue = true;
+  }
+  if (nsteps == 0) return PSMS_OK;
+  const bool mixed = b->prec == PSMS_MIXED;
+  hipError_t e = batch_sync_tables(b);
+  if (e == hipSuccess && need_prologue) e = mixed ? batch_stage<float>(b, 3, 0) : batch_stage<double>(b, 3, 0);
+  if (e != hipSuccess) return hip_fail(e, "batch prologue");
+  for (psms_ctx* c : b->box) c->g_valid = 1;
+  for (int s = 0; s < nsteps; ++s) {
+    e = batch_sync_tables(b);
+    bool any_ab1 = false;
+    for (psms_ctx* c : b->box) any_ab1 |= (c->nstep == 0);
+    const bool graph = use_graph && b->stream != nullptr && !any_ab1;
+    if (e == hipSuccess && graph && !b->graph_valid) {
+      e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t e2 = mixed ? batch_one_step<float>(b) : batch_one_step<double>(b);
+        e = hipStreamEndCapture(b->stream, &b->graph);
+        if (e2 != hipSuccess) e = e2;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e == hipSuccess) b->graph_valid = 1;
+    }
+    if (e == hipSuccess) {
+      if (graph) e = hipGraphLaunch(b->exec, b->stream);
+      else e = mixed ? batch_one_step<float>(b) : batch_one_step<double>(b);
+    }
+    if (e != hipSuccess) {
+      for (psms_ctx* c : b->box) c->g_valid = 0;
+      return hip_fail(e, "batch_step");
+    }
+    for (psms_ctx* c : b->box) c->nstep += 1;
+  }
+  return PSMS_OK;
+}
+
+int psms_batch_groups(const psms_batch* b, int32_t* h_ngroups, int32_t* h_n, int32_t* h_count) {
+  if (!b || !h_ngroups) return fail(PSMS_E_INVAL, "NULL argument");
+  *h_ngroups = int32_t(b->groups.size());
+  for (size_t i = 0; i < b->groups.size(); ++i) {
+    if (h_n) h_n[i] = b->groups[i].n;
+    if (h_count) h_count[i] = int32_t(b->groups[i].members.size());
+  }
+  return PSMS_OK;
+}
+
+int psms_batch_set_variants(psms_batch* b, const int32_t* h_variants) {
+  if (!b || !h_variants) return fail(PSMS_E_INVAL, "NULL argument");
+  for (size_t i = 0; i < 4 * b->groups.size(); ++i)
+    if (h_variants[i] < 0 || h_variants[i] >= psms::kStepVariants) return fail(PSMS_E_INVAL, "variant out of range");
+  for (size_t i = 0; i < b->groups.size(); ++i)
+    for (int s = 0; s < 4; ++s) b->groups[i].variant[s] = h_variants[4 * i + s];
+  batch_drop_graph(b);
+  return PSMS_OK;
+}
+
+int psms_batch_autotune(psms_batch* b, int32_t reps, int32_t* h_variants, double* h_ms) {
+  if (!b || reps < 1) return fail(PSMS_E_INVAL, "bad batch or reps");
+  for (psms_ctx* c : b->box)
+    if (c->have_state) return fail(PSMS_E_STATE, "autotune runs on an empty batch: call it before init_state");
+  const bool mixed = b->prec == PSMS_MIXED;
+  hipError_t e = hipSuccess;
+  // zero every box's workspace so the timed kernels see finite data
+  for (psms_ctx* c : b->box)
+    if (e == hipSuccess) e = hipMemsetAsync(c->state, 0, c->lay.tw64 - c->lay.state, b->stream);  // state..bufb
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = batch_sync_tables(b);
+  for (size_t gi = 0; e == hipSuccess && gi < b->groups.size(); ++gi) {
+    psms_batch::Group& g = b->groups[gi];
+    const psms_ctx* c0 = b->box[g.members[0]];
+    for (int stage = 0; e == hipSuccess && stage < 4; ++stage) {
+      double best = 1e300;
+      int arg = 2;
+      for (int v = 0; e == hipSuccess && v < psms::kStepVariants; ++v) {
+        auto run = [&]() {
+          return mixed ? psms::launch_step_stage<float>(g.n, stage, v, g.d_table, 0, int(g.members.size()),
+                                                        twiddles<float>(c0), 1, b->stream)
+                       : psms::launch_step_stage<double>(g.n, stage, v, g.d_table, 0, int(g.members.size()),
+                                                         twiddles<double>(c0), 1, b->stream);
+        };
+        e = run();  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int r = 0; e == hipSuccess && r < reps; ++r) e = run();
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double avg = double(ms) / reps;
+        if (h_ms) h_ms[(gi * 4 + stage) * psms::kStepVariants + v] = avg;
+        if (avg < best) {
+          best = avg;
+          arg = v;
+        }
+      }
+      g.variant[stage] = arg;
+      if (h_variants) h_variants[gi * 4 + stage] = arg;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  batch_drop_graph(b);
+  for (psms_ctx* c : b->box) c->g_valid = 0;
+  if (e != hipSuccess) return hip_fail(e, "batch_autotune");
   return PSMS_OK;
 }
 

@@ -2,10 +2,10 @@
 //
 // The step of Sec. 2.2 (steps ii-v) is executed as four kernels per time step,
 // all on the caller's stream:
-//   k_lines<+1>  y-inverse of u, v, w, phi, d_z phi, plus i k_y phi
+//   k_ystep<+1>  y-inverse of u, v, w, phi, d_z phi, plus i k_y phi
 //   k_xstep      x-inverse (7 fields), the pointwise products (Sec. 3.2.2,
 //                Hadamard products) and the x-forward of the 8 products
-//   k_lines<-1>  y-forward with 2/3 truncation
+//   k_ystep<-1>  y-forward with 2/3 truncation
 //   k_zstep      z-forward, spectral RHS assembly, Leray projection, CN/AB2
 //                (NS) and IE/AB2 (CH) updates, then the z-inverse of the new
 //                state for the next step.
@@ -20,7 +20,9 @@
 //   W (y-forward)  : [8][N z][C ky][H kx]
 //
 // Every kernel is instantiated per transform length N (compile time) so that
-// all index arithmetic folds to constants.
+// all index arithmetic folds to constants.  The step kernels read their
+// pointers and coefficients from a device table of boxes (BoxDev) indexed by
+// blockIdx.z, so one launch advances every box of a given size.
 #include <hip/hip_runtime.h>
 
 #include "box_kernels.hpp"
@@ -31,11 +33,15 @@ namespace psms {
 template <typename T>
 __device__ __forceinline__ cpx<T> to_cpx(cpx<double> v) { return {T(v.re), T(v.im)}; }
 
-template <int N>
+// Tiling of a batch of lines of length N: E values per thread, TT threads per
+// line, L lines per workgroup of THREADS = 64 << V threads (V is the
+// workgroup-size variant the autotuner chooses between; V = 2 is 256).
+template <int N, int V = 2>
 struct Tile {
   static constexpr int E = Plan<N>::E;
-  static constexpr int TT = N / E;                    // threads per line
-  static constexpr int L = (256 / TT) > 0 ? 256 / TT : 1;  // lines per workgroup
+  static constexpr int TT = N / E;
+  static constexpr int THREADS = 64 << V;
+  static constexpr int L = (THREADS / TT) > 0 ? THREADS / TT : 1;
   static constexpr int K = (N - 1) / 3;
   static constexpr int C = 2 * K + 1;
   static constexpr int H = K + 1;
@@ -48,10 +54,10 @@ struct Tile {
 // n_in slots, zero-padded).  Output field f reads input field (fmap >> 4f)&15;
 // bit f of dmask multiplies by i k along the axis.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int S>
-__global__ void __launch_bounds__(256) k_lines(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
-                                               const cpx<T>* __restrict__ tw_g, LineArgs a) {
-  using G = Tile<N>;
+template <typename T, int N, int S, int V>
+__device__ __forceinline__ void lines_body(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                           const cpx<T>* __restrict__ tw_g, const LineArgs& a, bool deriv) {
+  using G = Tile<N, V>;
   constexpr int E = G::E, L = G::L, LP = L + 1;
   constexpr int RI = first_radix<N, S>(), RO = last_radix<N, S>();
   __shared__ cpx<T> tw[N];
@@ -59,11 +65,6 @@ __global__ void __launch_bounds__(256) k_lines(const cpx<T>* __restrict__ in, cp
   const int tid = threadIdx.x;
   const int line = tid % L, t = tid / L;
   for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
-
-  const int fo = blockIdx.y;
-  const cpx<T>* src = in + (long long)((a.fmap >> (4 * fo)) & 15) * a.in_fstride;
-  cpx<T>* dst = out + (long long)fo * a.out_fstride;
-  const bool deriv = (a.dmask >> fo) & 1;
   const long long gl = (long long)blockIdx.x * L + line;
   const bool valid = gl < a.nlines;
   const long long o = valid ? gl / a.inner : 0, i = valid ? gl % a.inner : 0;
@@ -105,6 +106,42 @@ __global__ void __launch_bounds__(256) k_lines(const cpx<T>* __restrict__ in, cp
         dst[(o * a.n_out + s) * a.inner + i] = cpx<T>{sc * x.re, sc * x.im};
       }
     }
+  }
+}
+
+template <typename T, int N, int S>
+__global__ void __launch_bounds__(256) k_lines(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                               const cpx<T>* __restrict__ tw_g, LineArgs a) {
+  const int fo = blockIdx.y;
+  lines_body<T, N, S, 2>(in + (long long)((a.fmap >> (4 * fo)) & 15) * a.in_fstride,
+                         out + (long long)fo * a.out_fstride, tw_g, a, (a.dmask >> fo) & 1);
+}
+
+// y stages of the step for box box0 + blockIdx.z.
+//   S = +1: G [5][N][C][H] (bufb) -> Y [6][N][N][H] (bufa); output 4 is i ky phi.
+//   S = -1: X [8][N][N][H] (bufb) -> W [8][N][C][H] (bufa), truncated to the band.
+template <typename T, int N, int S, int V>
+__global__ void __launch_bounds__(64 << V) k_ystep(const BoxDev* __restrict__ boxes, int box0,
+                                                   const cpx<T>* __restrict__ tw_g) {
+  using G = Tile<N, V>;
+  const BoxDev& bx = boxes[box0 + blockIdx.z];
+  const int fo = blockIdx.y;
+  LineArgs a;
+  a.inner = G::H;
+  a.nlines = (long long)N * G::H;
+  a.scale = 1.0;
+  const long long nq = (long long)N * G::C * G::H, nnh = (long long)N * N * G::H;
+  if (S > 0) {
+    a.n_in = G::C;
+    a.n_out = N;
+    const int fin = (fo <= 3) ? fo : fo - 1;
+    lines_body<T, N, S, V>(static_cast<const cpx<T>*>(bx.bufb) + fin * nq, static_cast<cpx<T>*>(bx.bufa) + fo * nnh,
+                           tw_g, a, fo == 4);
+  } else {
+    a.n_in = N;
+    a.n_out = G::C;
+    lines_body<T, N, S, V>(static_cast<const cpx<T>*>(bx.bufb) + fo * nnh, static_cast<cpx<T>*>(bx.bufa) + fo * nq,
+                           tw_g, a, false);
   }
 }
 
@@ -209,10 +246,14 @@ __global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in,
 // the positions the inverse leaves them, which are the positions the forward
 // transform starts from, so the products need no data exchange.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(256) k_xstep(const cpx<T>* __restrict__ yin, cpx<T>* __restrict__ xout,
-                                               const cpx<T>* __restrict__ tw_g, double csig_d) {
-  using G = Tile<N>;
+template <typename T, int N, int V>
+__global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ boxes, int box0,
+                                                   const cpx<T>* __restrict__ tw_g) {
+  using G = Tile<N, V>;
+  const BoxDev& bx = boxes[box0 + blockIdx.z];
+  const cpx<T>* __restrict__ yin = static_cast<const cpx<T>*>(bx.bufa);
+  cpx<T>* __restrict__ xout = static_cast<cpx<T>*>(bx.bufb);
+  const double csig_d = bx.csig;
   constexpr int E = G::E, TT = G::TT, L = G::L, LP = N + 1, K = G::K, H = G::H;
   constexpr int RI = first_radix<N, 1>();   // inverse starts with R[NST-1]
   constexpr int RP = last_radix<N, 1>();    // inverse ends / forward starts with R[0]
@@ -323,11 +364,16 @@ __global__ void __launch_bounds__(256) k_xstep(const cpx<T>* __restrict__ yin, c
 // the inputs its inverse transform starts from.
 // do_update = 0 only loads the state and performs the z-inverse (prologue).
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(256) k_zstep(const cpx<T>* __restrict__ rhs, cpx<double>* __restrict__ state,
-                                               cpx<double>* __restrict__ hist, cpx<T>* __restrict__ gout,
-                                               const cpx<T>* __restrict__ tw_g, StepCoef sc, int do_update) {
-  using G = Tile<N>;
+template <typename T, int N, int V>
+__global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ boxes, int box0,
+                                                   const cpx<T>* __restrict__ tw_g, int do_update) {
+  using G = Tile<N, V>;
+  const BoxDev& bx = boxes[box0 + blockIdx.z];
+  const cpx<T>* __restrict__ rhs = static_cast<const cpx<T>*>(bx.bufa);
+  cpx<double>* __restrict__ state = bx.state;
+  cpx<double>* __restrict__ hist = bx.hist;
+  cpx<T>* __restrict__ gout = static_cast<cpx<T>*>(bx.bufb);
+  const StepCoef sc = bx.sc;
   constexpr int E = G::E, L = G::L, LP = L + 1, K = G::K, C = G::C, H = G::H;
   constexpr int Q = C * H;
   constexpr long long M = (long long)C * Q;
@@ -743,22 +789,46 @@ hipError_t rows_n(int dir, const void* in, void* out, const cpx<T>* tw, const Ro
   return hipGetLastError();
 }
 
-template <typename T, int N>
-hipError_t xstep_n(const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, double csig, hipStream_t st) {
-  using G = Tile<N>;
-  const long long pairs = (long long)N * N / 2;
-  k_xstep<T, N><<<unsigned((pairs + G::L - 1) / G::L), unsigned(G::L * G::TT), 0, st>>>(yin, xout, tw, csig);
+template <typename T, int N, int V>
+hipError_t step_nv(int stage, const BoxDev* boxes, int box0, int nbox, const cpx<T>* tw, int do_update,
+                   hipStream_t st) {
+  using G = Tile<N, V>;
+  const unsigned threads = unsigned(G::L * G::TT);
+  switch (stage) {
+    case 0: {  // y-inverse, 6 output fields
+      const dim3 grid(unsigned(((long long)N * G::H + G::L - 1) / G::L), 6, unsigned(nbox));
+      k_ystep<T, N, 1, V><<<grid, threads, 0, st>>>(boxes, box0, tw);
+      break;
+    }
+    case 1: {  // x stage with products
+      const long long pairs = (long long)N * N / 2;
+      const dim3 grid(unsigned((pairs + G::L - 1) / G::L), 1, unsigned(nbox));
+      k_xstep<T, N, V><<<grid, threads, 0, st>>>(boxes, box0, tw);
+      break;
+    }
+    case 2: {  // y-forward, 8 fields
+      const dim3 grid(unsigned(((long long)N * G::H + G::L - 1) / G::L), 8, unsigned(nbox));
+      k_ystep<T, N, -1, V><<<grid, threads, 0, st>>>(boxes, box0, tw);
+      break;
+    }
+    default: {  // z stage with the update
+      const int Q = G::C * G::H;
+      const dim3 grid(unsigned((Q + G::L - 1) / G::L), 1, unsigned(nbox));
+      k_zstep<T, N, V><<<grid, threads, 0, st>>>(boxes, box0, tw, do_update);
+      break;
+    }
+  }
   return hipGetLastError();
 }
 
 template <typename T, int N>
-hipError_t zstep_n(const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout, const cpx<T>* tw,
-                   const StepCoef& sc, int do_update, hipStream_t st) {
-  using G = Tile<N>;
-  const int Q = G::C * G::H;
-  k_zstep<T, N><<<unsigned((Q + G::L - 1) / G::L), unsigned(G::L * G::TT), 0, st>>>(rhs, state, hist, gout, tw, sc,
-                                                                                    do_update);
-  return hipGetLastError();
+hipError_t step_n(int stage, int variant, const BoxDev* boxes, int box0, int nbox, const cpx<T>* tw, int do_update,
+                  hipStream_t st) {
+  switch (variant) {
+    case 0: return step_nv<T, N, 0>(stage, boxes, box0, nbox, tw, do_update, st);
+    case 1: return step_nv<T, N, 1>(stage, boxes, box0, nbox, tw, do_update, st);
+    default: return step_nv<T, N, 2>(stage, boxes, box0, nbox, tw, do_update, st);
+  }
 }
 
 }  // namespace
@@ -786,20 +856,11 @@ hipError_t launch_rows(int n, int dir, const void* in, void* out, const cpx<T>* 
 }
 
 template <typename T>
-hipError_t launch_xstep(int n, const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, double csig, hipStream_t st) {
+hipError_t launch_step_stage(int n, int stage, int variant, const BoxDev* boxes, int box0, int nbox,
+                             const cpx<T>* tw, int do_update, hipStream_t st) {
+  if (nbox < 1) return hipSuccess;
   switch (n) {
-#define PSMS_CASE(NN) case NN: return xstep_n<T, NN>(yin, xout, tw, csig, st);
-    PSMS_FOR_EACH_N(PSMS_CASE)
-#undef PSMS_CASE
-  }
-  return hipErrorInvalidValue;
-}
-
-template <typename T>
-hipError_t launch_zstep(int n, const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout,
-                        const cpx<T>* tw, const StepCoef& sc, int do_update, hipStream_t st) {
-  switch (n) {
-#define PSMS_CASE(NN) case NN: return zstep_n<T, NN>(rhs, state, hist, gout, tw, sc, do_update, st);
+#define PSMS_CASE(NN) case NN: return step_n<T, NN>(stage, variant, boxes, box0, nbox, tw, do_update, st);
     PSMS_FOR_EACH_N(PSMS_CASE)
 #undef PSMS_CASE
   }
@@ -862,14 +923,10 @@ template hipError_t launch_rows<double>(int, int, const void*, void*, const cpx<
                                         hipStream_t);
 template hipError_t launch_rows<float>(int, int, const void*, void*, const cpx<float>*, const RowArgs&, int,
                                        hipStream_t);
-template hipError_t launch_xstep<double>(int, const cpx<double>*, cpx<double>*, const cpx<double>*, double,
-                                         hipStream_t);
-template hipError_t launch_xstep<float>(int, const cpx<float>*, cpx<float>*, const cpx<float>*, double,
-                                        hipStream_t);
-template hipError_t launch_zstep<double>(int, const cpx<double>*, cpx<double>*, cpx<double>*, cpx<double>*,
-                                         const cpx<double>*, const StepCoef&, int, hipStream_t);
-template hipError_t launch_zstep<float>(int, const cpx<float>*, cpx<double>*, cpx<double>*, cpx<float>*,
-                                        const cpx<float>*, const StepCoef&, int, hipStream_t);
+template hipError_t launch_step_stage<double>(int, int, int, const BoxDev*, int, int, const cpx<double>*, int,
+                                              hipStream_t);
+template hipError_t launch_step_stage<float>(int, int, int, const BoxDev*, int, int, const cpx<float>*, int,
+                                             hipStream_t);
 template hipError_t launch_expand<double>(const cpx<double>*, cpx<double>*, const BoxGeom&, int, hipStream_t);
 template hipError_t launch_compact<double>(const cpx<double>*, cpx<double>*, const BoxGeom&, int, hipStream_t);
 template hipError_t launch_spec_finish<double>(const cpx<double>*, cpx<double>*, const BoxGeom&, int, int, int,

@@ -27,6 +27,17 @@ struct StepCoef {
   int ab1;         // 1: Adams-Bashforth order 1 (first step)
 };
 
+// Per-box device descriptor read by the step kernels (box = table[box0 + blockIdx.z]).
+// bufa / bufb hold the step's intermediates (G and X in bufb, Y and W in bufa).
+struct BoxDev {
+  void* bufa;
+  void* bufb;
+  cpx<double>* state;
+  cpx<double>* hist;
+  StepCoef sc;
+  double csig;     // (3 / sqrt 8) Ch / We
+};
+
 // Batched transform along a strided axis: line l = o * inner + i holds
 // element a at ((o * cnt + a) * inner + i), cnt = n_in on input, n_out on
 // output (n: the full axis, 2K+1: the retained band).
@@ -56,11 +67,14 @@ hipError_t launch_lines(int n, int dir, const cpx<T>* in, cpx<T>* out, const cpx
 template <typename T>
 hipError_t launch_rows(int n, int dir, const void* in, void* out, const cpx<T>* tw, const RowArgs& a, int nfield,
                        hipStream_t st);
+// One stage of the step for boxes table[box0 .. box0+nbox-1], all of size n:
+// stage 0 y-inverse, 1 x stage with products, 2 y-forward, 3 z stage with the
+// update (do_update = 0: z-inverse of the state only).  variant selects the
+// workgroup size 64 << variant.
+constexpr int kStepVariants = 3;
 template <typename T>
-hipError_t launch_xstep(int n, const cpx<T>* yin, cpx<T>* xout, const cpx<T>* tw, double csig, hipStream_t st);
-template <typename T>
-hipError_t launch_zstep(int n, const cpx<T>* rhs, cpx<double>* state, cpx<double>* hist, cpx<T>* gout,
-                        const cpx<T>* tw, const StepCoef& sc, int do_update, hipStream_t st);
+hipError_t launch_step_stage(int n, int stage, int variant, const BoxDev* table, int box0, int nbox,
+                             const cpx<T>* tw, int do_update, hipStream_t st);
 template <typename T>
 hipError_t launch_expand(const cpx<T>* cmp, cpx<T>* full, const BoxGeom& g, int nf, hipStream_t st);
 template <typename T>

@@ -81,6 +81,20 @@ _SIGS = {
     "psms_wall_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "psms_wall_solve": (ctypes.c_int, [ctypes.POINTER(WallArgs), ctypes.c_void_p, ctypes.c_size_t,
                                        ctypes.c_void_p]),
+    "psms_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Params),
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "psms_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.POINTER(Params),
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "psms_batch_init_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "psms_batch_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "psms_batch_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Diag)]),
+    "psms_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "psms_batch_groups": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "psms_batch_set_variants": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "psms_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "psms_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "psms_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "psms_last_error": (ctypes.c_char_p, []),
     "psms_version": (ctypes.c_char_p, []),
@@ -324,3 +338,120 @@ def wall_solve(kx, ky, beta_ns, beta_a, beta_b, g_om, g_w, g_phi):
                  outs["phi"].data_ptr(), outs["u"].data_ptr(), outs["v"].data_ptr())
     _check(lib().psms_wall_solve(ctypes.byref(a), _ptr(work), int(nbytes.value), _stream()))
     return outs
+
+
+# ---------------------------------------------------------------------------
+# batches of independent boxes
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Many independent periodic boxes of uneven size stepped together.
+
+    params: list of dicts with n, re, we, ch, pe, dt (and optionally s).  All
+    boxes share `precision`.  The batch runs on `stream` (default: a new
+    torch stream, which graph capture needs; use it with torch.cuda.stream).
+    """
+
+    def __init__(self, params, precision="mixed", device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = precision
+        self.nbox = len(params)
+        arr = (Params * self.nbox)(*[make_params(q["n"], q["re"], q["we"], q["ch"], q["pe"], q["dt"],
+                                                 q.get("s", 0.0), precision) for q in params])
+        self._params = arr
+        self.ns = [int(q["n"]) for q in params]
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().psms_batch_workspace_bytes(self.nbox, arr, ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        h = ctypes.c_void_p()
+        _check(lib().psms_batch_create(ctypes.byref(h), self.nbox, arr, _ptr(self.workspace), int(nbytes.value),
+                                       ctypes.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().psms_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _on_stream(self, t):
+        # make the batch stream wait for work queued on the caller's stream
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        return t
+
+    def init_state(self, box, u, phi):
+        n = self.ns[box]
+        u = u.to(self.device, self.torch.float64).contiguous()
+        phi = phi.to(self.device, self.torch.float64).contiguous()
+        assert tuple(u.shape) == (3, n, n, n) and tuple(phi.shape) == (n, n, n)
+        self._on_stream(u)
+        _check(lib().psms_batch_init_state(self.h, int(box), _ptr(u), _ptr(phi)))
+        self.stream.synchronize()
+
+    def step(self, nsteps=1, use_graph=True):
+        _check(lib().psms_batch_step(self.h, int(nsteps), 1 if use_graph else 0))
+
+    def get_state(self, box):
+        torch = self.torch
+        n = self.ns[box]
+        uh = torch.empty((3, n, n, n // 2 + 1), dtype=torch.complex128, device=self.device)
+        ph = torch.empty((n, n, n // 2 + 1), dtype=torch.complex128, device=self.device)
+        self._on_stream(uh)
+        _check(lib().psms_batch_get_state(self.h, int(box), _ptr(uh), _ptr(ph)))
+        self.stream.synchronize()
+        return uh, ph
+
+    def diagnostics(self, box):
+        d = Diag()
+        _check(lib().psms_batch_diagnostics(self.h, int(box), ctypes.byref(d)))
+        return dict(mean_phi=d.mean_phi, ke=d.ke, grad2=d.grad2, max_div=d.max_div,
+                    nonfinite=int(d.nonfinite), nstep=int(d.nstep))
+
+    def groups(self):
+        ng = ctypes.c_int32(0)
+        _check(lib().psms_batch_groups(self.h, ctypes.byref(ng), None, None))
+        ns = (ctypes.c_int32 * ng.value)()
+        cnt = (ctypes.c_int32 * ng.value)()
+        _check(lib().psms_batch_groups(self.h, ctypes.byref(ng), ns, cnt))
+        return [(int(ns[i]), int(cnt[i])) for i in range(ng.value)]
+
+    def set_variants(self, variants):
+        arr = (ctypes.c_int32 * len(variants))(*variants)
+        _check(lib().psms_batch_set_variants(self.h, arr))
+
+    def autotune(self, reps=5, cache_path=None):
+        """Pick the workgroup-size variant of every stage of every group by timing (HIP
+        events), or reuse the choices stored in the JSON file `cache_path`.  Keys are
+        "<precision>/N<n>x<count>"; values are the 4 per-stage variants."""
+        import json
+        groups = self.groups()
+        keys = ["%s/N%dx%d" % (self.precision, n, c) for n, c in groups]
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        if all(k in cache for k in keys):
+            flat = [v for k in keys for v in cache[k]]
+            self.set_variants(flat)
+            return {"source": "cache", "variants": dict(zip(keys, [cache[k] for k in keys]))}
+        var = (ctypes.c_int32 * (4 * len(groups)))()
+        ms = (ctypes.c_double * (12 * len(groups)))()
+        _check(lib().psms_batch_autotune(self.h, int(reps), var, ms))
+        res = {}
+        for i, k in enumerate(keys):
+            cache[k] = [int(var[4 * i + s]) for s in range(4)]
+            res[k] = {"variants": cache[k], "ms": [[float(ms[(4 * i + s) * 3 + v]) for v in range(3)]
+                                                  for s in range(4)]}
+        if cache_path:
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        return {"source": "timed", "groups": res}

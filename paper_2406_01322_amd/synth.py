@@ -153,3 +153,24 @@ def box_case(name: str):
     c = drop_centres(rng, nd, r, ch)
     phi = drops_phi(n, c, r, ch)
     return p, u, phi
+
+
+def batch_cases(nbox: int = 96, seed: int = 4, sizes=(32, 48, 64, 96)):
+    """Independent boxes of uneven size: per box, drawn in this order, N from
+    `sizes`, the number of drops in [1, 8], Re ~ U[50, 400], We ~ U[0.5, 5];
+    Ch = 0.05, drop radius 0.4, Pe = 1/Ch, dt = 1e-3, k0 = 4.
+    Returns a list of (params, u, phi)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nbox):
+        n = int(rng.choice(sizes))
+        nd = int(rng.integers(1, 9))
+        re = float(rng.uniform(50.0, 400.0))
+        we = float(rng.uniform(0.5, 5.0))
+        ch = 0.05
+        p = dict(n=n, re=re, we=we, ch=ch, pe=1.0 / ch, dt=1e-3)
+        u = random_velocity(n, rng, k0=4.0)
+        c = drop_centres(rng, nd, 0.4, ch)
+        phi = drops_phi(n, c, 0.4, ch)
+        out.append((p, u, phi))
+    return out
