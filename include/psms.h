@@ -267,6 +267,32 @@ int psms_batch_set_variants(psms_batch* b, const int32_t* h_variants);
 int psms_batch_autotune(psms_batch* b, int32_t reps, int32_t* h_variants, double* h_ms);
 int psms_batch_destroy(psms_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint (discretise-then-differentiate) of the box step, for the
+ * objective J = int |grad phi|^2 dV + 1/2 int |u|^2 dV at the final step:
+ * gradients with respect to the initial phase field (a grid array) and the
+ * Weber number (eq. We).  The primal run (precision of p) stores the FP64
+ * state and history every seg_len steps; the backward sweep recomputes each
+ * segment in FP64 and applies the transposed step
+ *   Sbar = alpha B lam + mu, mu <- beta B lam, lam <- A lam + (dR/dx)^T Sbar,
+ *   dJ/dWe += (dR/dWe)^T Sbar
+ * (A, B the per-mode implicit factors, alpha, beta the Adams-Bashforth
+ * weights, R the projected nonlinear terms) under the half-spectrum inner
+ * product sum_k w_k Re(conj a_k b_k), w = 1 at kx = 0 and 2 otherwise.
+ * ------------------------------------------------------------------------- */
+typedef struct psms_adjoint psms_adjoint;
+
+int psms_adjoint_workspace_bytes(const psms_params* p, int32_t max_steps, int32_t seg_len, size_t* bytes);
+int psms_adjoint_create(psms_adjoint** out, const psms_params* p, int32_t max_steps, int32_t seg_len,
+                        void* d_workspace, size_t bytes, void* stream);
+/* Primal run from the physical fields d_u [3][n][n][n], d_phi [n][n][n]
+ * (double) for nsteps <= max_steps; writes J to *h_J (synchronises). */
+int psms_adjoint_forward(psms_adjoint* a, const double* d_u0, const double* d_phi0, int32_t nsteps, double* h_J);
+/* Backward sweep of the last forward run: d_dphi0 [n][n][n] receives dJ/dphi0
+ * on the grid, *h_dwe dJ/dWe (synchronises). */
+int psms_adjoint_backward(psms_adjoint* a, double* d_dphi0, double* h_dwe);
+int psms_adjoint_destroy(psms_adjoint* a);
+
 /* Number of retained modes per field, (2K+1)^2 (K+1). */
 int64_t psms_band_modes(const psms_ctx* c);
 

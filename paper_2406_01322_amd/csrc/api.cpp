@@ -12,6 +12,7 @@
 #include "../../include/psms.h"
 #include "box_kernels.hpp"
 #include "channel_kernels.hpp"
+#include "adjoint_kernels.hpp"
 
 using psms::BoxGeom;
 using psms::cpx;
@@ -333,6 +334,7 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
   }
   hipError_t e = hipMemcpyAsync(c->tw64, t64.data(), n * sizeof(cpx<double>), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->tw32, t32.data(), n * sizeof(cpx<float>), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = sync_box(c);  // the device descriptor is valid from creation on
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;
@@ -949,6 +951,228 @@ int psms_batch_autotune(psms_batch* b, int32_t reps, int32_t* h_variants, double
   batch_drop_graph(b);
   for (psms_ctx* c : b->box) c->g_valid = 0;
   if (e != hipSuccess) return hip_fail(e, "batch_autotune");
+  return PSMS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// discrete adjoint with segment checkpointing
+// ---------------------------------------------------------------------------
+struct psms_adjoint {
+  psms_params p;
+  int max_steps, seg_len, nckpt;
+  hipStream_t stream;
+  psms_ctx* prim;  // primal run, in the requested precision
+  psms_ctx* rec;   // FP64 recompute inside a segment
+  cpx<double>* lam;
+  cpx<double>* mu;
+  cpx<double>* seg;    // seg_len states (4 M each)
+  cpx<double>* ckpt;   // nckpt (state, history) pairs (8 M each)
+  cpx<double>* adja;   // [8][n][C][H]
+  cpx<double>* adjb;   // [8][n][n][H]
+  double* part;
+  double* acc;         // dJ/dWe accumulator
+  int nsteps;          // steps of the last forward run (-1: none)
+};
+
+namespace {
+struct AdjLayout {
+  size_t prim, prim_bytes, rec, rec_bytes, lam, mu, seg, ckpt, adja, adjb, part, acc, total;
+  int nckpt;
+};
+int adjoint_layout(const psms_params* p, int32_t max_steps, int32_t seg_len, AdjLayout* L) {
+  int r = validate(p);
+  if (r) return r;
+  if (max_steps < 1 || seg_len < 1) return fail(PSMS_E_INVAL, "max_steps and seg_len must be >= 1");
+  psms_params p64 = *p;
+  p64.precision = PSMS_FP64;
+  const BoxGeom g = make_geom(p->n);
+  const size_t n = size_t(p->n);
+  const size_t st = 4 * size_t(g.M) * sizeof(cpx<double>);
+  size_t off = 0;
+  L->prim = off; L->prim_bytes = make_layout(*p).total; off = align256(off + L->prim_bytes);
+  L->rec = off; L->rec_bytes = make_layout(p64).total; off = align256(off + L->rec_bytes);
+  L->lam = off; off = align256(off + st);
+  L->mu = off; off = align256(off + st);
+  L->seg = off; off = align256(off + size_t(seg_len) * st);
+  L->nckpt = (max_steps + seg_len - 1) / seg_len;
+  L->ckpt = off; off = align256(off + size_t(L->nckpt) * 2 * st);
+  L->adja = off; off = align256(off + 8 * n * size_t(g.Q) * sizeof(cpx<double>));
+  L->adjb = off; off = align256(off + std::max(8 * n * n * size_t(g.H), n * n * (n / 2 + 1)) * sizeof(cpx<double>));
+  L->part = off; off = align256(off + size_t(psms::adj_xblocks(p->n)) * sizeof(double));
+  L->acc = off; off = align256(off + 8 * sizeof(double));
+  L->total = off;
+  return PSMS_OK;
+}
+
+// y-direction transform of nf fields between band (C) and full (n) layouts, FP64.
+hipError_t y_lines64(psms_ctx* c, int dir, const cpx<double>* in, cpx<double>* out, int nf) {
+  const BoxGeom& g = c->g;
+  const int n = g.n;
+  psms::LineArgs la{};
+  la.n_in = dir > 0 ? g.C : n;
+  la.n_out = dir > 0 ? n : g.C;
+  la.inner = g.H;
+  la.nlines = (long long)n * g.H;
+  la.in_fstride = dir > 0 ? (long long)n * g.Q : (long long)n * n * g.H;
+  la.out_fstride = dir > 0 ? (long long)n * n * g.H : (long long)n * g.Q;
+  la.fmap = 0;
+  for (unsigned i = 0; i < 8; ++i) la.fmap |= i << (4 * i);
+  la.scale = 1.0;
+  return psms::launch_lines<double>(n, dir, in, out, c->tw64, la, nf, c->stream);
+}
+}  // namespace
+
+extern "C" {
+
+int psms_adjoint_workspace_bytes(const psms_params* p, int32_t max_steps, int32_t seg_len, size_t* bytes) {
+  if (!bytes) return fail(PSMS_E_INVAL, "bytes is NULL");
+  AdjLayout L;
+  int r = adjoint_layout(p, max_steps, seg_len, &L);
+  if (r) return r;
+  *bytes = L.total;
+  return PSMS_OK;
+}
+
+int psms_adjoint_create(psms_adjoint** out, const psms_params* p, int32_t max_steps, int32_t seg_len,
+                        void* d_workspace, size_t bytes, void* stream) {
+  if (!out) return fail(PSMS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  AdjLayout L;
+  int r = adjoint_layout(p, max_steps, seg_len, &L);
+  if (r) return r;
+  if (!d_workspace || !aligned(d_workspace)) return fail(PSMS_E_WORKSPACE, "workspace NULL or misaligned");
+  if (bytes < L.total) return fail(PSMS_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+  char* ws = static_cast<char*>(d_workspace);
+  psms_adjoint* a = new psms_adjoint();
+  a->p = *p;
+  a->max_steps = max_steps;
+  a->seg_len = seg_len;
+  a->nckpt = L.nckpt;
+  a->stream = static_cast<hipStream_t>(stream);
+  psms_params p64 = *p;
+  p64.precision = PSMS_FP64;
+  r = psms_create(&a->prim, p, ws + L.prim, L.prim_bytes, stream);
+  if (!r) r = psms_create(&a->rec, &p64, ws + L.rec, L.rec_bytes, stream);
+  if (r) {
+    psms_destroy(a->prim);
+    delete a;
+    return r;
+  }
+  a->lam = reinterpret_cast<cpx<double>*>(ws + L.lam);
+  a->mu = reinterpret_cast<cpx<double>*>(ws + L.mu);
+  a->seg = reinterpret_cast<cpx<double>*>(ws + L.seg);
+  a->ckpt = reinterpret_cast<cpx<double>*>(ws + L.ckpt);
+  a->adja = reinterpret_cast<cpx<double>*>(ws + L.adja);
+  a->adjb = reinterpret_cast<cpx<double>*>(ws + L.adjb);
+  a->part = reinterpret_cast<double*>(ws + L.part);
+  a->acc = reinterpret_cast<double*>(ws + L.acc);
+  a->nsteps = -1;
+  *out = a;
+  return PSMS_OK;
+}
+
+int psms_adjoint_destroy(psms_adjoint* a) {
+  if (!a) return PSMS_OK;
+  psms_destroy(a->prim);
+  psms_destroy(a->rec);
+  delete a;
+  return PSMS_OK;
+}
+
+int psms_adjoint_forward(psms_adjoint* a, const double* d_u0, const double* d_phi0, int32_t nsteps, double* h_J) {
+  if (!a || !d_u0 || !d_phi0 || !h_J) return fail(PSMS_E_INVAL, "NULL argument");
+  if (nsteps < 1 || nsteps > a->max_steps) return fail(PSMS_E_INVAL, "nsteps must be in 1..max_steps");
+  int r = psms_init_state(a->prim, d_u0, d_phi0);
+  if (r) return r;
+  psms_ctx* c = a->prim;
+  const size_t st = 4 * size_t(c->g.M) * sizeof(cpx<double>);
+  const long long M4 = 4 * c->g.M;
+  for (int s = 0; s * a->seg_len < nsteps; ++s) {
+    hipError_t e = hipMemcpyAsync(a->ckpt + 2 * s * M4, c->state, st, hipMemcpyDeviceToDevice, a->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(a->ckpt + (2 * s + 1) * M4, c->hist, st, hipMemcpyDeviceToDevice, a->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint checkpoint");
+    const int k = std::min(a->seg_len, nsteps - s * a->seg_len);
+    r = psms_step(c, k);
+    if (r) return r;
+  }
+  psms_diag d;
+  r = psms_diagnostics(c, &d);
+  if (r) return r;
+  if (d.nonfinite) return fail(PSMS_E_NONFINITE, "non-finite state in the forward run");
+  const double vol = 8.0 * M_PI * M_PI * M_PI;
+  *h_J = vol * (d.grad2 + d.ke);
+  a->nsteps = nsteps;
+  return PSMS_OK;
+}
+
+int psms_adjoint_backward(psms_adjoint* a, double* d_dphi0, double* h_dwe) {
+  if (!a || !d_dphi0 || !h_dwe) return fail(PSMS_E_INVAL, "NULL argument");
+  if (a->nsteps < 1) return fail(PSMS_E_STATE, "backward before forward");
+  psms_ctx* c = a->rec;
+  const BoxGeom& g = c->g;
+  const int n = g.n;
+  const size_t st = 4 * size_t(g.M) * sizeof(cpx<double>);
+  const long long M4 = 4 * g.M;
+  hipStream_t S = a->stream;
+  const double vol = 8.0 * M_PI * M_PI * M_PI;
+  const double csig = 3.0 / std::sqrt(8.0) * a->p.ch / a->p.we;
+  const double n3 = double(n) * n * n;
+  hipError_t e;
+#define PSMS_TRY(x) \
+  if ((e = (x)) != hipSuccess) return hip_fail(e, "adjoint_backward")
+  PSMS_TRY(psms::launch_adj_terminal(a->prim->state, a->lam, a->mu, g.K, g.C, g.H, g.M, vol, S));
+  PSMS_TRY(hipMemsetAsync(a->acc, 0, sizeof(double), S));
+  const int nseg = (a->nsteps + a->seg_len - 1) / a->seg_len;
+  psms::AdjCoef ac;
+  ac.dt = a->p.dt;
+  ac.nu = 1.0 / a->p.re;
+  ac.ch2_pe = a->p.ch * a->p.ch / a->p.pe;
+  ac.s = c->s;
+  ac.inv_pe = 1.0 / a->p.pe;
+  ac.e_coef = (1.0 + c->s * a->p.ch * a->p.ch) / a->p.pe;
+  ac.inv_n3 = 1.0 / n3;
+  for (int s = nseg - 1; s >= 0; --s) {
+    const int n0 = s * a->seg_len;
+    const int n1 = std::min(n0 + a->seg_len, a->nsteps);
+    // states x^n0 .. x^(n1-1) of the segment, recomputed in FP64 from the checkpoint
+    PSMS_TRY(hipMemcpyAsync(c->state, a->ckpt + 2 * s * M4, st, hipMemcpyDeviceToDevice, S));
+    PSMS_TRY(hipMemcpyAsync(c->hist, a->ckpt + (2 * s + 1) * M4, st, hipMemcpyDeviceToDevice, S));
+    c->nstep = n0;
+    c->have_state = 1;
+    c->g_valid = 0;
+    PSMS_TRY(hipMemcpyAsync(a->seg, c->state, st, hipMemcpyDeviceToDevice, S));
+    for (int m = n0; m < n1 - 1; ++m) {
+      int r = psms_step(c, 1);
+      if (r) return r;
+      PSMS_TRY(hipMemcpyAsync(a->seg + size_t(m - n0 + 1) * M4, c->state, st, hipMemcpyDeviceToDevice, S));
+    }
+    for (int m = n1 - 1; m >= n0; --m) {
+      // forward fields of x^m: z-inverse and y-inverse into the recompute context
+      PSMS_TRY(hipMemcpyAsync(c->state, a->seg + size_t(m - n0) * M4, st, hipMemcpyDeviceToDevice, S));
+      PSMS_TRY(psms::launch_step_stage<double>(n, 3, 2, c->d_box, 0, 1, c->tw64, 0, S));
+      PSMS_TRY(psms::launch_step_stage<double>(n, 0, 2, c->d_box, 0, 1, c->tw64, 1, S));
+      ac.alpha = (m == 0) ? 1.0 : 1.5;
+      ac.beta = (m == 0) ? 0.0 : -0.5;
+      PSMS_TRY(psms::launch_adj_stage(n, 0, a->lam, a->mu, nullptr, nullptr, a->adja, c->tw64, ac, csig, nullptr, S));
+      PSMS_TRY(y_lines64(c, +1, a->adja, a->adjb, 8));
+      PSMS_TRY(psms::launch_adj_stage(n, 1, a->lam, a->mu, static_cast<const cpx<double>*>(c->bufa), a->adjb,
+                                      static_cast<cpx<double>*>(c->bufb), c->tw64, ac, csig, a->part, S));
+      PSMS_TRY(psms::launch_adj_sum(a->part, psms::adj_xblocks(n), -csig / (a->p.we * n3), a->acc, S));
+      PSMS_TRY(y_lines64(c, -1, static_cast<const cpx<double>*>(c->bufb), a->adja, 7));
+      PSMS_TRY(psms::launch_adj_stage(n, 2, a->lam, a->mu, a->adja, nullptr, nullptr, c->tw64, ac, csig, nullptr, S));
+    }
+  }
+  // dJ/dphi0 on the grid: inv(D lam_phi) / n^3
+  PSMS_TRY(psms::launch_expand<double>(a->lam + 3 * g.M, a->adjb, g, 1, S));
+  PSMS_TRY(psms::launch_spec_finish<double>(a->adjb, a->adjb, g, 1, 0, -1, 1.0 / n3, S));
+  c->g_valid = 0;
+  PSMS_TRY(transform_fields<double>(c, -1, 1, a->adjb, d_dphi0, 0));
+  PSMS_TRY(hipMemcpyAsync(h_dwe, a->acc, sizeof(double), hipMemcpyDeviceToHost, S));
+  PSMS_TRY(hipStreamSynchronize(S));
+#undef PSMS_TRY
   return PSMS_OK;
 }
 

@@ -33,20 +33,6 @@ namespace psms {
 template <typename T>
 __device__ __forceinline__ cpx<T> to_cpx(cpx<double> v) { return {T(v.re), T(v.im)}; }
 
-// Tiling of a batch of lines of length N: E values per thread, TT threads per
-// line, L lines per workgroup of THREADS = 64 << V threads (V is the
-// workgroup-size variant the autotuner chooses between; V = 2 is 256).
-template <int N, int V = 2>
-struct Tile {
-  static constexpr int E = Plan<N>::E;
-  static constexpr int TT = N / E;
-  static constexpr int THREADS = 64 << V;
-  static constexpr int L = (THREADS / TT) > 0 ? THREADS / TT : 1;
-  static constexpr int K = (N - 1) / 3;
-  static constexpr int C = 2 * K + 1;
-  static constexpr int H = K + 1;
-};
-
 // ---------------------------------------------------------------------------
 // batched transforms along a strided axis (y or z): L lines per workgroup,
 // lanes line-fastest, LDS element (pos, line) at pos * (L+1) + line.

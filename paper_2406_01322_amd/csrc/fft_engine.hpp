@@ -191,6 +191,20 @@ __device__ __forceinline__ void fft_line(cpx<T>* v, cpx<T>* b0, cpx<T>* b1, int&
   fft_stages<T, N, S, 0, 1>(v, b0, b1, par, t, idx, tw);
 }
 
+// Tiling of a batch of lines of length N: E values per thread, TT threads per
+// line, L lines per workgroup of THREADS = 64 << V threads (V is the
+// workgroup-size variant the autotuner chooses between; V = 2 is 256).
+template <int N, int V = 2>
+struct Tile {
+  static constexpr int E = Plan<N>::E;
+  static constexpr int TT = N / E;
+  static constexpr int THREADS = 64 << V;
+  static constexpr int L = (THREADS / TT) > 0 ? THREADS / TT : 1;
+  static constexpr int K = (N - 1) / 3;
+  static constexpr int C = 2 * K + 1;
+  static constexpr int H = K + 1;
+};
+
 // ---------------------------------------------------------------------------
 // index maps of the retained band and of FFT order
 // ---------------------------------------------------------------------------

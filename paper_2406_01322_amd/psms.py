@@ -95,6 +95,14 @@ _SIGS = {
     "psms_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_double)]),
     "psms_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "psms_adjoint_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "psms_adjoint_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Params), ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "psms_adjoint_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_double)]),
+    "psms_adjoint_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "psms_adjoint_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "psms_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "psms_last_error": (ctypes.c_char_p, []),
     "psms_version": (ctypes.c_char_p, []),
@@ -455,3 +463,88 @@ class Batch:
             with open(cache_path, "w") as f:
                 json.dump(cache, f, indent=1, sort_keys=True)
         return {"source": "timed", "groups": res}
+
+
+# ---------------------------------------------------------------------------
+# discrete adjoint and torch.autograd
+# ---------------------------------------------------------------------------
+
+class Adjoint:
+    """Primal run with FP64 checkpoints every seg_len steps and the hand-written
+    discrete adjoint (recomputing each segment in FP64)."""
+
+    def __init__(self, n, re, we, ch, pe, dt, s=0.0, precision="fp64", max_steps=50, seg_len=10, device="cuda"):
+        import torch
+        self.torch = torch
+        self.n = int(n)
+        self.device = torch.device(device)
+        self.params = make_params(n, re, we, ch, pe, dt, s, precision)
+        nb = ctypes.c_size_t(0)
+        _check(lib().psms_adjoint_workspace_bytes(ctypes.byref(self.params), int(max_steps), int(seg_len),
+                                                  ctypes.byref(nb)))
+        self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().psms_adjoint_create(ctypes.byref(h), ctypes.byref(self.params), int(max_steps), int(seg_len),
+                                         _ptr(self.workspace), int(nb.value), ctypes.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().psms_adjoint_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, u0, phi0, nsteps):
+        torch = self.torch
+        n = self.n
+        u0 = u0.to(self.device, torch.float64).contiguous()
+        phi0 = phi0.to(self.device, torch.float64).contiguous()
+        assert tuple(u0.shape) == (3, n, n, n) and tuple(phi0.shape) == (n, n, n)
+        J = ctypes.c_double(0.0)
+        _check(lib().psms_adjoint_forward(self.h, _ptr(u0), _ptr(phi0), int(nsteps), ctypes.byref(J)))
+        return float(J.value)
+
+    def backward(self):
+        torch = self.torch
+        n = self.n
+        d = torch.empty((n, n, n), dtype=torch.float64, device=self.device)
+        dwe = ctypes.c_double(0.0)
+        _check(lib().psms_adjoint_backward(self.h, _ptr(d), ctypes.byref(dwe)))
+        return d, float(dwe.value)
+
+
+def _objective_function():
+    import torch
+
+    class NSCHObjective(torch.autograd.Function):
+        """J(phi0, We) = int |grad phi|^2 + 1/2 int |u|^2 after nsteps, with the gradient
+        from the hand-written discrete adjoint (segment checkpointing)."""
+
+        @staticmethod
+        def forward(ctx, phi0, we, u0, cfg):
+            a = Adjoint(cfg["n"], cfg["re"], float(we), cfg["ch"], cfg["pe"], cfg["dt"], cfg.get("s", 0.0),
+                        cfg.get("precision", "fp64"), cfg["nsteps"], cfg.get("seg_len", 10), device=phi0.device)
+            J = a.forward(u0, phi0, cfg["nsteps"])
+            ctx.adj = a
+            return torch.tensor(J, dtype=torch.float64, device=phi0.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            d, dwe = ctx.adj.backward()
+            ctx.adj.close()
+            g = gJ.to(torch.float64)
+            return g * d, g * torch.tensor(dwe, dtype=torch.float64, device=d.device), None, None
+
+    return NSCHObjective
+
+
+def objective(phi0, we, u0, cfg):
+    """Differentiable J(phi0, We): cfg holds n, re, ch, pe, dt, nsteps (and s, precision,
+    seg_len).  phi0 [n,n,n] and we (0-d) are float64 tensors on the GPU."""
+    return _objective_function().apply(phi0, we, u0, cfg)
