@@ -65,6 +65,23 @@ def step_model_bytes(n, mixed):
     return w_phys * 30 * P + 16 * 2 * 20 * M + w_rhs * 2 * 16 * M
 
 
+def measured_traffic(stage):
+    """HBM bytes per launch of a stage kernel from the committed counter record
+    (profiles/box128_mixed_hbm_counters.json), or None if the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "box128_mixed_hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"].get(stage)
+
+
 def run_gpu(precision, n, p, u, phi, steps, warmup):
     import torch
     from paper_2406_01322_amd.psms import Solver
@@ -138,6 +155,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first copy a buffer of this many MiB 3 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -146,6 +165,13 @@ def main():
     import torch
     from paper_2406_01322_amd import synth
 
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     name = "drops16_128"
     p, u, phi = synth.box_case(name)
     n = p["n"]
@@ -179,7 +205,8 @@ def main():
                    "n": n, "precision": head,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom) if head == "mixed" else None,
                      "algorithmic_bytes_per_launch": sb[dom]},
         "stage_ms": r["stage_ms"],
         "stage_gbs": {k: sb[k] / (r["stage_ms"][k] * 1e-3) / 1e9 for k in STAGES},

@@ -51,7 +51,7 @@ __device__ __forceinline__ void lines_body(const cpx<T>* __restrict__ src, cpx<T
   const int tid = threadIdx.x;
   const int line = tid % L, t = tid / L;
   for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
-  const long long gl = (long long)blockIdx.x * L + line;
+  const long long gl = (long long)xcd_tile(blockIdx.x, gridDim.x) * L + line;
   const bool valid = gl < a.nlines;
   const long long o = valid ? gl / a.inner : 0, i = valid ? gl % a.inner : 0;
 
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ bo
   const int tid = threadIdx.x;
   const int t = tid % TT, line = tid / TT;
   for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
-  const long long r0 = ((long long)blockIdx.x * L + line) * 2;
+  const long long r0 = ((long long)xcd_tile(blockIdx.x, gridDim.x) * L + line) * 2;
   const bool valid = r0 < ROWS;  // ROWS is even: both rows exist
   const IdxLineMajor idx{line * LP};
   int par = 0;
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
   const int tid = threadIdx.x;
   const int line = tid % L, t = tid / L;
   for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
-  const int q = blockIdx.x * L + line;
+  const int q = xcd_tile(blockIdx.x, gridDim.x) * L + line;
   const bool valid = q < Q;
   const int iy = valid ? q / H : 0, ix = valid ? q % H : 0;
   const double kx = double(ix);

@@ -205,6 +205,17 @@ struct Tile {
   static constexpr int H = K + 1;
 };
 
+// XCD-aware tile index.  Workgroups are dealt round-robin to the 8 XCDs of
+// the MI355X, each with its own L2; this bijection gives every XCD a
+// contiguous range of tiles, so neighbouring tiles (which share cache lines
+// of the strided-axis layouts) are served by the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int X = 8;
+  const int q = nb / X, r = nb % X;
+  const int x = b % X, i = b / X;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // ---------------------------------------------------------------------------
 // index maps of the retained band and of FFT order
 // ---------------------------------------------------------------------------

