@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -85,16 +86,18 @@ def measured_traffic(stage):
 def run_gpu(precision, n, p, u, phi, steps, warmup):
     import torch
     from paper_2406_01322_amd.psms import Solver
-    s = Solver(n, p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision)
-    s.init_state(torch.from_numpy(u).cuda(), torch.from_numpy(phi).cuda())
-    if warmup > 0:
-        s.step(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms = s.stage_times(steps)          # the timed steps, HIP events around each kernel
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    d = s.diagnostics()
+    stream = torch.cuda.Stream()       # a capturable stream: steps replay a hipGraph
+    with torch.cuda.stream(stream):
+        s = Solver(n, p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision)
+        s.init_state(torch.from_numpy(u).cuda(), torch.from_numpy(phi).cuda())
+        if warmup > 0:
+            s.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = s.stage_times(steps)      # the timed steps, HIP events around each kernel
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        d = s.diagnostics()
     if d["nonfinite"] or not (d["max_div"] < 1e-8):
         raise RuntimeError("%s run produced a bad state: %s" % (precision, d))
     wall = t1 - t0
@@ -129,6 +132,92 @@ def mixed_error(n, p, u, phi, nsteps=(1, 20)):
     return out
 
 
+def bench_batch(steps=100, nbox=96):
+    """The batched form: 96 independent boxes, N drawn from {32, 48, 64, 96}, 1-8 drops,
+    Re ~ U[50, 400], We ~ U[0.5, 5], MIXED; workgroup sizes autotuned; after the first
+    step every step is one hipGraph replay.  Timed with HIP events on the batch stream."""
+    import torch
+    from paper_2406_01322_amd import synth
+    from paper_2406_01322_amd.psms import Batch
+    cases = synth.batch_cases(nbox=nbox, seed=4)
+    b = Batch([c[0] for c in cases], precision="mixed")
+    tune = b.autotune(reps=3)
+    for i, (p, u, phi) in enumerate(cases):
+        b.init_state(i, torch.from_numpy(u), torch.from_numpy(phi))
+    b.step(2)                                   # AB1 step, graph capture
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    pts = sum(c[0]["n"] ** 3 for c in cases)
+    bad = [i for i in range(nbox) if b.diagnostics(i)["nonfinite"]]
+    if bad:
+        raise RuntimeError("batched boxes went non-finite: %s" % bad)
+    return {"boxes": nbox, "groups": b.groups(), "total_points": pts, "steps": steps,
+            "ms_per_step": ms / steps, "value": pts * steps / (ms * 1e-3), "unit": "grid-points*timesteps/s",
+            "variants": {k: v["variants"] for k, v in tune["groups"].items()}}
+
+
+def bench_adjoint(nsteps=50, seg_len=10):
+    """The adjoint form: 128^3 16-drop workload, MIXED primal with FP64 checkpoints every
+    seg_len steps, FP64 segment recompute and discrete adjoint; J = int |grad phi|^2 +
+    1/2 int |u|^2; gradient with respect to phi0 and We."""
+    import torch
+    from paper_2406_01322_amd import synth
+    from paper_2406_01322_amd.psms import Adjoint
+    p, u, phi = synth.box_case("drops16_128")
+    a = Adjoint(p["n"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision="mixed", max_steps=nsteps,
+                seg_len=seg_len)
+    u_d, phi_d = torch.from_numpy(u).cuda(), torch.from_numpy(phi).cuda()
+    a.forward(u_d, phi_d, nsteps)
+    a.backward()                                 # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = a.forward(u_d, phi_d, nsteps)
+    t1 = time.perf_counter()
+    d, dwe = a.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    if not (torch.isfinite(d).all() and math.isfinite(dwe)):
+        raise RuntimeError("adjoint produced non-finite values")
+    return {"n": p["n"], "steps": nsteps, "checkpoint_every": seg_len, "J": J, "dJ_dWe": dwe,
+            "forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1),
+            "backward_over_forward": (t2 - t1) / (t1 - t0)}
+
+
+def bench_wall_solve(reps=20):
+    """The channel's implicit wall-normal solves (omega_z, w with the influence matrix,
+    the two CH Helmholtz problems, u and v) for kx = 0..85, ky = -42..42 (7310 lines) of
+    nc + 1 = 129 Chebyshev coefficients, Re_tau = 150, dt = 1e-4, Ch = 0.02, Pe = 50."""
+    import numpy as np
+    import torch
+    from paper_2406_01322_amd import psms
+    nc = 128
+    kx = np.repeat(np.arange(86, dtype=float), 85)
+    ky = np.tile(np.arange(-42, 43, dtype=float), 86)
+    nl = len(kx)
+    rng = np.random.default_rng(3)
+    g = [torch.from_numpy((rng.standard_normal((nc + 1, nl)) + 1j * rng.standard_normal((nc + 1, nl)))
+                          * np.exp(-0.05 * np.arange(nc + 1))[:, None]).cuda() for _ in range(3)]
+    kxd, kyd = torch.from_numpy(kx).cuda(), torch.from_numpy(ky).cuda()
+    beta_ns = 2.0 * 150.0 / 1e-4
+    beta_ch = math.sqrt(50.0 / (1e-4 * 0.02 ** 2))
+    psms.wall_solve(kxd, kyd, beta_ns, beta_ch, beta_ch, *g)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        psms.wall_solve(kxd, kyd, beta_ns, beta_ch, beta_ch, *g)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"lines": nl, "nc": nc, "ms_per_solve_set": ms,
+            "lines_per_s": nl / (ms * 1e-3)}
+
+
 def cpu_baseline(n, p, u, phi, budget_s=20.0):
     """The FP64 oracle on the host: init, then as many steps as fit in ~budget_s."""
     import numpy as np  # noqa: F401
@@ -155,6 +244,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched, adjoint and channel wall-solve measurements")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a buffer of this many MiB 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -219,6 +310,12 @@ def main():
         out["speedup_mixed_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
     if "fp64" in res and "mixed" in res:
         out["mixed_vs_fp64_rel_l2"] = mixed_error(n, p, u, phi)
+    if not args.no_forms:
+        out["forms"] = {}
+        for name, fn in (("batched", bench_batch), ("adjoint", bench_adjoint), ("channel_wall_solve", bench_wall_solve)):
+            out["forms"][name] = fn()
+            print("[bench] %s: %s" % (name, {k: v for k, v in out["forms"][name].items() if k != "groups"}),
+                  file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, p, u, phi)
     print(json.dumps(out), flush=True)

@@ -122,8 +122,13 @@ int psms_set_state(psms_ctx* c, const double* d_uhat, const double* d_phihat, co
 
 /* Steps (ii)-(v) of Sec. 2.2, `nsteps` times: nonlinear terms in physical
  * space, Leray projection (the periodic form of the velocity-vorticity
- * system), CN + AB2 for u, IE + AB2 for phi.  Asynchronous, no allocation. */
+ * system), CN + AB2 for u, IE + AB2 for phi.  Asynchronous, no allocation.
+ * On a non-NULL stream, every step after the first (Adams-Bashforth 1) one
+ * replays a captured hipGraph of the step's four kernels. */
 int psms_step(psms_ctx* c, int32_t nsteps);
+
+/* Enable (default) or disable the graph replay of psms_step. */
+int psms_set_graphs(psms_ctx* c, int32_t enable);
 
 /* Copy the state out in the layouts of psms_set_state; d_hist may be NULL. */
 int psms_get_state(psms_ctx* c, double* d_uhat, double* d_phihat, double* d_hist);
@@ -154,7 +159,9 @@ int psms_index_maps(psms_ctx* c, int32_t* d_out);
  * runs `nsteps` steps like psms_step, recording a HIP event on the
  * context's stream around each of the step's kernels, synchronises, and
  * writes the average duration in milliseconds of each stage to h_ms[0..3]:
- * y-inverse, x stage with products, y-forward, z stage with the update. */
+ * y-inverse, x stage with products, y-forward, z stage with the update.
+ * When psms_step would replay a graph, the timed steps (with their event
+ * records) are captured into one graph and launched once. */
 int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms);
 
 /* ---------------------------------------------------------------------------

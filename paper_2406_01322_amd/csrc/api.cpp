@@ -111,6 +111,10 @@ struct psms_ctx {
   psms::BoxDev h_box;    // its host copy
   int box_ab1;           // ab1 value last written to d_box (-1: never)
   int variant[4];        // workgroup-size variant per stage
+  int use_graph;         // replay a captured step graph (needs a non-NULL stream)
+  int graph_ok;
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
   int have_state;
   int g_valid;  // the z-inverse of the current state sits in bufb
   int nstep;
@@ -322,6 +326,8 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
   c->h_box.csig = 3.0 / std::sqrt(8.0) * p->ch / p->we;
   c->box_ab1 = -1;
   for (int i = 0; i < 4; ++i) c->variant[i] = 2;
+  c->use_graph = 1;
+  c->graph_ok = 0;
 
   // Twiddles exp(-2 pi i m / n) in FP64, rounded once to FP32 for MIXED.
   const int n = p->n;
@@ -345,7 +351,17 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
 }
 
 int psms_destroy(psms_ctx* c) {
+  if (c && c->graph_ok) {
+    (void)hipGraphExecDestroy(c->gexec);
+    (void)hipGraphDestroy(c->graph);
+  }
   delete c;
+  return PSMS_OK;
+}
+
+int psms_set_graphs(psms_ctx* c, int32_t enable) {
+  if (!c) return fail(PSMS_E_INVAL, "NULL context");
+  c->use_graph = enable ? 1 : 0;
   return PSMS_OK;
 }
 
@@ -416,7 +432,25 @@ int psms_step(psms_ctx* c, int32_t nsteps) {
     c->g_valid = 1;
   }
   for (int i = 0; i < nsteps; ++i) {
-    e = mixed ? one_step<float>(c) : one_step<double>(c);
+    // after the Adams-Bashforth 1 step every step is the same launch sequence:
+    // capture it once and replay it
+    const bool graph = c->use_graph && c->stream != nullptr && c->nstep > 0;
+    if (graph) {
+      e = sync_box(c);
+      if (e == hipSuccess && !c->graph_ok) {
+        e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          hipError_t e2 = mixed ? one_step<float>(c) : one_step<double>(c);
+          e = hipStreamEndCapture(c->stream, &c->graph);
+          if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) c->graph_ok = 1;
+      }
+      if (e == hipSuccess) e = hipGraphLaunch(c->gexec, c->stream);
+    } else {
+      e = mixed ? one_step<float>(c) : one_step<double>(c);
+    }
     if (e != hipSuccess) {
       c->g_valid = 0;
       return hip_fail(e, "step");
@@ -437,14 +471,29 @@ int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms) {
     if (e != hipSuccess) return hip_fail(e, "step prologue");
     c->g_valid = 1;
   }
+  // with a capturable stream and history present, the timed steps run as one
+  // captured graph (event-record nodes between the kernels), as psms_step runs them
+  const bool graph = c->use_graph && c->stream != nullptr && c->nstep > 0;
   std::vector<hipEvent_t> ev(5 * size_t(nsteps));
   size_t made = 0;
   for (; made < ev.size(); ++made)
     if ((e = hipEventCreate(&ev[made])) != hipSuccess) break;
   double acc[4] = {0, 0, 0, 0};
+  hipGraph_t g = nullptr;
+  hipGraphExec_t gx = nullptr;
+  if (e == hipSuccess) e = sync_box(c);
+  if (e == hipSuccess && graph) e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
   for (int i = 0; e == hipSuccess && i < nsteps; ++i) {
-    e = mixed ? one_step<float>(c, &ev[5 * i]) : one_step<double>(c, &ev[5 * i]);
-    if (e == hipSuccess) c->nstep += 1;
+    if (!graph && i == 1) e = sync_box(c);
+    if (e == hipSuccess) e = mixed ? one_step<float>(c, &ev[5 * i]) : one_step<double>(c, &ev[5 * i]);
+    if (!graph && e == hipSuccess) c->nstep += 1;
+  }
+  if (graph) {
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(gx, c->stream);
+    if (e == hipSuccess) c->nstep += nsteps;
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   for (int i = 0; e == hipSuccess && i < nsteps; ++i) {
@@ -454,6 +503,8 @@ int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms) {
       acc[k] += ms;
     }
   }
+  if (gx) (void)hipGraphExecDestroy(gx);
+  if (g) (void)hipGraphDestroy(g);
   for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
   if (e != hipSuccess) {
     c->g_valid = 0;

@@ -103,6 +103,7 @@ _SIGS = {
                                             ctypes.POINTER(ctypes.c_double)]),
     "psms_adjoint_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "psms_adjoint_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "psms_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "psms_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "psms_last_error": (ctypes.c_char_p, []),
     "psms_version": (ctypes.c_char_p, []),
@@ -212,6 +213,9 @@ class Solver:
 
     def step(self, nsteps=1):
         _check(lib().psms_step(self.ctx, int(nsteps)))
+
+    def set_graphs(self, enable):
+        _check(lib().psms_set_graphs(self.ctx, 1 if enable else 0))
 
     def stage_times(self, nsteps):
         """Run nsteps steps and return the average ms of each of the 4 stage kernels."""

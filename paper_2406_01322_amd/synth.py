@@ -16,8 +16,12 @@ projection.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft
+
+_WORKERS = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1))
 
 TWO_PI = 2.0 * math.pi
 
@@ -48,7 +52,7 @@ def random_velocity(n: int, rng: np.random.Generator, k0: float = 4.0,
     KZ, KY, KX = _int_wavenumbers(n)
     kmag = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
     noise = rng.standard_normal((3, n, n, n))
-    a_hat = np.fft.rfftn(noise, axes=(1, 2, 3))
+    a_hat = scipy.fft.rfftn(noise, axes=(1, 2, 3), workers=_WORKERS)
     mag = np.abs(a_hat)
     mag[mag == 0.0] = 1.0
     amp = np.exp(-(kmag / k0) ** 2)
@@ -60,7 +64,7 @@ def random_velocity(n: int, rng: np.random.Generator, k0: float = 4.0,
     ux = 1j * (KY * az - KZ * ay)
     uy = 1j * (KZ * ax - KX * az)
     uz = 1j * (KX * ay - KY * ax)
-    u = np.stack([np.fft.irfftn(c, s=(n, n, n), axes=(0, 1, 2))
+    u = np.stack([scipy.fft.irfftn(c, s=(n, n, n), axes=(0, 1, 2), workers=_WORKERS)
                   for c in (ux, uy, uz)])
     rms = math.sqrt(float(np.mean(u * u)))
     if rms > 0.0:
