@@ -30,11 +30,12 @@ template <int N>
 __global__ void __launch_bounds__(256) k_zadj_in(cpx<double>* __restrict__ lam, cpx<double>* __restrict__ mu,
                                                  cpx<double>* __restrict__ gout, const cpx<double>* __restrict__ tw_g,
                                                  AdjCoef ac) {
-  using G = Tile<N>;
+  using P = Plan<N>;
+  using G = Tile<P>;
   constexpr int E = G::E, L = G::L, LP = L + 1, K = G::K, C = G::C, H = G::H;
   constexpr int Q = C * H;
   constexpr long long M = (long long)C * Q;
-  constexpr int RI = first_radix<N, 1>(), RO = last_radix<N, 1>();
+  constexpr int RI = first_radix<P, 1>(), RO = last_radix<P, 1>();
   __shared__ cpx<double> tw[N];
   __shared__ cpx<double> lds[2][N * LP];
   const int tid = threadIdx.x;
@@ -55,7 +56,7 @@ __global__ void __launch_bounds__(256) k_zadj_in(cpx<double>* __restrict__ lam, 
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
       const int e = b * RI + r;
-      const int p = slot_pos<N, RI>(t, b, r);
+      const int p = slot_pos<P, RI>(t, b, r);
       const int s = band_slot(p, C, N);
       inb[e] = valid && s >= 0;
       kz[e] = double(signed_k(p, N));
@@ -118,13 +119,13 @@ __global__ void __launch_bounds__(256) k_zadj_in(cpx<double>* __restrict__ lam, 
       }
       v[e] = x;
     }
-    fft_line<double, N, 1>(v, lds[0], lds[1], par, t, idx, tw);
+    fft_line<double, P, 1>(v, lds[0], lds[1], par, t, idx, tw);
     cpx<double>* dst = gout + (long long)f * N * Q;
     if (valid) {
 #pragma unroll
       for (int b = 0; b < E / RO; ++b)
 #pragma unroll
-        for (int r = 0; r < RO; ++r) dst[(long long)slot_pos<N, RO>(t, b, r) * Q + q] = v[b * RO + r];
+        for (int r = 0; r < RO; ++r) dst[(long long)slot_pos<P, RO>(t, b, r) * Q + q] = v[b * RO + r];
     }
   }
 }
@@ -139,20 +140,23 @@ template <int N>
 __global__ void __launch_bounds__(256) k_xadj(const cpx<double>* __restrict__ yf, const cpx<double>* __restrict__ yb,
                                               cpx<double>* __restrict__ out, const cpx<double>* __restrict__ tw_g,
                                               double csig, double* __restrict__ part) {
-  using G = Tile<N>;
-  constexpr int E = G::E, TT = G::TT, L = G::L, LP = N + 1, K = G::K, H = G::H;
-  constexpr int RI = first_radix<N, 1>(), RP = last_radix<N, 1>(), RO = last_radix<N, -1>();
-  static_assert(RP == first_radix<N, -1>(), "mirrored radix order");
+  using P = Plan<N>;
+  using G = Tile<P>;
+  constexpr int E = G::E, TT = G::TT, L = G::L, LP = kRowStride<N>, K = G::K, H = G::H;
+  constexpr int RI = first_radix<P, 1>(), RP = last_radix<P, 1>(), RO = last_radix<P, -1>();
+  static_assert(RP == first_radix<P, -1>(), "mirrored radix order");
   constexpr long long ROWS = (long long)N * N;
-  __shared__ cpx<double> tw[N];
+  __shared__ cpx<double> twf[tw_size<P, -1>()];
+  __shared__ cpx<double> twi[tw_size<P, 1>()];
   __shared__ cpx<double> lds[2][L * LP];
   __shared__ double red[256];
   const int tid = threadIdx.x;
   const int t = tid % TT, line = tid / TT;
-  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
+  build_twiddles<double, P, -1>(twf, [&](int m) { return tw_g[m]; }, tid, int(blockDim.x));
+  build_twiddles<double, P, 1>(twi, [&](int m) { return tw_g[m]; }, tid, int(blockDim.x));
   const long long r0 = ((long long)blockIdx.x * L + line) * 2;
   const bool valid = r0 < ROWS;
-  const IdxLineMajor idx{line * LP};
+  const IdxLineMajor<N, TT> idx{line * LP};
   int par = 0;
   __syncthreads();
 
@@ -162,7 +166,7 @@ __global__ void __launch_bounds__(256) k_xadj(const cpx<double>* __restrict__ yf
     for (int b = 0; b < E / RI; ++b)
 #pragma unroll
       for (int r = 0; r < RI; ++r) {
-        const int p = slot_pos<N, RI>(t, b, r);
+        const int p = slot_pos<P, RI>(t, b, r);
         const int k = (p <= N / 2) ? p : N - p;
         cpx<double> z = {0.0, 0.0};
         if (valid && k <= K) {
@@ -180,18 +184,18 @@ __global__ void __launch_bounds__(256) k_xadj(const cpx<double>* __restrict__ yf
         }
         v[b * RI + r] = z;
       }
-    fft_line<double, N, 1>(v, lds[0], lds[1], par, t, idx, tw);
+    fft_line<double, P, 1>(v, lds[0], lds[1], par, t, idx, twi);
   };
   // x-forward of register slots and store of the retained kx of both rows
   auto xfwd = [&](cpx<double>* v, cpx<double>* dst) {
-    fft_line<double, N, -1>(v, lds[0], lds[1], par, t, idx, tw);
+    fft_line<double, P, -1>(v, lds[0], lds[1], par, t, idx, twf);
     cpx<double>* Lb = par ? lds[1] : lds[0];
     par ^= 1;
 #pragma unroll
     for (int b = 0; b < E / RO; ++b)
 #pragma unroll
-      for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<N, RO>(t, b, r))] = v[b * RO + r];
-    __syncthreads();
+      for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<P, RO>(t, b, r))] = v[b * RO + r];
+    wave_lds_sync();  // the line's threads are one wavefront's lanes
     for (int k = t; valid && k < H; k += TT) {
       const cpx<double> zk = Lb[idx(k)], zm = Lb[idx((N - k) % N)];
       dst[r0 * H + k] = cpx<double>{0.5 * (zk.re + zm.re), 0.5 * (zk.im - zm.im)};
@@ -279,11 +283,12 @@ __global__ void __launch_bounds__(256) k_xadj(const cpx<double>* __restrict__ yf
 template <int N>
 __global__ void __launch_bounds__(256) k_zadj_out(const cpx<double>* __restrict__ zin, cpx<double>* __restrict__ lam,
                                                   const cpx<double>* __restrict__ tw_g, double inv_n3) {
-  using G = Tile<N>;
+  using P = Plan<N>;
+  using G = Tile<P>;
   constexpr int E = G::E, L = G::L, LP = L + 1, K = G::K, C = G::C, H = G::H;
   constexpr int Q = C * H;
   constexpr long long M = (long long)C * Q;
-  constexpr int RF = first_radix<N, -1>(), RL = last_radix<N, -1>();
+  constexpr int RF = first_radix<P, -1>(), RL = last_radix<P, -1>();
   __shared__ cpx<double> tw[N];
   __shared__ cpx<double> lds[2][N * LP];
   const int tid = threadIdx.x;
@@ -309,15 +314,15 @@ __global__ void __launch_bounds__(256) k_zadj_out(const cpx<double>* __restrict_
     for (int b = 0; b < E / RF; ++b)
 #pragma unroll
       for (int r = 0; r < RF; ++r)
-        v[b * RF + r] = valid ? src[(long long)slot_pos<N, RF>(t, b, r) * Q + q] : cpx<double>{0.0, 0.0};
-    fft_line<double, N, -1>(v, lds[0], lds[1], par, t, idx, tw);
+        v[b * RF + r] = valid ? src[(long long)slot_pos<P, RF>(t, b, r) * Q + q] : cpx<double>{0.0, 0.0};
+    fft_line<double, P, -1>(v, lds[0], lds[1], par, t, idx, tw);
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int e = b * RL + r;
         const cpx<double> w = {v[e].re * inv_n3, v[e].im * inv_n3};
-        const double kz = double(signed_k(slot_pos<N, RL>(t, b, r), N));
+        const double kz = double(signed_k(slot_pos<P, RL>(t, b, r), N));
         if (f == 0) acc[0][e] = cadd(acc[0][e], w);
         else if (f == 1) acc[1][e] = cadd(acc[1][e], w);
         else if (f == 2) acc[2][e] = cadd(acc[2][e], w);
@@ -335,7 +340,7 @@ __global__ void __launch_bounds__(256) k_zadj_out(const cpx<double>* __restrict_
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int e = b * RL + r;
-        const int s = band_slot(slot_pos<N, RL>(t, b, r), C, N);
+        const int s = band_slot(slot_pos<P, RL>(t, b, r), C, N);
         if (s >= 0) {
           const long long id = (long long)s * Q + q;
 #pragma unroll
@@ -388,7 +393,8 @@ template <int N>
 hipError_t adj_n(int stage, cpx<double>* lam, cpx<double>* mu, const cpx<double>* a, const cpx<double>* b,
                  cpx<double>* out, const cpx<double>* tw, const AdjCoef& ac, double csig, double* part,
                  hipStream_t st) {
-  using G = Tile<N>;
+  using P = Plan<N>;
+  using G = Tile<P>;
   const int Q = G::C * G::H;
   const unsigned threads = unsigned(G::L * G::TT);
   if (stage == 0) {
@@ -406,7 +412,7 @@ hipError_t adj_n(int stage, cpx<double>* lam, cpx<double>* mu, const cpx<double>
 int adj_xblocks(int n) {
   switch (n) {
 #define PSMS_CASE(NN) \
-  case NN: return int(((long long)NN * NN / 2 + Tile<NN>::L - 1) / Tile<NN>::L);
+  case NN: return int(((long long)NN * NN / 2 + Tile<Plan<NN>>::L - 1) / Tile<Plan<NN>>::L);
     PSMS_FOR_EACH_N(PSMS_CASE)
 #undef PSMS_CASE
   }

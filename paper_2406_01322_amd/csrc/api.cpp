@@ -471,29 +471,16 @@ int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms) {
     if (e != hipSuccess) return hip_fail(e, "step prologue");
     c->g_valid = 1;
   }
-  // with a capturable stream and history present, the timed steps run as one
-  // captured graph (event-record nodes between the kernels), as psms_step runs them
-  const bool graph = c->use_graph && c->stream != nullptr && c->nstep > 0;
+  // eager launches with an event between consecutive kernels (events recorded
+  // inside a captured graph cannot be timed)
   std::vector<hipEvent_t> ev(5 * size_t(nsteps));
   size_t made = 0;
   for (; made < ev.size(); ++made)
     if ((e = hipEventCreate(&ev[made])) != hipSuccess) break;
   double acc[4] = {0, 0, 0, 0};
-  hipGraph_t g = nullptr;
-  hipGraphExec_t gx = nullptr;
-  if (e == hipSuccess) e = sync_box(c);
-  if (e == hipSuccess && graph) e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
   for (int i = 0; e == hipSuccess && i < nsteps; ++i) {
-    if (!graph && i == 1) e = sync_box(c);
-    if (e == hipSuccess) e = mixed ? one_step<float>(c, &ev[5 * i]) : one_step<double>(c, &ev[5 * i]);
-    if (!graph && e == hipSuccess) c->nstep += 1;
-  }
-  if (graph) {
-    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(gx, c->stream);
-    if (e == hipSuccess) c->nstep += nsteps;
+    e = mixed ? one_step<float>(c, &ev[5 * i]) : one_step<double>(c, &ev[5 * i]);
+    if (e == hipSuccess) c->nstep += 1;
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   for (int i = 0; e == hipSuccess && i < nsteps; ++i) {
@@ -503,8 +490,6 @@ int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms) {
       acc[k] += ms;
     }
   }
-  if (gx) (void)hipGraphExecDestroy(gx);
-  if (g) (void)hipGraphDestroy(g);
   for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
   if (e != hipSuccess) {
     c->g_valid = 0;

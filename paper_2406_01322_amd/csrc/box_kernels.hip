@@ -25,6 +25,7 @@
 // blockIdx.z, so one launch advances every box of a given size.
 #include <hip/hip_runtime.h>
 
+
 #include "box_kernels.hpp"
 #include "fft_engine.hpp"
 
@@ -33,6 +34,7 @@ namespace psms {
 template <typename T>
 __device__ __forceinline__ cpx<T> to_cpx(cpx<double> v) { return {T(v.re), T(v.im)}; }
 
+
 // ---------------------------------------------------------------------------
 // batched transforms along a strided axis (y or z): L lines per workgroup,
 // lanes line-fastest, LDS element (pos, line) at pos * (L+1) + line.
@@ -40,12 +42,13 @@ __device__ __forceinline__ cpx<T> to_cpx(cpx<double> v) { return {T(v.re), T(v.i
 // n_in slots, zero-padded).  Output field f reads input field (fmap >> 4f)&15;
 // bit f of dmask multiplies by i k along the axis.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int S, int V>
+template <typename T, class P, int S, int V>
 __device__ __forceinline__ void lines_body(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                            const cpx<T>* __restrict__ tw_g, const LineArgs& a, bool deriv) {
-  using G = Tile<N, V>;
+  using G = Tile<P, V>;
+  constexpr int N = P::N;
   constexpr int E = G::E, L = G::L, LP = L + 1;
-  constexpr int RI = first_radix<N, S>(), RO = last_radix<N, S>();
+  constexpr int RI = first_radix<P, S>(), RO = last_radix<P, S>();
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> lds[2][N * LP];
   const int tid = threadIdx.x;
@@ -60,11 +63,11 @@ __device__ __forceinline__ void lines_body(const cpx<T>* __restrict__ src, cpx<T
   for (int b = 0; b < E / RI; ++b) {
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
-      const int p = slot_pos<N, RI>(t, b, r);
+      const int p = slot_pos<P, RI>(t, b, r);
       const int s = band_slot(p, a.n_in, N);
       cpx<T> x = {T(0), T(0)};
       if (valid && s >= 0) {
-        x = src[(o * a.n_in + s) * a.inner + i];
+        x = ld_global(src + (o * a.n_in + s) * a.inner + i);
         if (S > 0 && deriv) {
           const T k = T(signed_k(p, N));
           x = cpx<T>{-k * x.im, k * x.re};
@@ -75,13 +78,13 @@ __device__ __forceinline__ void lines_body(const cpx<T>* __restrict__ src, cpx<T
   }
   __syncthreads();
   int par = 0;
-  fft_line<T, N, S>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
+  fft_line<T, P, S>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
   const T sc = T(a.scale);
 #pragma unroll
   for (int b = 0; b < E / RO; ++b) {
 #pragma unroll
     for (int r = 0; r < RO; ++r) {
-      const int p = slot_pos<N, RO>(t, b, r);
+      const int p = slot_pos<P, RO>(t, b, r);
       const int s = band_slot(p, a.n_out, N);
       if (valid && s >= 0) {
         cpx<T> x = v[b * RO + r];
@@ -89,7 +92,7 @@ __device__ __forceinline__ void lines_body(const cpx<T>* __restrict__ src, cpx<T
           const T k = T(signed_k(p, N));
           x = cpx<T>{-k * x.im, k * x.re};
         }
-        dst[(o * a.n_out + s) * a.inner + i] = cpx<T>{sc * x.re, sc * x.im};
+        st_global(dst + (o * a.n_out + s) * a.inner + i, cpx<T>{sc * x.re, sc * x.im});
       }
     }
   }
@@ -99,7 +102,7 @@ template <typename T, int N, int S>
 __global__ void __launch_bounds__(256) k_lines(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                                const cpx<T>* __restrict__ tw_g, LineArgs a) {
   const int fo = blockIdx.y;
-  lines_body<T, N, S, 2>(in + (long long)((a.fmap >> (4 * fo)) & 15) * a.in_fstride,
+  lines_body<T, Plan<N>, S, 2>(in + (long long)((a.fmap >> (4 * fo)) & 15) * a.in_fstride,
                          out + (long long)fo * a.out_fstride, tw_g, a, (a.dmask >> fo) & 1);
 }
 
@@ -109,7 +112,8 @@ __global__ void __launch_bounds__(256) k_lines(const cpx<T>* __restrict__ in, cp
 template <typename T, int N, int S, int V>
 __global__ void __launch_bounds__(64 << V) k_ystep(const BoxDev* __restrict__ boxes, int box0,
                                                    const cpx<T>* __restrict__ tw_g) {
-  using G = Tile<N, V>;
+  using P = Plan<N>;
+  using G = Tile<P, V>;
   const BoxDev& bx = boxes[box0 + blockIdx.z];
   const int fo = blockIdx.y;
   LineArgs a;
@@ -121,12 +125,14 @@ __global__ void __launch_bounds__(64 << V) k_ystep(const BoxDev* __restrict__ bo
     a.n_in = G::C;
     a.n_out = N;
     const int fin = (fo <= 3) ? fo : fo - 1;
-    lines_body<T, N, S, V>(static_cast<const cpx<T>*>(bx.bufb) + fin * nq, static_cast<cpx<T>*>(bx.bufa) + fo * nnh,
+    lines_body<T, P, S, V>(static_cast<const cpx<T>*>(bx.bufb) + fin * nq,
+                           static_cast<cpx<T>*>(bx.bufa) + fo * nnh,
                            tw_g, a, fo == 4);
   } else {
     a.n_in = N;
     a.n_out = G::C;
-    lines_body<T, N, S, V>(static_cast<const cpx<T>*>(bx.bufb) + fo * nnh, static_cast<cpx<T>*>(bx.bufa) + fo * nq,
+    lines_body<T, P, S, V>(static_cast<const cpx<T>*>(bx.bufb) + fo * nnh,
+                           static_cast<cpx<T>*>(bx.bufa) + fo * nq,
                            tw_g, a, false);
   }
 }
@@ -139,14 +145,15 @@ __global__ void __launch_bounds__(64 << V) k_ystep(const BoxDev* __restrict__ bo
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_rows_fwd(const T* __restrict__ in, cpx<T>* __restrict__ out,
                                                   const cpx<T>* __restrict__ tw_g, RowArgs a) {
-  using G = Tile<N>;
-  constexpr int E = G::E, TT = G::TT, L = G::L, LP = N + 1;
-  constexpr int RI = first_radix<N, -1>(), RO = last_radix<N, -1>();
-  __shared__ cpx<T> tw[N];
+  using P = Plan<N>;
+  using G = Tile<P>;
+  constexpr int E = G::E, TT = G::TT, L = G::L, LP = kRowStride<N>;
+  constexpr int RI = first_radix<P, -1>(), RO = last_radix<P, -1>();
+  __shared__ cpx<T> tw[tw_size<P, -1>()];
   __shared__ cpx<T> lds[2][L * LP];
   const int tid = threadIdx.x;
   const int t = tid % TT, line = tid / TT;
-  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
+  build_twiddles<T, P, -1>(tw, [&](int m) { return tw_g[m]; }, tid, int(blockDim.x));
   const T* src = in + (long long)blockIdx.y * a.in_fstride;
   cpx<T>* dst = out + (long long)blockIdx.y * a.out_fstride;
   const long long r0 = ((long long)blockIdx.x * L + line) * 2;
@@ -156,19 +163,19 @@ __global__ void __launch_bounds__(256) k_rows_fwd(const T* __restrict__ in, cpx<
   for (int b = 0; b < E / RI; ++b)
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
-      const int p = slot_pos<N, RI>(t, b, r);
+      const int p = slot_pos<P, RI>(t, b, r);
       v[b * RI + r] = cpx<T>{v0 ? src[r0 * N + p] : T(0), v1 ? src[(r0 + 1) * N + p] : T(0)};
     }
   __syncthreads();
   int par = 0;
-  const IdxLineMajor idx{line * LP};
-  fft_line<T, N, -1>(v, lds[0], lds[1], par, t, idx, tw);
+  const IdxLineMajor<N, TT> idx{line * LP};
+  fft_line<T, P, -1>(v, lds[0], lds[1], par, t, idx, tw);
   cpx<T>* Lb = par ? lds[1] : lds[0];
 #pragma unroll
   for (int b = 0; b < E / RO; ++b)
 #pragma unroll
-    for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<N, RO>(t, b, r))] = v[b * RO + r];
-  __syncthreads();
+    for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<P, RO>(t, b, r))] = v[b * RO + r];
+  wave_lds_sync();  // the line's threads are one wavefront's lanes
   const T h = T(0.5) * T(a.scale);
   for (int k = t; k < a.n_out; k += TT) {
     const cpx<T> zk = Lb[idx(k)];
@@ -181,14 +188,15 @@ __global__ void __launch_bounds__(256) k_rows_fwd(const T* __restrict__ in, cpx<
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in, T* __restrict__ out,
                                                   const cpx<T>* __restrict__ tw_g, RowArgs a) {
-  using G = Tile<N>;
-  constexpr int E = G::E, TT = G::TT, L = G::L, LP = N + 1;
-  constexpr int RI = first_radix<N, 1>(), RO = last_radix<N, 1>();
-  __shared__ cpx<T> tw[N];
+  using P = Plan<N>;
+  using G = Tile<P>;
+  constexpr int E = G::E, TT = G::TT, L = G::L, LP = kRowStride<N>;
+  constexpr int RI = first_radix<P, 1>(), RO = last_radix<P, 1>();
+  __shared__ cpx<T> tw[tw_size<P, 1>()];
   __shared__ cpx<T> lds[2][L * LP];
   const int tid = threadIdx.x;
   const int t = tid % TT, line = tid / TT;
-  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
+  build_twiddles<T, P, 1>(tw, [&](int m) { return tw_g[m]; }, tid, int(blockDim.x));
   const cpx<T>* src = in + (long long)blockIdx.y * a.in_fstride;
   T* dst = out + (long long)blockIdx.y * a.out_fstride;
   const long long r0 = ((long long)blockIdx.x * L + line) * 2;
@@ -198,7 +206,7 @@ __global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in,
   for (int b = 0; b < E / RI; ++b)
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
-      const int p = slot_pos<N, RI>(t, b, r);
+      const int p = slot_pos<P, RI>(t, b, r);
       const int k = (p <= N / 2) ? p : N - p;
       cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
       if (k < a.n_in) {
@@ -214,13 +222,13 @@ __global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in,
     }
   __syncthreads();
   int par = 0;
-  fft_line<T, N, 1>(v, lds[0], lds[1], par, t, IdxLineMajor{line * LP}, tw);
+  fft_line<T, P, 1>(v, lds[0], lds[1], par, t, IdxLineMajor<N, TT>{line * LP}, tw);
   const T sc = T(a.scale);
 #pragma unroll
   for (int b = 0; b < E / RO; ++b)
 #pragma unroll
     for (int r = 0; r < RO; ++r) {
-      const int p = slot_pos<N, RO>(t, b, r);
+      const int p = slot_pos<P, RO>(t, b, r);
       if (v0) dst[r0 * N + p] = sc * v[b * RO + r].re;
       if (v1) dst[(r0 + 1) * N + p] = sc * v[b * RO + r].im;
     }
@@ -235,24 +243,27 @@ __global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in,
 template <typename T, int N, int V>
 __global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ boxes, int box0,
                                                    const cpx<T>* __restrict__ tw_g) {
-  using G = Tile<N, V>;
+  using P = Plan<N>;
+  using G = Tile<P, V>;
   const BoxDev& bx = boxes[box0 + blockIdx.z];
   const cpx<T>* __restrict__ yin = static_cast<const cpx<T>*>(bx.bufa);
   cpx<T>* __restrict__ xout = static_cast<cpx<T>*>(bx.bufb);
   const double csig_d = bx.csig;
-  constexpr int E = G::E, TT = G::TT, L = G::L, LP = N + 1, K = G::K, H = G::H;
-  constexpr int RI = first_radix<N, 1>();   // inverse starts with R[NST-1]
-  constexpr int RP = last_radix<N, 1>();    // inverse ends / forward starts with R[0]
-  constexpr int RO = last_radix<N, -1>();   // forward ends with R[NST-1]
+  constexpr int E = G::E, TT = G::TT, L = G::L, LP = kRowStride<N>, K = G::K, H = G::H;
+  constexpr int RI = first_radix<P, 1>();   // inverse starts with R[NST-1]
+  constexpr int RP = last_radix<P, 1>();    // inverse ends / forward starts with R[0]
+  constexpr int RO = last_radix<P, -1>();   // forward ends with R[NST-1]
   constexpr long long ROWS = (long long)N * N;
-  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> twf[tw_size<P, -1>()];
+  __shared__ cpx<T> twi[tw_size<P, 1>()];
   __shared__ cpx<T> lds[2][L * LP];
   const int tid = threadIdx.x;
   const int t = tid % TT, line = tid / TT;
-  for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
+  build_twiddles<T, P, -1>(twf, [&](int m) { return tw_g[m]; }, tid, int(blockDim.x));
+  build_twiddles<T, P, 1>(twi, [&](int m) { return tw_g[m]; }, tid, int(blockDim.x));
   const long long r0 = ((long long)xcd_tile(blockIdx.x, gridDim.x) * L + line) * 2;
   const bool valid = r0 < ROWS;  // ROWS is even: both rows exist
-  const IdxLineMajor idx{line * LP};
+  const IdxLineMajor<N, TT> idx{line * LP};
   int par = 0;
   __syncthreads();
 
@@ -267,12 +278,12 @@ __global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ bo
     for (int b = 0; b < E / RI; ++b)
 #pragma unroll
       for (int r = 0; r < RI; ++r) {
-        const int p = slot_pos<N, RI>(t, b, r);
+        const int p = slot_pos<P, RI>(t, b, r);
         const int k = (p <= N / 2) ? p : N - p;
         cpx<T> z = {T(0), T(0)};
         if (valid && k <= K) {
-          cpx<T> A = src[r0 * H + k];
-          cpx<T> B = src[(r0 + 1) * H + k];
+          cpx<T> A = ld_global(src + r0 * H + k);
+          cpx<T> B = ld_global(src + (r0 + 1) * H + k);
           if (vf == 4) {
             const T kx = T(k);
             A = cpx<T>{-kx * A.im, kx * A.re};
@@ -286,7 +297,7 @@ __global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ bo
         }
         v[b * RI + r] = z;
       }
-    fft_line<T, N, 1>(v, lds[0], lds[1], par, t, idx, tw);
+    fft_line<T, P, 1>(v, lds[0], lds[1], par, t, idx, twi);
 #pragma unroll
     for (int e = 0; e < E; ++e) ph[vf][e] = v[e];
   }
@@ -324,21 +335,21 @@ __global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ bo
       }
       v[e] = cpx<T>{res[0], res[1]};
     }
-    static_assert(RP == first_radix<N, -1>(), "mirrored radix order");
-    fft_line<T, N, -1>(v, lds[0], lds[1], par, t, idx, tw);
+    static_assert(RP == first_radix<P, -1>(), "mirrored radix order");
+    fft_line<T, P, -1>(v, lds[0], lds[1], par, t, idx, twf);
     cpx<T>* Lb = par ? lds[1] : lds[0];
     par ^= 1;
 #pragma unroll
     for (int b = 0; b < E / RO; ++b)
 #pragma unroll
-      for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<N, RO>(t, b, r))] = v[b * RO + r];
-    __syncthreads();
+      for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<P, RO>(t, b, r))] = v[b * RO + r];
+    wave_lds_sync();  // the line's threads are one wavefront's lanes
     cpx<T>* dst = xout + (long long)f * ROWS * H;
     for (int k = t; valid && k < H; k += TT) {
       const cpx<T> zk = Lb[idx(k)];
       const cpx<T> zm = Lb[idx((N - k) % N)];
-      dst[r0 * H + k] = cpx<T>{h * (zk.re + zm.re), h * (zk.im - zm.im)};
-      dst[(r0 + 1) * H + k] = cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)};
+      st_global(dst + r0 * H + k, cpx<T>{h * (zk.re + zm.re), h * (zk.im - zm.im)});
+      st_global(dst + (r0 + 1) * H + k, cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)});
     }
   }
 }
@@ -353,7 +364,8 @@ __global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ bo
 template <typename T, int N, int V>
 __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ boxes, int box0,
                                                    const cpx<T>* __restrict__ tw_g, int do_update) {
-  using G = Tile<N, V>;
+  using P = Plan<N>;
+  using G = Tile<P, V>;
   const BoxDev& bx = boxes[box0 + blockIdx.z];
   const cpx<T>* __restrict__ rhs = static_cast<const cpx<T>*>(bx.bufa);
   cpx<double>* __restrict__ state = bx.state;
@@ -363,9 +375,9 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
   constexpr int E = G::E, L = G::L, LP = L + 1, K = G::K, C = G::C, H = G::H;
   constexpr int Q = C * H;
   constexpr long long M = (long long)C * Q;
-  constexpr int RF = first_radix<N, -1>();   // forward starts with R[0]
-  constexpr int RL = last_radix<N, -1>();    // forward ends / inverse starts with R[NST-1]
-  static_assert(RL == first_radix<N, 1>(), "mirrored radix order");
+  constexpr int RF = first_radix<P, -1>();   // forward starts with R[0]
+  constexpr int RL = last_radix<P, -1>();    // forward ends / inverse starts with R[NST-1]
+  static_assert(RL == first_radix<P, 1>(), "mirrored radix order");
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> lds[2][N * LP];
   const int tid = threadIdx.x;
@@ -387,7 +399,7 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
   for (int b = 0; b < E / RL; ++b)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
-      const int p = slot_pos<N, RL>(t, b, r);
+      const int p = slot_pos<P, RL>(t, b, r);
       const int s = band_slot(p, C, N);
       inb[b * RL + r] = valid && s >= 0;
       slot[b * RL + r] = s;
@@ -407,7 +419,7 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
     for (int b = 0; b < E / RF; ++b)
 #pragma unroll
       for (int r = 0; r < RF; ++r)
-        nx[b * RF + r] = valid ? rhs[(long long)slot_pos<N, RF>(t, b, r) * Q + q] : cpx<T>{T(0), T(0)};
+        nx[b * RF + r] = valid ? ld_global(rhs + (long long)slot_pos<P, RF>(t, b, r) * Q + q) : cpx<T>{T(0), T(0)};
 #pragma unroll 1
     for (int f = 0; f < 8; ++f) {
       cpx<T> v[E];
@@ -419,9 +431,9 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
         for (int b = 0; b < E / RF; ++b)
 #pragma unroll
           for (int r = 0; r < RF; ++r)
-            nx[b * RF + r] = valid ? src[(long long)slot_pos<N, RF>(t, b, r) * Q + q] : cpx<T>{T(0), T(0)};
+            nx[b * RF + r] = valid ? ld_global(src + (long long)slot_pos<P, RF>(t, b, r) * Q + q) : cpx<T>{T(0), T(0)};
       }
-      fft_line<T, N, -1>(v, lds[0], lds[1], par, t, idx, tw);
+      fft_line<T, P, -1>(v, lds[0], lds[1], par, t, idx, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         if (inb[e]) {
@@ -458,7 +470,7 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
         const double k2 = kx * kx + ky * ky + kz[e] * kz[e];
         const long long id = (long long)slot[e] * Q + q;
         cpx<double> Sx = acc[0][e], Sy = acc[1][e], Sz = acc[2][e], Sp = acc[3][e];
-        const cpx<double> ph = state[3 * M + id];
+        const cpx<double> ph = ld_global(state + 3 * M + id);
         Sp.re += sc.e_coef * k2 * ph.re;
         Sp.im += sc.e_coef * k2 * ph.im;
         if (k2 == 0.0) {
@@ -475,28 +487,28 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
         if (!sc.ab1) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const cpx<double> hp = hist[c * M + id];
+            const cpx<double> hp = ld_global(hist + c * M + id);
             ex[c].re = 1.5 * ex[c].re - 0.5 * hp.re;
             ex[c].im = 1.5 * ex[c].im - 0.5 * hp.im;
           }
         }
-        hist[0 * M + id] = Sx;
-        hist[1 * M + id] = Sy;
-        hist[2 * M + id] = Sz;
-        hist[3 * M + id] = Sp;
+        st_global(hist + 0 * M + id, Sx);
+        st_global(hist + 1 * M + id, Sy);
+        st_global(hist + 2 * M + id, Sz);
+        st_global(hist + 3 * M + id, Sp);
         const double a = 0.5 * sc.dt * sc.nu * k2;
         const double ia = 1.0 / (1.0 + a);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const cpx<double> u = state[c * M + id];
+          const cpx<double> u = ld_global(state + c * M + id);
           const cpx<double> un = {((1.0 - a) * u.re + sc.dt * ex[c].re) * ia,
                                   ((1.0 - a) * u.im + sc.dt * ex[c].im) * ia};
-          state[c * M + id] = un;
+          st_global(state + c * M + id, un);
           acc[c][e] = un;
         }
         const double den = 1.0 / (1.0 + sc.dt * sc.ch2_pe * (k2 * k2 + sc.s * k2));
         const cpx<double> pn = {(ph.re + sc.dt * ex[3].re) * den, (ph.im + sc.dt * ex[3].im) * den};
-        state[3 * M + id] = pn;
+        st_global(state + 3 * M + id, pn);
         acc[3][e] = pn;
       }
     }
@@ -506,7 +518,7 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
       if (inb[e]) {
         const long long id = (long long)slot[e] * Q + q;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c][e] = state[c * M + id];
+        for (int c = 0; c < 4; ++c) acc[c][e] = ld_global(state + c * M + id);
       }
     }
   }
@@ -527,13 +539,13 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
       }
       v[e] = to_cpx<T>(x);
     }
-    fft_line<T, N, 1>(v, lds[0], lds[1], par, t, idx, tw);
+    fft_line<T, P, 1>(v, lds[0], lds[1], par, t, idx, tw);
     cpx<T>* dst = gout + (long long)gf * N * Q;
     if (valid) {
 #pragma unroll
       for (int b = 0; b < E / RF; ++b)
 #pragma unroll
-        for (int r = 0; r < RF; ++r) dst[(long long)slot_pos<N, RF>(t, b, r) * Q + q] = v[b * RF + r];
+        for (int r = 0; r < RF; ++r) st_global(dst + (long long)slot_pos<P, RF>(t, b, r) * Q + q, v[b * RF + r]);
     }
   }
 }
@@ -753,7 +765,8 @@ namespace {
 template <typename T, int N>
 hipError_t lines_n(int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, const LineArgs& a, int nfield,
                    hipStream_t st) {
-  using G = Tile<N>;
+  using P = Plan<N>;
+  using G = Tile<P>;
   const dim3 grid(unsigned((a.nlines + G::L - 1) / G::L), unsigned(nfield));
   const dim3 block(unsigned(G::L * G::TT));
   if (dir < 0) k_lines<T, N, -1><<<grid, block, 0, st>>>(in, out, tw, a);
@@ -764,7 +777,8 @@ hipError_t lines_n(int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, con
 template <typename T, int N>
 hipError_t rows_n(int dir, const void* in, void* out, const cpx<T>* tw, const RowArgs& a, int nfield,
                   hipStream_t st) {
-  using G = Tile<N>;
+  using P = Plan<N>;
+  using G = Tile<P>;
   const long long pairs = (a.nrows + 1) / 2;
   const dim3 grid(unsigned((pairs + G::L - 1) / G::L), unsigned(nfield));
   const dim3 block(unsigned(G::L * G::TT));
@@ -778,7 +792,8 @@ hipError_t rows_n(int dir, const void* in, void* out, const cpx<T>* tw, const Ro
 template <typename T, int N, int V>
 hipError_t step_nv(int stage, const BoxDev* boxes, int box0, int nbox, const cpx<T>* tw, int do_update,
                    hipStream_t st) {
-  using G = Tile<N, V>;
+  using P = Plan<N>;
+  using G = Tile<P, V>;
   const unsigned threads = unsigned(G::L * G::TT);
   switch (stage) {
     case 0: {  // y-inverse, 6 output fields

@@ -24,9 +24,10 @@ namespace psms {
 
 namespace {
 
-template <int N>
+template <class P>
 struct CTile {
-  static constexpr int E = Plan<N>::E;
+  static constexpr int N = P::N;
+  static constexpr int E = P::E;
   static constexpr int TT = N / E;
   static constexpr int L = (256 / TT) > 0 ? 256 / TT : 1;
 };
@@ -40,9 +41,10 @@ struct CTile {
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                              long long nlines, int dir) {
-  using G = CTile<N>;
+  using P = Plan<N>;
+  using G = CTile<P>;
   constexpr int E = G::E, L = G::L, LP = L + 1, NC = N / 2;
-  constexpr int RI = first_radix<N, -1>(), RO = last_radix<N, -1>();
+  constexpr int RI = first_radix<P, -1>(), RO = last_radix<P, -1>();
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> lds[2][N * LP];
   const int tid = threadIdx.x;
@@ -59,7 +61,7 @@ __global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<
   for (int b = 0; b < E / RI; ++b)
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
-      const int p = slot_pos<N, RI>(t, b, r);
+      const int p = slot_pos<P, RI>(t, b, r);
       const int j = (p <= NC) ? p : N - p;
       cpx<T> x = {T(0), T(0)};
       if (valid) {
@@ -73,13 +75,13 @@ __global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<
     }
   __syncthreads();
   int par = 0;
-  fft_line<T, N, -1>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
+  fft_line<T, P, -1>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
   if (valid) {
 #pragma unroll
     for (int b = 0; b < E / RO; ++b)
 #pragma unroll
       for (int r = 0; r < RO; ++r) {
-        const int p = slot_pos<N, RO>(t, b, r);
+        const int p = slot_pos<P, RO>(t, b, r);
         if (p <= NC) {
           cpx<T> x = v[b * RO + r];
           if (dir > 0) {
@@ -285,7 +287,7 @@ bool supported_nc(int nc) {
 namespace {
 template <typename T, int N>
 hipError_t dct_n(const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st) {
-  using G = CTile<N>;
+  using G = CTile<Plan<N>>;
   k_dct<T, N><<<unsigned((nlines + G::L - 1) / G::L), unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir);
   return hipGetLastError();
 }

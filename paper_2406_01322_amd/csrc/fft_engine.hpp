@@ -17,7 +17,8 @@
 //
 // Radix plans: N = 2^m uses E = 4 (radix 4 stages, one radix-2 stage when m
 // is odd); N = 3*2^m uses E = 6 (one radix-3 stage, radix-2 stages).
-// Twiddles exp(-2 pi i m / N) come from a table computed in FP64 on the host.
+// Twiddles exp(-2 pi i m / N) come from a table computed in FP64 on the host,
+// regrouped per stage in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,40 +49,72 @@ __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
   return (S > 0) ? cpx<T>{-a.im, a.re} : cpx<T>{a.im, -a.re};
 }
 
+// Global-memory access through an explicit global address space.  Pointers
+// read from a descriptor table in memory are generic (flat) to the compiler,
+// and flat accesses also count against the LDS wait counter, so every LDS
+// wait of a transform would drain them; these helpers issue global loads and
+// stores instead.  p must point to device global memory, 2 * sizeof(T)
+// aligned.
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_global(const cpx<T>* p) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  const T2 v = *(const __attribute__((address_space(1))) T2*)(const void*)p;
+  return cpx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_global(cpx<T>* p, cpx<T> v) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  T2 w;
+  w.x = v.re;
+  w.y = v.im;
+  *(__attribute__((address_space(1))) T2*)(void*)p = w;
+}
+
 // ---------------------------------------------------------------------------
-// compile-time plans
+// compile-time plans: transform length N, values per thread E, radix sequence
 // ---------------------------------------------------------------------------
+template <int N_, int E_, int R0, int R1 = 0, int R2 = 0, int R3 = 0, int R4 = 0, int R5 = 0, int R6 = 0>
+struct PlanT {
+  static constexpr int N = N_;
+  static constexpr int E = E_;
+  static constexpr int NST = (R0 > 0) + (R1 > 0) + (R2 > 0) + (R3 > 0) + (R4 > 0) + (R5 > 0) + (R6 > 0);
+  static constexpr int R[8] = {R0, R1, R2, R3, R4, R5, R6, 0};
+};
+
+// Default plans: N = 2^m with E = 4 (radix-4 stages, one radix-2 stage when m
+// is odd); N = 3*2^m with E = 6 (one radix-3 stage, radix-2 stages).
+template <int N> struct PlanSel;
+template <> struct PlanSel<8>   { using type = PlanT<8, 4, 4, 2>; };
+template <> struct PlanSel<16>  { using type = PlanT<16, 4, 4, 4>; };
+template <> struct PlanSel<32>  { using type = PlanT<32, 4, 4, 4, 2>; };
+template <> struct PlanSel<64>  { using type = PlanT<64, 4, 4, 4, 4>; };
+template <> struct PlanSel<128> { using type = PlanT<128, 4, 4, 4, 4, 2>; };
+template <> struct PlanSel<256> { using type = PlanT<256, 4, 4, 4, 4, 4>; };
+template <> struct PlanSel<12>  { using type = PlanT<12, 6, 3, 2, 2>; };
+template <> struct PlanSel<24>  { using type = PlanT<24, 6, 3, 2, 2, 2>; };
+template <> struct PlanSel<48>  { using type = PlanT<48, 6, 3, 2, 2, 2, 2>; };
+template <> struct PlanSel<96>  { using type = PlanT<96, 6, 3, 2, 2, 2, 2, 2>; };
+template <> struct PlanSel<192> { using type = PlanT<192, 6, 3, 2, 2, 2, 2, 2, 2>; };
 template <int N>
-struct Plan;
-template <> struct Plan<8>   { static constexpr int E = 4, NST = 2; static constexpr int R[8] = {4, 2}; };
-template <> struct Plan<16>  { static constexpr int E = 4, NST = 2; static constexpr int R[8] = {4, 4}; };
-template <> struct Plan<32>  { static constexpr int E = 4, NST = 3; static constexpr int R[8] = {4, 4, 2}; };
-template <> struct Plan<64>  { static constexpr int E = 4, NST = 3; static constexpr int R[8] = {4, 4, 4}; };
-template <> struct Plan<128> { static constexpr int E = 4, NST = 4; static constexpr int R[8] = {4, 4, 4, 2}; };
-template <> struct Plan<256> { static constexpr int E = 4, NST = 4; static constexpr int R[8] = {4, 4, 4, 4}; };
-template <> struct Plan<12>  { static constexpr int E = 6, NST = 3; static constexpr int R[8] = {3, 2, 2}; };
-template <> struct Plan<24>  { static constexpr int E = 6, NST = 4; static constexpr int R[8] = {3, 2, 2, 2}; };
-template <> struct Plan<48>  { static constexpr int E = 6, NST = 5; static constexpr int R[8] = {3, 2, 2, 2, 2}; };
-template <> struct Plan<96>  { static constexpr int E = 6, NST = 6; static constexpr int R[8] = {3, 2, 2, 2, 2, 2}; };
-template <> struct Plan<192> { static constexpr int E = 6, NST = 7; static constexpr int R[8] = {3, 2, 2, 2, 2, 2, 2}; };
+using Plan = typename PlanSel<N>::type;
 
 // Radix of stage s when running in direction S (S < 0: forward order,
 // S > 0: reversed order).
-template <int N, int S, int s>
+template <class P, int S, int s>
 __host__ __device__ constexpr int radix_at() {
-  return (S < 0) ? Plan<N>::R[s] : Plan<N>::R[Plan<N>::NST - 1 - s];
+  return (S < 0) ? P::R[s] : P::R[P::NST - 1 - s];
 }
 // Radix of the first / last stage in direction S.
-template <int N, int S>
-__host__ __device__ constexpr int first_radix() { return radix_at<N, S, 0>(); }
-template <int N, int S>
-__host__ __device__ constexpr int last_radix() { return radix_at<N, S, Plan<N>::NST - 1>(); }
+template <class P, int S>
+__host__ __device__ constexpr int first_radix() { return radix_at<P, S, 0>(); }
+template <class P, int S>
+__host__ __device__ constexpr int last_radix() { return radix_at<P, S, P::NST - 1>(); }
 
 // Position of register slot (b, r) for a stage of radix R: t + TT*b + r*N/R.
-template <int N, int R>
+template <class P, int R>
 __device__ __forceinline__ int slot_pos(int t, int b, int r) {
-  constexpr int TT = N / Plan<N>::E;
-  return t + TT * b + r * (N / R);
+  constexpr int TT = P::N / P::E;
+  return t + TT * b + r * (P::N / R);
 }
 
 // ---------------------------------------------------------------------------
@@ -104,7 +137,7 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
     v[1] = cadd(m, r);
     v[2] = csub(m, r);
   } else {
-    static_assert(R == 4, "radix");
+    static_assert(R == 4, "radix 2, 3 or 4");
     const cpx<T> t0 = cadd(v[0], v[2]);
     const cpx<T> t1 = csub(v[0], v[2]);
     const cpx<T> t2 = cadd(v[1], v[3]);
@@ -116,12 +149,52 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
   }
 }
 
+// Twiddles.  Stage s of direction S (radix R, stride NS > 1) needs
+// w(r, k) = exp(-2 pi i r k / (NS R)) for r = 1..R-1, k = 0..NS-1; the inverse
+// applies the conjugates.  Two LDS layouts:
+//  * the plain table exp(-2 pi i m / N), m < N, read at m = r k N / (NS R):
+//    used by strided tiles, whose lanes run over lines and so read the same
+//    entry (a broadcast);
+//  * per-stage tables [r-1][k] at the stage's offset (build_twiddles): used by
+//    row tiles, whose lanes run over positions (k), so that they read
+//    consecutive entries instead of entries r N / (NS R) apart.
+template <class P, int S, int s, int NS = 1>
+__host__ __device__ constexpr int tw_span() {
+  if constexpr (s >= P::NST) {
+    return 0;
+  } else {
+    constexpr int R = radix_at<P, S, s>();
+    return (NS > 1 ? (R - 1) * NS : 0) + tw_span<P, S, s + 1, NS * R>();
+  }
+}
+// Entries of the whole table of direction S.
+template <class P, int S>
+__host__ __device__ constexpr int tw_size() { return tw_span<P, S, 0>(); }
+
+// Fill the table of direction S from base(m) = exp(-2 pi i m / N), with the
+// nthr threads of the block (tid = 0..nthr-1).  The caller synchronises.
+template <typename T, class P, int S, int s = 0, int NS = 1, int OFF = 0, class Base>
+__device__ __forceinline__ void build_twiddles(cpx<T>* dst, const Base& base, int tid, int nthr) {
+  if constexpr (s < P::NST) {
+    constexpr int R = radix_at<P, S, s>();
+    if constexpr (NS > 1) {
+      for (int e = tid; e < (R - 1) * NS; e += nthr) {
+        const int r = 1 + e / NS, k = e % NS;
+        dst[OFF + e] = base(r * k * (P::N / (NS * R)));
+      }
+    }
+    build_twiddles<T, P, S, s + 1, NS * R, OFF + (NS > 1 ? (R - 1) * NS : 0)>(dst, base, tid, nthr);
+  }
+}
+
 // One Stockham stage on registers.  Input  v[b*R + r] = x[j_b + r N/R],
 // output v[b*R + r] = y[d_b + r NS], j_b = t + TT b, k = j_b mod NS,
-// d_b = (j_b / NS) NS R + k, with the twiddle exp(S 2 pi i r k / (NS R)).
-template <typename T, int N, int R, int NS, int S>
+// d_b = (j_b / NS) NS R + k, with the twiddle exp(S 2 pi i r k / (NS R)),
+// read from the stage table at OFF (ST) or from the plain table.
+template <typename T, class P, int R, int NS, int S, int OFF, bool ST>
 __device__ __forceinline__ void stage_regs(cpx<T>* v, int t, const cpx<T>* tw) {
-  constexpr int E = Plan<N>::E;
+  constexpr int N = P::N;
+  constexpr int E = P::E;
   constexpr int TT = N / E;
   constexpr int NB = E / R;
 #pragma unroll
@@ -131,7 +204,7 @@ __device__ __forceinline__ void stage_regs(cpx<T>* v, int t, const cpx<T>* tw) {
       const int k = j % NS;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const cpx<T> w = tw[r * k * (N / (NS * R))];
+        const cpx<T> w = ST ? tw[OFF + (r - 1) * NS + k] : tw[r * k * (N / (NS * R))];
         v[b * R + r] = (S < 0) ? cmul(v[b * R + r], w) : cmulc(v[b * R + r], w);
       }
     }
@@ -139,30 +212,61 @@ __device__ __forceinline__ void stage_regs(cpx<T>* v, int t, const cpx<T>* tw) {
   }
 }
 
-// LDS index functors.  Strided tiles: element (pos, line) at pos*LP + line.
-// Row tiles: element (line, pos) at line*LP + pos.
+// LDS index functors.  kWaveLocal also selects the twiddle layout (per-stage
+// tables for row tiles, the plain table for strided tiles).
+//  * strided tiles (lanes run over lines first): element (pos, line) at
+//    pos * (L + 1) + line; a line's threads span the workgroup, so the
+//    exchanges synchronise the workgroup;
+//  * row tiles (lanes run over positions first): element (line, pos) at
+//    line * kRowStride<N> + pos + 3 (pos >> 4), the padding spreading the
+//    stride-R writes of the early stages over the banks; a line's TT <= 64
+//    threads are consecutive lanes of one wavefront, so the exchanges only
+//    need the wavefront's own ordering.
+template <int N>
+constexpr int kRowStride = N + 3 * ((N - 1) >> 4) + 2;
 struct IdxPosMajor {
-  int lp, line;
+  static constexpr bool kWaveLocal = false;
+  int lp, line;  // lp = L + 1
   __device__ __forceinline__ int operator()(int pos) const { return pos * lp + line; }
 };
+template <int N, int TT = N>
 struct IdxLineMajor {
-  int base;  // line * LP
-  __device__ __forceinline__ int operator()(int pos) const { return base + pos; }
+  static_assert(TT <= 64 && 64 % TT == 0, "a row line must lie within one wavefront");
+  static constexpr bool kWaveLocal = true;
+  int base;  // line * kRowStride<N>
+  __device__ __forceinline__ int operator()(int pos) const { return base + pos + 3 * (pos >> 4); }
 };
+
+// Orders the LDS accesses of one wavefront: the LDS executes a wavefront's
+// instructions in issue order, so only the compiler must not move memory
+// operations across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <class Idx>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (Idx::kWaveLocal) {
+    wave_lds_sync();
+  } else {
+    __syncthreads();
+  }
+}
 
 // Stages s .. NST-1 of a transform in direction S, starting from registers
 // holding the input of stage s.  The exchange buffer alternates between b0 and
-// b1 (selected by par); one barrier per exchange.  All threads of the block
-// must call it.
-template <typename T, int N, int S, int s, int NS, class Idx>
+// b1 (selected by par); one synchronisation per exchange (of the workgroup or,
+// for row tiles, of the wavefront).  All threads of the block must call it.
+template <typename T, class P, int S, int s, int NS, int OFF, class Idx>
 __device__ __forceinline__ void fft_stages(cpx<T>* v, cpx<T>* b0, cpx<T>* b1, int& par, int t, const Idx& idx,
                                            const cpx<T>* tw) {
-  constexpr int R = radix_at<N, S, s>();
-  stage_regs<T, N, R, NS, S>(v, t, tw);
-  if constexpr (s + 1 < Plan<N>::NST) {
-    constexpr int E = Plan<N>::E;
-    constexpr int TT = N / E;
-    constexpr int R2 = radix_at<N, S, s + 1>();
+  constexpr int R = radix_at<P, S, s>();
+  stage_regs<T, P, R, NS, S, OFF, Idx::kWaveLocal>(v, t, tw);
+  if constexpr (s + 1 < P::NST) {
+    constexpr int E = P::E;
+    constexpr int TT = P::N / E;
+    constexpr int R2 = radix_at<P, S, s + 1>();
     cpx<T>* L = par ? b1 : b0;
     par ^= 1;
 #pragma unroll
@@ -172,31 +276,32 @@ __device__ __forceinline__ void fft_stages(cpx<T>* v, cpx<T>* b0, cpx<T>* b1, in
 #pragma unroll
       for (int r = 0; r < R; ++r) L[idx(d + r * NS)] = v[b * R + r];
     }
-    __syncthreads();
+    exchange_sync<Idx>();
 #pragma unroll
     for (int b = 0; b < E / R2; ++b) {
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[b * R2 + r] = L[idx(slot_pos<N, R2>(t, b, r))];
+      for (int r = 0; r < R2; ++r) v[b * R2 + r] = L[idx(slot_pos<P, R2>(t, b, r))];
     }
-    fft_stages<T, N, S, s + 1, NS * R>(v, b0, b1, par, t, idx, tw);
+    fft_stages<T, P, S, s + 1, NS * R, OFF + (NS > 1 ? (R - 1) * NS : 0)>(v, b0, b1, par, t, idx, tw);
   }
 }
 
-// Whole transform.  On entry v[b*R + r] holds x at slot_pos<N, first_radix>;
-// on exit it holds X at slot_pos<N, last_radix>.  S = -1 forward, +1 inverse
-// (unnormalised).
-template <typename T, int N, int S, class Idx>
+// Whole transform.  On entry v[b*R + r] holds x at slot_pos<P, first_radix>;
+// on exit it holds X at slot_pos<P, last_radix>.  S = -1 forward, +1 inverse
+// (unnormalised); tw is the stage table of direction S (build_twiddles).
+template <typename T, class P, int S, class Idx>
 __device__ __forceinline__ void fft_line(cpx<T>* v, cpx<T>* b0, cpx<T>* b1, int& par, int t, const Idx& idx,
                                          const cpx<T>* tw) {
-  fft_stages<T, N, S, 0, 1>(v, b0, b1, par, t, idx, tw);
+  fft_stages<T, P, S, 0, 1, 0>(v, b0, b1, par, t, idx, tw);
 }
 
 // Tiling of a batch of lines of length N: E values per thread, TT threads per
 // line, L lines per workgroup of THREADS = 64 << V threads (V is the
 // workgroup-size variant the autotuner chooses between; V = 2 is 256).
-template <int N, int V = 2>
+template <class P, int V = 2>
 struct Tile {
-  static constexpr int E = Plan<N>::E;
+  static constexpr int N = P::N;
+  static constexpr int E = P::E;
   static constexpr int TT = N / E;
   static constexpr int THREADS = 64 << V;
   static constexpr int L = (THREADS / TT) > 0 ? THREADS / TT : 1;
