@@ -240,9 +240,14 @@ __global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in,
 // the positions the inverse leaves them, which are the positions the forward
 // transform starts from, so the products need no data exchange.
 // ---------------------------------------------------------------------------
+// In FP32 the power-of-two plans up to 128 fit 128 VGPRs without spilling, so
+// the compiler is asked for four waves per SIMD.
+template <typename T, int N>
+constexpr int kXstepWaves = (sizeof(T) == 4 && N <= 128 && (N & (N - 1)) == 0) ? 4 : 1;
+
 template <typename T, int N, int V>
-__global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ boxes, int box0,
-                                                   const cpx<T>* __restrict__ tw_g) {
+__global__ void __launch_bounds__(64 << V) __attribute__((amdgpu_waves_per_eu(kXstepWaves<T, N>)))
+k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ tw_g) {
   using P = Plan<N>;
   using G = Tile<P, V>;
   const BoxDev& bx = boxes[box0 + blockIdx.z];
@@ -267,89 +272,148 @@ __global__ void __launch_bounds__(64 << V) k_xstep(const BoxDev* __restrict__ bo
   int par = 0;
   __syncthreads();
 
-  // x-inverse of u v w phi dx_phi dy_phi dz_phi
+  // x-inverse of u v w phi dx_phi dy_phi dz_phi, two fields at a time; each of
+  // the pair exchanges through its own buffer lds[g] (wavefront-local).  Where
+  // registers allow (PF), the loads of the next pair are issued before the
+  // current pair is transformed, so that their latency overlaps the transforms;
+  // under the four-wavefront register budget they would spill.
   cpx<T> ph[7][E];
-#pragma unroll
-  for (int vf = 0; vf < 7; ++vf) {
+  // raw retained kx of both rows of field vf at slot e (= b RI + r) of the
+  // positions the inverse starts from
+  auto load_raw_slot = [&](int vf, int e, cpx<T>& A, cpx<T>& B) {
     const int fin = (vf <= 3) ? vf : vf - 1;   // vf 4 is i kx times phi
     const cpx<T>* src = yin + (long long)fin * ROWS * H;
-    cpx<T> v[E];
+    const int p = slot_pos<P, RI>(t, e / RI, e % RI);
+    const int k = (p <= N / 2) ? p : N - p;
+    A = cpx<T>{T(0), T(0)};
+    B = cpx<T>{T(0), T(0)};
+    if (valid && k <= K) {
+      A = ld_global(src + r0 * H + k);
+      B = ld_global(src + (r0 + 1) * H + k);
+    }
+  };
+  // the packed complex line z = row0 + i row1 in Hermitian-extended FFT order
+  auto pack_slot = [&](int vf, int e, cpx<T> A, cpx<T> B, cpx<T>& z) {
+    const int p = slot_pos<P, RI>(t, e / RI, e % RI);
+    const int k = (p <= N / 2) ? p : N - p;
+    if (vf == 4) {
+      const T kx = T(k);
+      A = cpx<T>{-kx * A.im, kx * A.re};
+      B = cpx<T>{-kx * B.im, kx * B.re};
+    }
+    if (k == 0) {
+      A.im = T(0);
+      B.im = T(0);
+    }
+    z = (p <= N / 2) ? cpx<T>{A.re - B.im, A.im + B.re} : cpx<T>{A.re + B.im, B.re - A.im};
+  };
+  auto load_raw = [&](int vf, cpx<T>* a, cpx<T>* bb) {
 #pragma unroll
-    for (int b = 0; b < E / RI; ++b)
+    for (int e = 0; e < E; ++e) load_raw_slot(vf, e, a[e], bb[e]);
+  };
+  auto pack = [&](int vf, const cpx<T>* a, const cpx<T>* bb, cpx<T>* v) {
 #pragma unroll
-      for (int r = 0; r < RI; ++r) {
-        const int p = slot_pos<P, RI>(t, b, r);
-        const int k = (p <= N / 2) ? p : N - p;
-        cpx<T> z = {T(0), T(0)};
-        if (valid && k <= K) {
-          cpx<T> A = ld_global(src + r0 * H + k);
-          cpx<T> B = ld_global(src + (r0 + 1) * H + k);
-          if (vf == 4) {
-            const T kx = T(k);
-            A = cpx<T>{-kx * A.im, kx * A.re};
-            B = cpx<T>{-kx * B.im, kx * B.re};
+    for (int e = 0; e < E; ++e) pack_slot(vf, e, a[e], bb[e], v[e]);
+  };
+  constexpr int FS = L * LP;  // buffer of the second transform of a pair
+  constexpr bool PF = kXstepWaves<T, N> == 1;  // registers to spare for prefetching
+  cpx<T> ra[2][E], rb[2][E];
+  if (PF) {
+    load_raw(0, ra[0], rb[0]);
+    load_raw(1, ra[1], rb[1]);
+  }
+#pragma unroll
+  for (int vf = 0; vf < 7; vf += 2) {
+    const int nf = (vf + 1 < 7) ? 2 : 1;
+    cpx<T> v[2][E];
+    if (PF) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (g < nf) pack(vf + g, ra[g], rb[g], v[g]);
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (vf + 2 + g < 7) load_raw(vf + 2 + g, ra[g], rb[g]);
+    } else {
+      // load and pack slot by slot, so that few raw values are live at once
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (g < nf) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            cpx<T> A, B;
+            load_raw_slot(vf + g, e, A, B);
+            pack_slot(vf + g, e, A, B, v[g][e]);
           }
-          if (k == 0) {
-            A.im = T(0);
-            B.im = T(0);
-          }
-          z = (p <= N / 2) ? cpx<T>{A.re - B.im, A.im + B.re} : cpx<T>{A.re + B.im, B.re - A.im};
         }
-        v[b * RI + r] = z;
-      }
-    fft_line<T, P, 1>(v, lds[0], lds[1], par, t, idx, twi);
+    }
+    if (nf == 2) {
+      fft_lines<T, P, 1, 2>(v, lds[0], FS, 0, par, t, idx, twi);
+    } else {
+      fft_lines<T, P, 1, 1>(v, lds[0], FS, 0, par, t, idx, twi);
+    }
 #pragma unroll
-    for (int e = 0; e < E; ++e) ph[vf][e] = v[e];
+    for (int g = 0; g < 2; ++g)
+      if (g < nf)
+#pragma unroll
+        for (int e = 0; e < E; ++e) ph[vf + g][e] = v[g][e];
   }
 
-  // products and x-forward of each
+  // products and x-forward, two fields at a time
   const T cs = T(csig_d);
   const T h = T(0.5);
+  static_assert(RP == first_radix<P, -1>(), "mirrored radix order");
 #pragma unroll 1
-  for (int f = 0; f < 8; ++f) {
-    cpx<T> v[E];
+  for (int f0 = 0; f0 < 8; f0 += 2) {
+    cpx<T> v[2][E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      T res[2];
+    for (int g = 0; g < 2; ++g) {
+      const int f = f0 + g;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const T u = c ? ph[0][e].im : ph[0][e].re;
-        const T vv = c ? ph[1][e].im : ph[1][e].re;
-        const T w = c ? ph[2][e].im : ph[2][e].re;
-        const T p3 = c ? ph[3][e].im : ph[3][e].re;
-        const T gx = c ? ph[4][e].im : ph[4][e].re;
-        const T gy = c ? ph[5][e].im : ph[5][e].re;
-        const T gz = c ? ph[6][e].im : ph[6][e].re;
-        T x;
-        switch (f) {
-          case 0: x = -u * u + cs * (gy * gy + gz * gz); break;     // T_xx
-          case 1: x = -vv * vv + cs * (gx * gx + gz * gz); break;   // T_yy
-          case 2: x = -w * w + cs * (gx * gx + gy * gy); break;     // T_zz
-          case 3: x = -u * vv - cs * gx * gy; break;                // T_xy
-          case 4: x = -u * w - cs * gx * gz; break;                 // T_xz
-          case 5: x = -vv * w - cs * gy * gz; break;                // T_yz
-          case 6: x = u * gx + vv * gy + w * gz; break;             // u . grad phi
-          default: x = p3 * p3 * p3; break;                         // phi^3
+      for (int e = 0; e < E; ++e) {
+        T res[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const T u = c ? ph[0][e].im : ph[0][e].re;
+          const T vv = c ? ph[1][e].im : ph[1][e].re;
+          const T w = c ? ph[2][e].im : ph[2][e].re;
+          const T p3 = c ? ph[3][e].im : ph[3][e].re;
+          const T gx = c ? ph[4][e].im : ph[4][e].re;
+          const T gy = c ? ph[5][e].im : ph[5][e].re;
+          const T gz = c ? ph[6][e].im : ph[6][e].re;
+          T x;
+          switch (f) {
+            case 0: x = -u * u + cs * (gy * gy + gz * gz); break;     // T_xx
+            case 1: x = -vv * vv + cs * (gx * gx + gz * gz); break;   // T_yy
+            case 2: x = -w * w + cs * (gx * gx + gy * gy); break;     // T_zz
+            case 3: x = -u * vv - cs * gx * gy; break;                // T_xy
+            case 4: x = -u * w - cs * gx * gz; break;                 // T_xz
+            case 5: x = -vv * w - cs * gy * gz; break;                // T_yz
+            case 6: x = u * gx + vv * gy + w * gz; break;             // u . grad phi
+            default: x = p3 * p3 * p3; break;                         // phi^3
+          }
+          res[c] = x;
         }
-        res[c] = x;
+        v[g][e] = cpx<T>{res[0], res[1]};
       }
-      v[e] = cpx<T>{res[0], res[1]};
     }
-    static_assert(RP == first_radix<P, -1>(), "mirrored radix order");
-    fft_line<T, P, -1>(v, lds[0], lds[1], par, t, idx, twf);
-    cpx<T>* Lb = par ? lds[1] : lds[0];
-    par ^= 1;
+    fft_lines<T, P, -1, 2>(v, lds[0], FS, 0, par, t, idx, twf);
+    // natural order through the pair's buffers, then the retained kx of both rows
 #pragma unroll
-    for (int b = 0; b < E / RO; ++b)
+    for (int g = 0; g < 2; ++g)
 #pragma unroll
-      for (int r = 0; r < RO; ++r) Lb[idx(slot_pos<P, RO>(t, b, r))] = v[b * RO + r];
+      for (int b = 0; b < E / RO; ++b)
+#pragma unroll
+        for (int r = 0; r < RO; ++r) lds[g][idx(slot_pos<P, RO>(t, b, r))] = v[g][b * RO + r];
     wave_lds_sync();  // the line's threads are one wavefront's lanes
-    cpx<T>* dst = xout + (long long)f * ROWS * H;
-    for (int k = t; valid && k < H; k += TT) {
-      const cpx<T> zk = Lb[idx(k)];
-      const cpx<T> zm = Lb[idx((N - k) % N)];
-      st_global(dst + r0 * H + k, cpx<T>{h * (zk.re + zm.re), h * (zk.im - zm.im)});
-      st_global(dst + (r0 + 1) * H + k, cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)});
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      cpx<T>* dst = xout + (long long)(f0 + g) * ROWS * H;
+      for (int k = t; valid && k < H; k += TT) {
+        const cpx<T> zk = lds[g][idx(k)];
+        const cpx<T> zm = lds[g][idx((N - k) % N)];
+        st_global(dst + r0 * H + k, cpx<T>{h * (zk.re + zm.re), h * (zk.im - zm.im)});
+        st_global(dst + (r0 + 1) * H + k, cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)});
+      }
     }
   }
 }

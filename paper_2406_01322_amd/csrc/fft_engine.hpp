@@ -254,45 +254,64 @@ __device__ __forceinline__ void exchange_sync() {
   }
 }
 
-// Stages s .. NST-1 of a transform in direction S, starting from registers
-// holding the input of stage s.  The exchange buffer alternates between b0 and
-// b1 (selected by par); one synchronisation per exchange (of the workgroup or,
-// for row tiles, of the wavefront).  All threads of the block must call it.
-template <typename T, class P, int S, int s, int NS, int OFF, class Idx>
-__device__ __forceinline__ void fft_stages(cpx<T>* v, cpx<T>* b0, cpx<T>* b1, int& par, int t, const Idx& idx,
-                                           const cpx<T>* tw) {
+// Stages s .. NST-1 of NF independent transforms in direction S, starting
+// from registers holding the input of stage s (v[f] holds line f).  Line f
+// exchanges through the LDS buffer base + f * fstride + par * pstride, par
+// alternating between exchanges; one synchronisation per exchange (of the
+// workgroup or, for row tiles, of the wavefront) serves all NF lines, and
+// their independent butterflies fill each other's LDS latency.  A row tile may
+// use a single buffer per line (pstride = 0): a wavefront's LDS accesses
+// complete in order, and each exchange's writes depend on the previous one's
+// reads.  All threads of the block must call it.
+template <typename T, class P, int S, int s, int NS, int OFF, int NF, class Idx>
+__device__ __forceinline__ void fft_stages(cpx<T> (*v)[P::E], cpx<T>* base, int fstride, int pstride, int& par,
+                                           int t, const Idx& idx, const cpx<T>* tw) {
   constexpr int R = radix_at<P, S, s>();
-  stage_regs<T, P, R, NS, S, OFF, Idx::kWaveLocal>(v, t, tw);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) stage_regs<T, P, R, NS, S, OFF, Idx::kWaveLocal>(v[f], t, tw);
   if constexpr (s + 1 < P::NST) {
     constexpr int E = P::E;
     constexpr int TT = P::N / E;
     constexpr int R2 = radix_at<P, S, s + 1>();
-    cpx<T>* L = par ? b1 : b0;
+    cpx<T>* L = base + par * pstride;
     par ^= 1;
 #pragma unroll
-    for (int b = 0; b < E / R; ++b) {
-      const int j = t + TT * b;
-      const int d = (j / NS) * NS * R + (j % NS);
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
-      for (int r = 0; r < R; ++r) L[idx(d + r * NS)] = v[b * R + r];
-    }
+      for (int b = 0; b < E / R; ++b) {
+        const int j = t + TT * b;
+        const int d = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) L[f * fstride + idx(d + r * NS)] = v[f][b * R + r];
+      }
     exchange_sync<Idx>();
 #pragma unroll
-    for (int b = 0; b < E / R2; ++b) {
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
-      for (int r = 0; r < R2; ++r) v[b * R2 + r] = L[idx(slot_pos<P, R2>(t, b, r))];
-    }
-    fft_stages<T, P, S, s + 1, NS * R, OFF + (NS > 1 ? (R - 1) * NS : 0)>(v, b0, b1, par, t, idx, tw);
+      for (int b = 0; b < E / R2; ++b)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[f][b * R2 + r] = L[f * fstride + idx(slot_pos<P, R2>(t, b, r))];
+    fft_stages<T, P, S, s + 1, NS * R, OFF + (NS > 1 ? (R - 1) * NS : 0), NF>(v, base, fstride, pstride, par, t,
+                                                                              idx, tw);
   }
 }
 
 // Whole transform.  On entry v[b*R + r] holds x at slot_pos<P, first_radix>;
 // on exit it holds X at slot_pos<P, last_radix>.  S = -1 forward, +1 inverse
-// (unnormalised); tw is the stage table of direction S (build_twiddles).
+// (unnormalised); tw is the twiddle table of direction S for the tile kind.
+// Exchanges alternate between the buffers b0 and b1.
 template <typename T, class P, int S, class Idx>
 __device__ __forceinline__ void fft_line(cpx<T>* v, cpx<T>* b0, cpx<T>* b1, int& par, int t, const Idx& idx,
                                          const cpx<T>* tw) {
-  fft_stages<T, P, S, 0, 1, 0>(v, b0, b1, par, t, idx, tw);
+  fft_stages<T, P, S, 0, 1, 0, 1>(reinterpret_cast<cpx<T>(*)[P::E]>(v), b0, 0, int(b1 - b0), par, t, idx, tw);
+}
+
+// NF transforms at once (see fft_stages): line f exchanges through
+// base + f * fstride (+ pstride on alternate exchanges).
+template <typename T, class P, int S, int NF, class Idx>
+__device__ __forceinline__ void fft_lines(cpx<T> (*v)[P::E], cpx<T>* base, int fstride, int pstride, int& par, int t,
+                                          const Idx& idx, const cpx<T>* tw) {
+  fft_stages<T, P, S, 0, 1, 0, NF>(v, base, fstride, pstride, par, t, idx, tw);
 }
 
 // Tiling of a batch of lines of length N: E values per thread, TT threads per
