@@ -238,6 +238,56 @@ int psms_wall_workspace_bytes(int32_t nc, int64_t nlines, size_t* bytes);
 int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The channel step (Sec. 2.1-2.2): x, y periodic (lengths lx, ly; Fourier, nx
+ * and ny points), z in [-1, 1] between no-slip walls (Chebyshev-Gauss-Lobatto
+ * points z_j = cos(pi j / nc), j = 0..nc).  The velocity is carried as the
+ * wall-normal vorticity omega_z and velocity w (eqs. omegaz, ww, omegadef)
+ * plus the mean velocities U(z), V(z); phi obeys the split CH equation
+ * (eq. phisplit) with no flux through the walls.  One step: u, v from
+ * continuity and eq. omegadef; u, v, w, phi, grad phi to physical space; the
+ * products of eqs. NSE, kort, CHE (divergence form) at the collocation points;
+ * back to spectral space with the 2/3 rule in x, y and in the Chebyshev index
+ * (n <= floor((2 nc - 1)/3)); H_omega = (curl S)_z, H_w = lap_h S_z - D div_h S;
+ * Adams-Bashforth (order 1 on the first step) with Crank-Nicolson viscous terms
+ * and implicit Euler for the split CH operator, i.e. the wall-normal solves of
+ * psms_wall_solve with beta_ns = 2 re / dt and the two CH factors, and the
+ * Dirichlet mean-flow problem driven by -dP/dx = forcing.  re is Re_tau = 1/nu.
+ *
+ * Spectral arrays are complex double [field][n][ky][kx] over the band
+ * kx = 0..Kx, ky = 0..Ky, -Ky..-1 (Kx = floor((nx-1)/3), Ky = floor((ny-1)/3)),
+ * n = 0..nc: the state is [3] = (omega_z, w, phi), the history (the previous
+ * step's H_omega, H_w, S_phi) likewise; the mean lines are [2][nc+1] complex
+ * (U, V) and their history (mean S_x, S_y).  Physical fields are real double
+ * [z][y][x], x_i = lx i / nx, y_j = ly j / ny.
+ * Transforms and products run in FP32 for PSMS_MIXED; the state, the
+ * right-hand sides and every solve are FP64.
+ * ------------------------------------------------------------------------- */
+typedef struct psms_channel_params {
+  int32_t nx, ny, nc; /* nx, ny as for psms_params.n; nc in {4 6 8 12 16 24 32 48 64 96 128} */
+  int32_t precision;  /* PSMS_FP64 or PSMS_MIXED */
+  double lx, ly;      /* periods in x and y */
+  double re, we, ch, pe, dt;
+  double s;           /* CH splitting coefficient; 0 selects sqrt(4 Pe / (Ch^2 dt)) */
+  double forcing;     /* mean pressure gradient -dP/dx (1 in wall units) */
+} psms_channel_params;
+typedef struct psms_channel psms_channel;
+
+int psms_channel_workspace_bytes(const psms_channel_params* p, size_t* bytes);
+int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* d_workspace, size_t bytes,
+                        void* stream);
+/* State from physical u, v, w, phi ([nc+1][ny][nx] each, on the collocation
+ * grid); the next step is Adams-Bashforth 1.  Synchronises. */
+int psms_channel_init_state(psms_channel* c, const double* d_u, const double* d_v, const double* d_w,
+                            const double* d_phi);
+/* State, mean lines and (for nstep > 0) history in the layouts above. */
+int psms_channel_set_state(psms_channel* c, const double* d_state, const double* d_mean, const double* d_hist,
+                           const double* d_hmean, int32_t nstep);
+int psms_channel_step(psms_channel* c, int32_t nsteps);
+/* d_hist and d_hmean may be NULL. */
+int psms_channel_get_state(psms_channel* c, double* d_state, double* d_mean, double* d_hist, double* d_hmean);
+int psms_channel_destroy(psms_channel* c);
+
+/* ---------------------------------------------------------------------------
  * Batches of independent boxes of uneven size (each with its own N, Re, We,
  * Ch, Pe, dt, s; one precision for the whole batch).  Boxes of equal N form a
  * group; each stage kernel is launched once per group and advances all its

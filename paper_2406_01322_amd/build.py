@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsms.so")
 
-SOURCES = ["box_kernels.hip", "channel_kernels.hip", "adjoint_kernels.hip", "api.cpp"]
+SOURCES = ["box_kernels.hip", "channel_kernels.hip", "channel_step_kernels.hip", "adjoint_kernels.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

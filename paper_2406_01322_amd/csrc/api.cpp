@@ -13,6 +13,7 @@
 #include "box_kernels.hpp"
 #include "channel_kernels.hpp"
 #include "adjoint_kernels.hpp"
+#include "channel_step_kernels.hpp"
 
 using psms::BoxGeom;
 using psms::cpx;
@@ -1209,6 +1210,473 @@ int psms_adjoint_backward(psms_adjoint* a, double* d_dphi0, double* h_dwe) {
   PSMS_TRY(hipMemcpyAsync(h_dwe, a->acc, sizeof(double), hipMemcpyDeviceToHost, S));
   PSMS_TRY(hipStreamSynchronize(S));
 #undef PSMS_TRY
+  return PSMS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// the channel step (Sec. 2.2): Fourier in x and y, Chebyshev in z
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ChanLayout {
+  size_t kx, ky, twx64, twx32, twy64, twy32;
+  size_t state, mean, hist, hmean;
+  size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, T1, T2, lapc, lapphi, lapom, psi, lappsi, G;
+  size_t dmean, d2mean, gmean, xwm, wall, total;
+};
+
+psms::ChanGeom chan_geom(const psms_channel_params& p) {
+  psms::ChanGeom g{};
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nc = p.nc;
+  g.Kx = (p.nx - 1) / 3;
+  g.Hx = g.Kx + 1;
+  g.Ky = (p.ny - 1) / 3;
+  g.Cy = 2 * g.Ky + 1;
+  g.Kz = (2 * p.nc - 1) / 3;
+  g.NL = (long long)g.Cy * g.Hx;
+  g.NZL = (long long)(p.nc + 1) * g.NL;
+  g.P = (long long)(p.nc + 1) * p.ny * p.nx;
+  return g;
+}
+
+ChanLayout chan_layout(const psms_channel_params& p) {
+  const psms::ChanGeom g = chan_geom(p);
+  const size_t t = (p.precision == PSMS_MIXED) ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  const size_t tr = t / 2;
+  const size_t nz = size_t(p.nc) + 1;
+  const size_t c64 = sizeof(cpx<double>);
+  const size_t arr = align256(size_t(g.NZL) * c64);
+  ChanLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t& field, size_t bytes) {
+    field = off;
+    off += align256(bytes);
+  };
+  take(L.kx, size_t(g.NL) * sizeof(double));
+  take(L.ky, size_t(g.NL) * sizeof(double));
+  take(L.twx64, size_t(p.nx) * c64);
+  take(L.twx32, size_t(p.nx) * sizeof(cpx<float>));
+  take(L.twy64, size_t(p.ny) * c64);
+  take(L.twy32, size_t(p.ny) * sizeof(cpx<float>));
+  take(L.state, 3 * arr);
+  take(L.mean, 2 * nz * c64);
+  take(L.hist, 3 * arr);
+  take(L.hmean, 2 * nz * c64);
+  take(L.dw, arr);
+  take(L.dphi, arr);
+  take(L.A, 8 * size_t(g.NZL) * t);
+  take(L.A2, 8 * size_t(g.NZL) * t);
+  take(L.B, 8 * nz * size_t(p.ny) * size_t(g.Hx) * t);
+  take(L.C, 8 * size_t(g.P) * tr);
+  take(L.R, 8 * arr);
+  take(L.D3, 3 * arr);
+  take(L.S3, 3 * arr);
+  take(L.Q, arr);
+  take(L.DQ, arr);
+  take(L.T1, arr);
+  take(L.T2, arr);
+  take(L.lapc, arr);
+  take(L.lapphi, arr);
+  take(L.lapom, arr);
+  take(L.psi, arr);
+  take(L.lappsi, arr);
+  take(L.G, 3 * arr);
+  take(L.dmean, 2 * nz * c64);
+  take(L.d2mean, 2 * nz * c64);
+  take(L.gmean, 2 * nz * c64);
+  take(L.xwm, 2 * nz * sizeof(double));
+  size_t wb = 0;
+  psms_wall_workspace_bytes(p.nc, g.NL, &wb);
+  take(L.wall, wb);
+  L.total = off;
+  return L;
+}
+
+int chan_validate(const psms_channel_params* p) {
+  if (!p) return fail(PSMS_E_INVAL, "params is NULL");
+  if (p->precision != PSMS_FP64 && p->precision != PSMS_MIXED) return fail(PSMS_E_INVAL, "precision");
+  if (!psms::supported_n(p->nx) || !psms::supported_n(p->ny))
+    return fail(PSMS_E_NOTSUP, "nx, ny must be one of 8 12 16 24 32 48 64 96 128 192 256");
+  if (!psms::supported_nc(p->nc)) return fail(PSMS_E_NOTSUP, "nc must be one of 4 6 8 12 16 24 32 48 64 96 128");
+  if (!(p->lx > 0) || !(p->ly > 0) || !(p->re > 0) || !(p->we > 0) || !(p->ch > 0) || !(p->pe > 0) || !(p->dt > 0) ||
+      !(p->s >= 0) || !std::isfinite(p->forcing))
+    return fail(PSMS_E_INVAL, "lx, ly, re, we, ch, pe, dt must be > 0, s >= 0, forcing finite");
+  const double s = (p->s > 0.0) ? p->s : std::sqrt(4.0 * p->pe / (p->ch * p->ch * p->dt));
+  if (s * s < 4.0 * p->pe / (p->ch * p->ch * p->dt) * (1.0 - 1e-12))
+    return fail(PSMS_E_INVAL, "s^2 < 4 Pe / (Ch^2 dt): the CH operator has no real factors");
+  return PSMS_OK;
+}
+
+}  // namespace
+
+struct psms_channel {
+  psms_channel_params p;
+  psms::ChanGeom g;
+  psms::ChanCoef coef;
+  ChanLayout lay;
+  char* ws;
+  hipStream_t stream;
+  double a_fac, b_fac;
+  int nstep;
+  int have_state;
+  template <typename X>
+  X* at(size_t off) const {
+    return reinterpret_cast<X*>(ws + off);
+  }
+};
+
+namespace {
+
+template <typename T>
+const cpx<T>* chan_tw(const psms_channel* c, bool x) {
+  if (std::is_same<T, double>::value)
+    return reinterpret_cast<const cpx<T>*>(c->ws + (x ? c->lay.twx64 : c->lay.twy64));
+  return reinterpret_cast<const cpx<T>*>(c->ws + (x ? c->lay.twx32 : c->lay.twy32));
+}
+
+// physical [nf][z][y][x] (T) -> band [nf][n][line] (T): x rows, y lines (1/(nx ny)), DCT-I
+template <typename T>
+hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf) {
+  const psms::ChanGeom& g = c->g;
+  const long long nz = g.nc + 1;
+  cpx<T>* B = c->at<cpx<T>>(c->lay.B);
+  cpx<T>* A2 = c->at<cpx<T>>(c->lay.A2);
+  psms::RowArgs ra{};
+  ra.nrows = nz * g.ny;
+  ra.n_in = g.nx;
+  ra.n_out = g.Hx;
+  ra.in_fstride = g.P;
+  ra.out_fstride = nz * g.ny * g.Hx;
+  ra.scale = 1.0;
+  hipError_t e = psms::launch_rows<T>(g.nx, -1, phys, B, chan_tw<T>(c, true), ra, nf, c->stream);
+  if (e != hipSuccess) return e;
+  psms::LineArgs la{};
+  la.n_in = g.ny;
+  la.n_out = g.Cy;
+  la.inner = g.Hx;
+  la.nlines = nz * g.Hx;
+  la.in_fstride = nz * g.ny * g.Hx;
+  la.out_fstride = g.NZL;
+  la.fmap = 0x76543210u;
+  la.dmask = 0;
+  la.scale = 1.0 / (double(g.nx) * double(g.ny));
+  e = psms::launch_lines<T>(g.ny, -1, B, A2, chan_tw<T>(c, false), la, nf, c->stream);
+  for (int f = 0; f < nf && e == hipSuccess; ++f)
+    e = psms::launch_dct<T>(g.nc, A2 + f * g.NZL, band + f * g.NZL, g.NL, +1, c->stream);
+  return e;
+}
+
+// band [nf][n][line] (T) -> physical [nf][z][y][x] (T)
+template <typename T>
+hipError_t chan_inverse(psms_channel* c, const cpx<T>* band, T* phys, int nf) {
+  const psms::ChanGeom& g = c->g;
+  const long long nz = g.nc + 1;
+  cpx<T>* B = c->at<cpx<T>>(c->lay.B);
+  cpx<T>* A2 = c->at<cpx<T>>(c->lay.A2);
+  hipError_t e = hipSuccess;
+  for (int f = 0; f < nf && e == hipSuccess; ++f)
+    e = psms::launch_dct<T>(g.nc, band + f * g.NZL, A2 + f * g.NZL, g.NL, -1, c->stream);
+  if (e != hipSuccess) return e;
+  psms::LineArgs la{};
+  la.n_in = g.Cy;
+  la.n_out = g.ny;
+  la.inner = g.Hx;
+  la.nlines = nz * g.Hx;
+  la.in_fstride = g.NZL;
+  la.out_fstride = nz * g.ny * g.Hx;
+  la.fmap = 0x76543210u;
+  la.dmask = 0;
+  la.scale = 1.0;
+  e = psms::launch_lines<T>(g.ny, +1, A2, B, chan_tw<T>(c, false), la, nf, c->stream);
+  if (e != hipSuccess) return e;
+  psms::RowArgs ra{};
+  ra.nrows = nz * g.ny;
+  ra.n_in = g.Hx;
+  ra.n_out = g.nx;
+  ra.in_fstride = nz * g.ny * g.Hx;
+  ra.out_fstride = g.P;
+  ra.scale = 1.0;
+  return psms::launch_rows<T>(g.nx, +1, B, phys, chan_tw<T>(c, true), ra, nf, c->stream);
+}
+
+template <typename T>
+hipError_t chan_step_once(psms_channel* c) {
+  const psms::ChanGeom& g = c->g;
+  const ChanLayout& L = c->lay;
+  hipStream_t st = c->stream;
+  const int nc = g.nc;
+  const long long nl = g.NL;
+  auto C64 = [&](size_t off) { return c->at<cpx<double>>(off); };
+  cpx<double>* om = C64(L.state);
+  cpx<double>* w = om + g.NZL;
+  cpx<double>* phi = w + g.NZL;
+  const double* kx = c->at<double>(L.kx);
+  const double* ky = c->at<double>(L.ky);
+  cpx<double>* R = C64(L.R);
+  hipError_t e;
+#define PSMS_TRY(x) \
+  if ((e = (x)) != hipSuccess) return e
+  // 1-2. fields and the inverse transforms
+  PSMS_TRY(psms::launch_chebd(w, C64(L.dw), nc, nl, st));
+  PSMS_TRY(psms::launch_chebd(phi, C64(L.dphi), nc, nl, st));
+  PSMS_TRY(psms::launch_ch_fields<T>(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky,
+                                     c->at<cpx<T>>(L.A), st));
+  PSMS_TRY(chan_inverse<T>(c, c->at<cpx<T>>(L.A), c->at<T>(L.C), 7));
+  // 3-4. products and the forward transforms, 2/3 rule in x, y and z
+  PSMS_TRY(psms::launch_ch_products<T>(g, c->at<T>(L.C), c->coef.csig, st));
+  PSMS_TRY(chan_forward<T>(c, c->at<T>(L.C), c->at<cpx<T>>(L.A), 8));
+  PSMS_TRY(psms::launch_ch_promote<T>(g, c->at<cpx<T>>(L.A), R, st));
+  // 5. S = div T, and the wall-normal derivatives the right-hand sides need
+  cpx<double>* D3 = C64(L.D3);
+  PSMS_TRY(psms::launch_chebd(R + 4 * g.NZL, D3, nc, nl, st));              // D T_xz
+  PSMS_TRY(psms::launch_chebd(R + 5 * g.NZL, D3 + g.NZL, nc, nl, st));      // D T_yz
+  PSMS_TRY(psms::launch_chebd(R + 2 * g.NZL, D3 + 2 * g.NZL, nc, nl, st));  // D T_zz
+  PSMS_TRY(psms::launch_ch_s(g, R, D3, D3 + g.NZL, D3 + 2 * g.NZL, kx, ky, C64(L.S3), C64(L.Q), st));
+  PSMS_TRY(psms::launch_chebd(C64(L.Q), C64(L.DQ), nc, nl, st));
+  auto lap = [&](const cpx<double>* a, cpx<double>* out) -> hipError_t {
+    hipError_t r = psms::launch_chebd(a, C64(L.T1), nc, nl, st);
+    if (r == hipSuccess) r = psms::launch_chebd(C64(L.T1), C64(L.T2), nc, nl, st);
+    if (r == hipSuccess) r = psms::launch_ch_lap(g, a, C64(L.T2), kx, ky, out, st);
+    return r;
+  };
+  PSMS_TRY(lap(R + 7 * g.NZL, C64(L.lapc)));
+  PSMS_TRY(lap(phi, C64(L.lapphi)));
+  PSMS_TRY(lap(om, C64(L.lapom)));
+  PSMS_TRY(lap(w, C64(L.psi)));
+  PSMS_TRY(lap(C64(L.psi), C64(L.lappsi)));
+  PSMS_TRY(psms::launch_chebd(C64(L.mean), C64(L.dmean), nc, 2, st));
+  PSMS_TRY(psms::launch_chebd(C64(L.dmean), C64(L.d2mean), nc, 2, st));
+  // 6. Adams-Bashforth, Crank-Nicolson / implicit Euler right-hand sides
+  c->coef.ab1 = (c->nstep == 0) ? 1 : 0;
+  psms::ChanAssembleArgs aa{};
+  aa.s3 = C64(L.S3);
+  aa.dq = C64(L.DQ);
+  aa.R = R;
+  aa.lapc = C64(L.lapc);
+  aa.phi = phi;
+  aa.lapphi = C64(L.lapphi);
+  aa.om = om;
+  aa.lapom = C64(L.lapom);
+  aa.psi = C64(L.psi);
+  aa.lappsi = C64(L.lappsi);
+  aa.kx = kx;
+  aa.ky = ky;
+  aa.hist = C64(L.hist);
+  aa.g = C64(L.G);
+  aa.mean = C64(L.mean);
+  aa.d2mean = C64(L.d2mean);
+  aa.hmean = C64(L.hmean);
+  aa.gmean = C64(L.gmean);
+  PSMS_TRY(psms::launch_ch_assemble(g, c->coef, aa, st));
+  // the wall-normal solves of every (kx, ky) pair, and the mean flow
+  psms_wall_args wa{};
+  wa.nc = nc;
+  wa.nlines = nl;
+  wa.d_kx = kx;
+  wa.d_ky = ky;
+  wa.beta_ns = c->coef.beta;
+  wa.beta_a = c->a_fac;
+  wa.beta_b = c->b_fac;
+  wa.d_g_om = reinterpret_cast<const double*>(C64(L.G));
+  wa.d_g_w = reinterpret_cast<const double*>(C64(L.G) + g.NZL);
+  wa.d_g_phi = reinterpret_cast<const double*>(C64(L.G) + 2 * g.NZL);
+  wa.d_om = reinterpret_cast<double*>(om);
+  wa.d_w = reinterpret_cast<double*>(w);
+  wa.d_phi = reinterpret_cast<double*>(phi);
+  wa.d_u = reinterpret_cast<double*>(C64(L.S3));
+  wa.d_v = reinterpret_cast<double*>(C64(L.S3) + g.NZL);
+  size_t wb = 0;
+  psms_wall_workspace_bytes(nc, nl, &wb);
+  const int r = psms_wall_solve(&wa, c->ws + L.wall, wb, st);
+  if (r) return hipErrorLaunchFailure;
+  const cpx<double> z0 = {0.0, 0.0};
+  PSMS_TRY(psms::launch_helm(C64(L.gmean), C64(L.mean), c->at<double>(L.xwm), nc, 2, nullptr, c->coef.beta,
+                             nullptr, nullptr, 0, nullptr, z0, z0, st));
+#undef PSMS_TRY
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int psms_channel_workspace_bytes(const psms_channel_params* p, size_t* bytes) {
+  if (!bytes) return fail(PSMS_E_INVAL, "bytes is NULL");
+  const int r = chan_validate(p);
+  if (r) return r;
+  *bytes = chan_layout(*p).total;
+  return PSMS_OK;
+}
+
+int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* d_workspace, size_t bytes,
+                        void* stream) {
+  if (!out) return fail(PSMS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int r = chan_validate(p);
+  if (r) return r;
+  const ChanLayout lay = chan_layout(*p);
+  if (!d_workspace || !aligned(d_workspace)) return fail(PSMS_E_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  if (bytes < lay.total) return fail(PSMS_E_WORKSPACE, "workspace too small: need " + std::to_string(lay.total));
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(PSMS_E_DEVICE, "no HIP device available");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(PSMS_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  psms_channel* c = new psms_channel();
+  c->p = *p;
+  c->g = chan_geom(*p);
+  c->lay = lay;
+  c->ws = static_cast<char*>(d_workspace);
+  c->stream = static_cast<hipStream_t>(stream);
+  const double s = (p->s > 0.0) ? p->s : std::sqrt(4.0 * p->pe / (p->ch * p->ch * p->dt));
+  const double ab = p->pe / (p->dt * p->ch * p->ch);
+  const double d = std::sqrt(std::max(s * s - 4.0 * ab, 0.0));
+  c->a_fac = 0.5 * (s - d);
+  c->b_fac = 0.5 * (s + d);
+  c->coef.re = p->re;
+  c->coef.beta = 2.0 * p->re / p->dt;
+  c->coef.inv_pe = 1.0 / p->pe;
+  c->coef.e_coef = (1.0 + s * p->ch * p->ch) / p->pe;
+  c->coef.g_phi_scale = ab;
+  c->coef.dt = p->dt;
+  c->coef.forcing = p->forcing;
+  c->coef.csig = 3.0 / std::sqrt(8.0) * p->ch / p->we;
+  c->coef.ab1 = 1;
+  c->nstep = 0;
+  c->have_state = 0;
+  // line wavenumbers (kx = 2 pi m / lx, ky = 2 pi m / ly over the band) and twiddles
+  const psms::ChanGeom& g = c->g;
+  std::vector<double> hkx(g.NL), hky(g.NL);
+  for (int iy = 0; iy < g.Cy; ++iy)
+    for (int ix = 0; ix < g.Hx; ++ix) {
+      const int my = (iy <= g.Ky) ? iy : iy - g.Cy;
+      hkx[size_t(iy) * g.Hx + ix] = 2.0 * M_PI / p->lx * ix;
+      hky[size_t(iy) * g.Hx + ix] = 2.0 * M_PI / p->ly * my;
+    }
+  auto tws = [](int n, std::vector<cpx<double>>& t64, std::vector<cpx<float>>& t32) {
+    t64.resize(n);
+    t32.resize(n);
+    for (int m = 0; m < n; ++m) {
+      const double a = -2.0 * M_PI * double(m) / double(n);
+      t64[m] = cpx<double>{std::cos(a), std::sin(a)};
+      t32[m] = cpx<float>{float(t64[m].re), float(t64[m].im)};
+    }
+  };
+  std::vector<cpx<double>> x64, y64;
+  std::vector<cpx<float>> x32, y32;
+  tws(p->nx, x64, x32);
+  tws(p->ny, y64, y32);
+  hipStream_t st = c->stream;
+  hipError_t e = hipMemcpyAsync(c->ws + lay.kx, hkx.data(), g.NL * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.ky, hky.data(), g.NL * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twx64, x64.data(), x64.size() * sizeof(cpx<double>), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twx32, x32.data(), x32.size() * sizeof(cpx<float>), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twy64, y64.data(), y64.size() * sizeof(cpx<double>), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twy32, y32.data(), y32.size() * sizeof(cpx<float>), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "channel_create");
+  }
+  *out = c;
+  return PSMS_OK;
+}
+
+int psms_channel_init_state(psms_channel* c, const double* d_u, const double* d_v, const double* d_w,
+                            const double* d_phi) {
+  if (!c || !d_u || !d_v || !d_w || !d_phi) return fail(PSMS_E_INVAL, "NULL argument");
+  const psms::ChanGeom& g = c->g;
+  const ChanLayout& L = c->lay;
+  // FP64 forward chain of the 4 fields through the step's buffers: in MIXED the
+  // physical, y-expanded and band buffers hold 8 FP32 fields, i.e. 4 FP64 ones
+  double* C = c->at<double>(L.C);
+  cpx<double>* A = c->at<cpx<double>>(L.R);
+  hipError_t e = hipSuccess;
+  const double* src[4] = {d_u, d_v, d_w, d_phi};
+  for (int f = 0; f < 4 && e == hipSuccess; ++f)
+    e = hipMemcpyAsync(C + f * g.P, src[f], size_t(g.P) * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = chan_forward<double>(c, C, A, 4);
+  if (e == hipSuccess)
+    e = psms::launch_ch_init(g, A, c->at<double>(L.kx), c->at<double>(L.ky), c->at<cpx<double>>(L.state),
+                             c->at<cpx<double>>(L.state) + g.NZL, c->at<cpx<double>>(L.state) + 2 * g.NZL,
+                             c->at<cpx<double>>(L.mean), c->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(c->ws + L.hist, 0, size_t(3 * g.NZL) * sizeof(cpx<double>), c->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(c->ws + L.hmean, 0, size_t(2 * (g.nc + 1)) * sizeof(cpx<double>), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "channel_init_state");
+  c->nstep = 0;
+  c->have_state = 1;
+  return PSMS_OK;
+}
+
+int psms_channel_set_state(psms_channel* c, const double* d_state, const double* d_mean, const double* d_hist,
+                           const double* d_hmean, int32_t nstep) {
+  if (!c || !d_state || !d_mean) return fail(PSMS_E_INVAL, "NULL argument");
+  if (nstep < 0) return fail(PSMS_E_INVAL, "nstep must be >= 0");
+  if (nstep > 0 && (!d_hist || !d_hmean)) return fail(PSMS_E_INVAL, "nstep > 0 needs the history");
+  const psms::ChanGeom& g = c->g;
+  const ChanLayout& L = c->lay;
+  const size_t sz = size_t(3 * g.NZL) * sizeof(cpx<double>);
+  hipError_t e = hipMemcpyAsync(c->ws + L.state, d_state, sz, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = psms::launch_ch_mean_io(g, reinterpret_cast<const cpx<double>*>(d_mean), c->at<cpx<double>>(L.mean), +1,
+                                c->stream);
+  if (e == hipSuccess) {
+    if (nstep > 0) {
+      e = hipMemcpyAsync(c->ws + L.hist, d_hist, sz, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess)
+        e = psms::launch_ch_mean_io(g, reinterpret_cast<const cpx<double>*>(d_hmean), c->at<cpx<double>>(L.hmean),
+                                    +1, c->stream);
+    } else {
+      e = hipMemsetAsync(c->ws + L.hist, 0, sz, c->stream);
+      if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.hmean, 0, 2 * size_t(g.nc + 1) * sizeof(cpx<double>), c->stream);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "channel_set_state");
+  c->nstep = nstep;
+  c->have_state = 1;
+  return PSMS_OK;
+}
+
+int psms_channel_step(psms_channel* c, int32_t nsteps) {
+  if (!c) return fail(PSMS_E_INVAL, "NULL context");
+  if (nsteps < 0) return fail(PSMS_E_INVAL, "nsteps must be >= 0");
+  if (!c->have_state) return fail(PSMS_E_STATE, "step before init_state / set_state");
+  for (int i = 0; i < nsteps; ++i) {
+    const hipError_t e = (c->p.precision == PSMS_MIXED) ? chan_step_once<float>(c) : chan_step_once<double>(c);
+    if (e != hipSuccess) return hip_fail(e, "channel_step");
+    ++c->nstep;
+  }
+  return PSMS_OK;
+}
+
+int psms_channel_get_state(psms_channel* c, double* d_state, double* d_mean, double* d_hist, double* d_hmean) {
+  if (!c || !d_state || !d_mean) return fail(PSMS_E_INVAL, "NULL argument");
+  if (!c->have_state) return fail(PSMS_E_STATE, "no state");
+  const psms::ChanGeom& g = c->g;
+  const ChanLayout& L = c->lay;
+  const size_t sz = size_t(3 * g.NZL) * sizeof(cpx<double>);
+  hipError_t e = hipMemcpyAsync(d_state, c->ws + L.state, sz, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = psms::launch_ch_mean_io(g, c->at<cpx<double>>(L.mean), reinterpret_cast<cpx<double>*>(d_mean), -1,
+                                c->stream);
+  if (e == hipSuccess && d_hist) e = hipMemcpyAsync(d_hist, c->ws + L.hist, sz, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && d_hmean)
+    e = psms::launch_ch_mean_io(g, c->at<cpx<double>>(L.hmean), reinterpret_cast<cpx<double>*>(d_hmean), -1,
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(e, "channel_get_state");
+  return PSMS_OK;
+}
+
+int psms_channel_destroy(psms_channel* c) {
+  delete c;
   return PSMS_OK;
 }
 

@@ -1,0 +1,79 @@
+// Launchers of the pointwise and per-mode kernels of the channel step (Sec. 2.2).
+// Spectral arrays are [field][n][line], line = iy * Hx + ix over the 2/3 band
+// (ky = 0..Ky, -Ky..-1; kx = 0..Kx), n the Chebyshev index 0..nc; physical
+// arrays are [field][z][y][x] at the Chebyshev-Gauss-Lobatto points in z.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_engine.hpp"
+
+namespace psms {
+
+// Geometry and coefficients of one channel step.
+struct ChanGeom {
+  int nx, ny, nc;
+  int Kx, Hx, Ky, Cy, Kz;  // band cut-offs; Kz: Chebyshev modes kept in the products
+  long long NL;            // lines Cy * Hx
+  long long NZL;           // (nc + 1) * NL
+  long long P;             // (nc + 1) * ny * nx physical points
+};
+
+struct ChanCoef {
+  double re, beta;     // Re_tau and 2 Re / dt
+  double inv_pe, e_coef, g_phi_scale, dt, forcing;
+  double csig;
+  int ab1;
+};
+
+// the 7 spectral fields u, v, w, phi, i kx phi, i ky phi, D phi (precision T)
+template <typename T>
+hipError_t launch_ch_fields(const ChanGeom& g, const cpx<double>* om, const cpx<double>* w, const cpx<double>* phi,
+                            const cpx<double>* dw, const cpx<double>* dphi, const cpx<double>* mean, const double* kx,
+                            const double* ky, cpx<T>* out, hipStream_t st);
+// pointwise products, 7 physical fields in, 8 out (in place, [8][P])
+template <typename T>
+hipError_t launch_ch_products(const ChanGeom& g, T* f, double csig, hipStream_t st);
+// 8 transformed products (precision T) -> FP64 with Chebyshev modes n > Kz zeroed
+template <typename T>
+hipError_t launch_ch_promote(const ChanGeom& g, const cpx<T>* in, cpx<double>* out, hipStream_t st);
+// S_x, S_y, S_z and Q = i kx S_x + i ky S_y from the products and D T_xz, D T_yz, D T_zz
+hipError_t launch_ch_s(const ChanGeom& g, const cpx<double>* R, const cpx<double>* dxz, const cpx<double>* dyz,
+                       const cpx<double>* dzz, const double* kx, const double* ky, cpx<double>* s3, cpx<double>* q,
+                       hipStream_t st);
+// out = D2 a - k^2 a
+hipError_t launch_ch_lap(const ChanGeom& g, const cpx<double>* a, const cpx<double>* d2a, const double* kx,
+                         const double* ky, cpx<double>* out, hipStream_t st);
+// H_omega, H_w, S_phi; Adams-Bashforth with the history (then overwritten);
+// the right-hand sides g_om, g_w, g_phi of the wall-normal solves; the mean
+// lines' H and right-hand sides.
+struct ChanAssembleArgs {
+  const cpx<double>* s3;      // [3][NZL]
+  const cpx<double>* dq;      // D Q
+  const cpx<double>* R;       // products, field 6 = a, 7 = c
+  const cpx<double>* lapc;    // lap c
+  const cpx<double>* phi;     // phi^n
+  const cpx<double>* lapphi;  // lap phi^n
+  const cpx<double>* om;      // omega^n
+  const cpx<double>* lapom;   // lap omega^n
+  const cpx<double>* psi;     // lap w^n
+  const cpx<double>* lappsi;  // lap psi
+  const double* kx;
+  const double* ky;
+  cpx<double>* hist;          // [3][NZL] H_omega, H_w, S_phi of the previous step (in/out)
+  cpx<double>* g;             // [3][NZL] g_om, g_w, g_phi
+  const cpx<double>* mean;    // [nc+1][2] U, V
+  const cpx<double>* d2mean;  // [nc+1][2]
+  cpx<double>* hmean;         // [nc+1][2] (in/out)
+  cpx<double>* gmean;         // [nc+1][2]
+};
+hipError_t launch_ch_assemble(const ChanGeom& g, const ChanCoef& c, const ChanAssembleArgs& a, hipStream_t st);
+// initial state from the 4 transformed physical fields u, v, w, phi ([4][NZL], FP64)
+hipError_t launch_ch_init(const ChanGeom& g, const cpx<double>* U4, const double* kx, const double* ky,
+                          cpx<double>* om, cpx<double>* w, cpx<double>* phi, cpx<double>* mean, hipStream_t st);
+// zero Chebyshev modes n > kz of nf fields [nf][NZL] (FP64)
+hipError_t launch_ch_zcut(const ChanGeom& g, cpx<double>* a, int nf, int kz, hipStream_t st);
+// mean lines: [2][nc+1] (caller) <-> [nc+1][2] (internal); dir > 0 copies into internal
+hipError_t launch_ch_mean_io(const ChanGeom& g, const cpx<double>* in, cpx<double>* out, int dir, hipStream_t st);
+
+}  // namespace psms

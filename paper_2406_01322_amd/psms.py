@@ -50,11 +50,26 @@ class WallArgs(ctypes.Structure):
                 ("d_v", ctypes.c_void_p)]
 
 
+class ChannelParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nc", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("re", ctypes.c_double), ("we", ctypes.c_double),
+                ("ch", ctypes.c_double), ("pe", ctypes.c_double), ("dt", ctypes.c_double), ("s", ctypes.c_double),
+                ("forcing", ctypes.c_double)]
+
+
 DIRICHLET, NEUMANN = 1, 2
 
 _lib = None
 
 _SIGS = {
+    "psms_channel_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ChannelParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "psms_channel_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ChannelParams),
+                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "psms_channel_init_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "psms_channel_set_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int32]),
+    "psms_channel_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "psms_channel_get_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "psms_channel_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "psms_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
     "psms_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Params), ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p]),
@@ -552,3 +567,78 @@ def objective(phi0, we, u0, cfg):
     """Differentiable J(phi0, We): cfg holds n, re, ch, pe, dt, nsteps (and s, precision,
     seg_len).  phi0 [n,n,n] and we (0-d) are float64 tensors on the GPU."""
     return _objective_function().apply(phi0, we, u0, cfg)
+
+
+# ---------------------------------------------------------------------------
+# the channel step
+# ---------------------------------------------------------------------------
+
+class Channel:
+    """One channel NS+CH context (x, y periodic, Chebyshev in z between walls).
+
+    Spectral arrays: complex128 [..., nc+1, 2 Ky + 1, Kx + 1] (Chebyshev index,
+    ky in band order 0..Ky, -Ky..-1, kx = 0..Kx); mean lines [2, nc+1] (U, V);
+    physical fields float64 [nc+1, ny, nx] at z_j = cos(pi j / nc).
+    """
+
+    def __init__(self, nx, ny, nc, re, we, ch, pe, dt, s=0.0, precision="fp64", lx=4 * 3.141592653589793,
+                 ly=2 * 3.141592653589793, forcing=1.0, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        prec = {"fp64": FP64, "mixed": MIXED}[precision]
+        self.params = ChannelParams(int(nx), int(ny), int(nc), prec, float(lx), float(ly), float(re), float(we),
+                                    float(ch), float(pe), float(dt), float(s or 0.0), float(forcing))
+        self.nx, self.ny, self.nc = int(nx), int(ny), int(nc)
+        self.band = (self.nc + 1, 2 * ((self.ny - 1) // 3) + 1, (self.nx - 1) // 3 + 1)
+        self.device = torch.device(device)
+        b = ctypes.c_size_t(0)
+        _check(lib().psms_channel_workspace_bytes(ctypes.byref(self.params), ctypes.byref(b)))
+        self.workspace = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().psms_channel_create(ctypes.byref(h), ctypes.byref(self.params), _ptr(self.workspace),
+                                         int(b.value), ctypes.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().psms_channel_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, x, dtype):
+        t = self.torch
+        return x.to(device=self.device, dtype=dtype).contiguous()
+
+    def init_state(self, u, v, w, phi):
+        t = self.torch
+        f = [self._dev(x, t.float64) for x in (u, v, w, phi)]
+        _check(lib().psms_channel_init_state(self.h, *[_ptr(x) for x in f]))
+
+    def set_state(self, state, mean, hist=None, hmean=None, nstep=0):
+        t = self.torch
+        st = self._dev(state, t.complex128)
+        mn = self._dev(mean, t.complex128)
+        hs = self._dev(hist, t.complex128) if hist is not None else None
+        hm = self._dev(hmean, t.complex128) if hmean is not None else None
+        _check(lib().psms_channel_set_state(self.h, _ptr(st), _ptr(mn), _ptr(hs) if hs is not None else None,
+                                            _ptr(hm) if hm is not None else None, int(nstep)))
+        self._keep = (st, mn, hs, hm)
+
+    def step(self, nsteps=1):
+        _check(lib().psms_channel_step(self.h, int(nsteps)))
+
+    def get_state(self, with_history=False):
+        t = self.torch
+        st = t.empty((3,) + self.band, dtype=t.complex128, device=self.device)
+        mn = t.empty((2, self.nc + 1), dtype=t.complex128, device=self.device)
+        hs = t.empty_like(st) if with_history else None
+        hm = t.empty_like(mn) if with_history else None
+        _check(lib().psms_channel_get_state(self.h, _ptr(st), _ptr(mn), _ptr(hs) if hs is not None else None,
+                                            _ptr(hm) if hm is not None else None))
+        return (st, mn, hs, hm) if with_history else (st, mn)

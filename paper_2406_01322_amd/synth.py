@@ -178,3 +178,113 @@ def batch_cases(nbox: int = 96, seed: int = 4, sizes=(32, 48, 64, 96)):
         phi = drops_phi(n, c, 0.4, ch)
         out.append((p, u, phi))
     return out
+
+
+# ---------------------------------------------------------------------------
+# the channel: x, y periodic (lengths lx, ly), z in [-1, 1] at the
+# Chebyshev-Gauss-Lobatto points z_j = cos(pi j / nc)
+# ---------------------------------------------------------------------------
+
+def channel_grid(nx: int, ny: int, nc: int, lx: float, ly: float):
+    """Coordinates X, Y, Z of shape (nc+1, ny, nx)."""
+    z = np.cos(math.pi * np.arange(nc + 1) / nc)
+    x = grid_coords(nx, lx)
+    y = grid_coords(ny, ly)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X, Y, Z
+
+
+def channel_perturbation(X, Y, Z, lx: float, ly: float, rng: np.random.Generator, mmax: int, amp: float):
+    """Divergence-free velocity vanishing at the walls with its normal derivative:
+    the curl of A = (f(z) r_x(x, y), f(z) r_y(x, y), 0), f = (1 - z^2)^2, with r_x,
+    r_y random-phase sums of the modes 1 <= |m_x|, |m_y| <= mmax; scaled so that the
+    largest rms over an (x, y) plane of the streamwise component is `amp`."""
+    f = (1.0 - Z ** 2) ** 2
+    fp = -4.0 * Z * (1.0 - Z ** 2)
+    X2, Y2 = X[0], Y[0]          # r_x, r_y depend on (x, y) only
+    rx = np.zeros_like(X2)
+    ry = np.zeros_like(X2)
+    drx_dy = np.zeros_like(X2)
+    dry_dx = np.zeros_like(X2)
+    for mx in range(-mmax, mmax + 1):
+        for my in range(-mmax, mmax + 1):
+            if abs(mx) < 1 or abs(my) < 1:
+                continue
+            kx, ky = TWO_PI * mx / lx, TWO_PI * my / ly
+            ax, ay = rng.standard_normal(2)
+            px, py = rng.uniform(0.0, TWO_PI, 2)
+            sx = kx * X2 + ky * Y2 + px
+            sy = kx * X2 + ky * Y2 + py
+            rx += ax * np.cos(sx)
+            drx_dy += -ax * ky * np.sin(sx)
+            ry += ay * np.cos(sy)
+            dry_dx += -ay * kx * np.sin(sy)
+    u = -fp * ry[None]
+    v = fp * rx[None]
+    w = f * (dry_dx - drx_dy)[None]
+    scale = amp / np.max(np.sqrt(np.mean(u * u, axis=(1, 2))))
+    return u * scale, v * scale, w * scale
+
+
+def channel_drops(X, Y, Z, lx: float, ly: float, rng: np.random.Generator, ndrops: int, radius: float, ch: float):
+    """phi = max_i tanh((R - d_i)/(sqrt(2) Ch)), d_i the distance to centre i with
+    periodic images in x and y; centres drawn uniformly with |z_c| <= 1 - R -
+    4 sqrt(2) Ch and pairwise distances >= 2R + 8 sqrt(2) Ch (rejection)."""
+    zmax = 1.0 - radius - 4.0 * math.sqrt(2.0) * ch
+    sep = 2.0 * radius + 8.0 * math.sqrt(2.0) * ch
+    cs = []
+    tries = 0
+    while len(cs) < ndrops:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place the drops")
+        c = np.array([rng.uniform(0, lx), rng.uniform(0, ly), rng.uniform(-zmax, zmax)])
+        ok = True
+        for d in cs:
+            dx = abs(c[0] - d[0]); dx = min(dx, lx - dx)
+            dy = abs(c[1] - d[1]); dy = min(dy, ly - dy)
+            if math.sqrt(dx * dx + dy * dy + (c[2] - d[2]) ** 2) < sep:
+                ok = False
+                break
+        if ok:
+            cs.append(c)
+    phi = np.full(X.shape, -1.0)
+    w = math.sqrt(2.0) * ch
+    # beyond R + 20 w from a centre, tanh((R - d)/w) rounds to -1 in FP64: only
+    # the points inside that box are evaluated
+    reach = radius + 20.0 * w
+    x1, y1, z1 = X[0, 0, :], Y[0, :, 0], Z[:, 0, 0]
+    for c in cs:
+        dx = np.abs(x1 - c[0]); dx = np.minimum(dx, lx - dx)
+        dy = np.abs(y1 - c[1]); dy = np.minimum(dy, ly - dy)
+        dz = np.abs(z1 - c[2])
+        ix, iy, iz = np.nonzero(dx < reach)[0], np.nonzero(dy < reach)[0], np.nonzero(dz < reach)[0]
+        sub = np.ix_(iz, iy, ix)
+        d = np.sqrt(dx[ix][None, None, :] ** 2 + dy[iy][None, :, None] ** 2 + dz[iz][:, None, None] ** 2)
+        phi[sub] = np.maximum(phi[sub], np.tanh((radius - d) / w))
+    return phi
+
+
+def channel_case(name: str):
+    """(params, u, v, w, phi): laminar profile U = Re (1 - z^2)/2 (wall units,
+    -dP/dx = 1) plus a wall-bounded random perturbation of 10% of the centreline
+    velocity, and drops.  params: nx, ny, nc, lx, ly, re, we, ch, pe, dt.
+      chan_small: 16 x 12 x 17, Re_tau 20, 2 drops R = 0.4, Ch 0.1 (seed 11);
+      chan_mid:   32 x 24 x 33, Re_tau 50, 4 drops R = 0.3, Ch 0.05 (seed 12);
+      chan_256:   256 x 128 x 129 on 4 pi x 2 pi x 2, Re_tau 150, 64 drops R = 0.2,
+                  Ch 0.02, We 3, Pe 50, dt 1e-4 (seed 3)."""
+    table = {
+        "chan_small": (dict(nx=16, ny=12, nc=16, re=20.0, we=1.0, ch=0.1, pe=10.0, dt=1e-3), 2, 0.4, 11),
+        "chan_mid": (dict(nx=32, ny=24, nc=32, re=50.0, we=2.0, ch=0.05, pe=20.0, dt=5e-4), 4, 0.3, 12),
+        "chan_256": (dict(nx=256, ny=128, nc=128, re=150.0, we=3.0, ch=0.02, pe=50.0, dt=1e-4), 64, 0.2, 3),
+    }
+    p, nd, radius, seed = table[name]
+    p = dict(p, lx=4.0 * math.pi, ly=2.0 * math.pi)
+    rng = np.random.default_rng(seed)
+    X, Y, Z = channel_grid(p["nx"], p["ny"], p["nc"], p["lx"], p["ly"])
+    mmax = min(4, (p["nx"] - 1) // 3, (p["ny"] - 1) // 3)
+    uc = p["re"] / 2.0
+    up, vp, wp = channel_perturbation(X, Y, Z, p["lx"], p["ly"], rng, mmax, 0.1 * uc)
+    u = uc * (1.0 - Z ** 2) + up
+    phi = channel_drops(X, Y, Z, p["lx"], p["ly"], rng, nd, radius, p["ch"])
+    return p, u, vp, wp, phi
