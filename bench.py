@@ -227,6 +227,35 @@ def bench_wall_solve(reps=20):
             "lines_per_s": nl / (ms * 1e-3)}
 
 
+def bench_channel(steps=20, warmup=2):
+    """The channel step at 256 x 128 x 129 (4 pi x 2 pi x 2, Re_tau 150, 64 drops R = 0.2,
+    Ch 0.02, We 3, Pe 50, dt 1e-4), MIXED and FP64: ms per step (HIP events on the
+    stream) after `warmup` steps from the synthetic initial state."""
+    import torch
+    from paper_2406_01322_amd import psms, synth
+    p, u, v, w, phi = synth.channel_case("chan_256")
+    npts = (p["nc"] + 1) * p["ny"] * p["nx"]
+    out = {"grid": [p["nx"], p["ny"], p["nc"] + 1], "points": npts, "steps": steps}
+    f = [torch.from_numpy(x).cuda() for x in (u, v, w, phi)]
+    for prec in ("mixed", "fp64"):
+        c = psms.Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=prec,
+                         lx=p["lx"], ly=p["ly"])
+        c.init_state(*f)
+        c.step(warmup)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.step(steps)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[prec] = {"ms_per_step": ms, "value": npts / (ms * 1e-3)}
+        c.close()
+        del c
+    out["unit"] = "grid-points*timesteps/s"
+    return out
+
+
 def cpu_baseline(n, p, u, phi, budget_s=20.0):
     """The FP64 oracle on the host: init, then as many steps as fit in ~budget_s."""
     import numpy as np  # noqa: F401
@@ -254,7 +283,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched, adjoint and channel wall-solve measurements")
+                    help="skip the batched, adjoint, channel wall-solve and channel-step measurements")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a buffer of this many MiB 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -322,7 +351,8 @@ def main():
         out["mixed_vs_fp64_rel_l2"] = mixed_error(n, p, u, phi)
     if not args.no_forms:
         out["forms"] = {}
-        for name, fn in (("batched", bench_batch), ("adjoint", bench_adjoint), ("channel_wall_solve", bench_wall_solve)):
+        for name, fn in (("batched", bench_batch), ("adjoint", bench_adjoint), ("channel_wall_solve", bench_wall_solve),
+                         ("channel_step", bench_channel)):
             out["forms"][name] = fn()
             print("[bench] %s: %s" % (name, {k: v for k, v in out["forms"][name].items() if k != "groups"}),
                   file=sys.stderr, flush=True)
