@@ -1223,8 +1223,8 @@ namespace {
 struct ChanLayout {
   size_t kx, ky, twx64, twx32, twy64, twy32;
   size_t state, mean, hist, hmean;
-  size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, T1, T2, lapc, lapphi, lapom, psi, lappsi, G;
-  size_t dmean, d2mean, gmean, xwm, wall, total;
+  size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, lapc, lapphi, lapom, psi, lappsi, G;
+  size_t d2mean, gmean, xwm, wall, total;
 };
 
 psms::ChanGeom chan_geom(const psms_channel_params& p) {
@@ -1277,15 +1277,12 @@ ChanLayout chan_layout(const psms_channel_params& p) {
   take(L.S3, 3 * arr);
   take(L.Q, arr);
   take(L.DQ, arr);
-  take(L.T1, arr);
-  take(L.T2, arr);
   take(L.lapc, arr);
   take(L.lapphi, arr);
   take(L.lapom, arr);
   take(L.psi, arr);
   take(L.lappsi, arr);
   take(L.G, 3 * arr);
-  take(L.dmean, 2 * nz * c64);
   take(L.d2mean, 2 * nz * c64);
   take(L.gmean, 2 * nz * c64);
   take(L.xwm, 2 * nz * sizeof(double));
@@ -1437,19 +1434,15 @@ hipError_t chan_step_once(psms_channel* c) {
   PSMS_TRY(psms::launch_chebd(R + 2 * g.NZL, D3 + 2 * g.NZL, nc, nl, st));  // D T_zz
   PSMS_TRY(psms::launch_ch_s(g, R, D3, D3 + g.NZL, D3 + 2 * g.NZL, kx, ky, C64(L.S3), C64(L.Q), st));
   PSMS_TRY(psms::launch_chebd(C64(L.Q), C64(L.DQ), nc, nl, st));
-  auto lap = [&](const cpx<double>* a, cpx<double>* out) -> hipError_t {
-    hipError_t r = psms::launch_chebd(a, C64(L.T1), nc, nl, st);
-    if (r == hipSuccess) r = psms::launch_chebd(C64(L.T1), C64(L.T2), nc, nl, st);
-    if (r == hipSuccess) r = psms::launch_ch_lap(g, a, C64(L.T2), kx, ky, out, st);
-    return r;
+  auto lap = [&](const cpx<double>* a, cpx<double>* out) {   // D^2 a - k^2 a
+    return psms::launch_cheb_lap(a, out, nc, nl, kx, ky, st);
   };
   PSMS_TRY(lap(R + 7 * g.NZL, C64(L.lapc)));
   PSMS_TRY(lap(phi, C64(L.lapphi)));
   PSMS_TRY(lap(om, C64(L.lapom)));
   PSMS_TRY(lap(w, C64(L.psi)));
   PSMS_TRY(lap(C64(L.psi), C64(L.lappsi)));
-  PSMS_TRY(psms::launch_chebd(C64(L.mean), C64(L.dmean), nc, 2, st));
-  PSMS_TRY(psms::launch_chebd(C64(L.dmean), C64(L.d2mean), nc, 2, st));
+  PSMS_TRY(psms::launch_cheb_lap(C64(L.mean), C64(L.d2mean), nc, 2, nullptr, nullptr, st));
   // 6. Adams-Bashforth, Crank-Nicolson / implicit Euler right-hand sides
   c->coef.ab1 = (c->nstep == 0) ? 1 : 0;
   psms::ChanAssembleArgs aa{};

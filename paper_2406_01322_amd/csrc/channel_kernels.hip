@@ -95,21 +95,52 @@ __global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<
   }
 }
 
-// Coefficients of d/dz, one thread per line: b_nc = 0,
-// c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n for n = nc .. 1 (c_0 = 2, else 1).
+// Coefficients of d/dz: b_nc = 0, c_{m} b_{m} = b_{m+2} + 2 (m+1) a_{m+1} for
+// m = nc-1 .. 0 (c_0 = 2, else 1).  The recurrence links m to m+2 only, so the
+// even and odd outputs are two independent chains: one thread per (line,
+// parity).  The loads do not depend on the recurrence; unrolling lets several
+// be in flight.
 __global__ void k_chebd(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ d, int nc, long long nlines) {
-  const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= nlines) return;
-  cpx<double> b1 = {0.0, 0.0};  // b_{n+1}
-  cpx<double> b0 = {0.0, 0.0};  // b_n
-  d[(long long)nc * nlines + l] = b0;
-  for (int n = nc; n >= 1; --n) {
-    const cpx<double> an = a[(long long)n * nlines + l];
-    const double inv_c = (n - 1 == 0) ? 0.5 : 1.0;
-    const cpx<double> bm = {(b1.re + 2.0 * n * an.re) * inv_c, (b1.im + 2.0 * n * an.im) * inv_c};
-    d[(long long)(n - 1) * nlines + l] = bm;
-    b1 = b0;
-    b0 = bm;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * nlines) return;
+  const long long l = id % nlines;
+  const int q = int(id / nlines);
+  const int top = ((nc - q) & 1) ? nc - 1 : nc;   // largest m <= nc of parity q
+  cpx<double> b2 = {0.0, 0.0};                     // b_{m+2}
+#pragma unroll 4
+  for (int m = top; m >= 0; m -= 2) {
+    const cpx<double> am = (m + 1 <= nc) ? a[(long long)(m + 1) * nlines + l] : cpx<double>{0.0, 0.0};
+    const double s = (m == 0) ? 0.5 : 1.0;
+    const cpx<double> bm = {(b2.re + 2.0 * (m + 1) * am.re) * s, (b2.im + 2.0 * (m + 1) * am.im) * s};
+    d[(long long)m * nlines + l] = bm;
+    b2 = bm;
+  }
+}
+
+// out = D^2 a - k^2 a (k^2 = kx^2 + ky^2 of the line, 0 if kx is NULL) in one
+// backward pass: with b = D a and c = D b, c_m = (c_{m+2} + 2(m+1) b_{m+1})/c_m
+// and b_{m+1} = b_{m+3} + 2(m+2) a_{m+2}; the outputs of parity q need b of the
+// other parity and a of parity q, so each (line, parity) is one thread.
+__global__ void k_cheb_lap(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ out, int nc,
+                           long long nlines, const double* __restrict__ kx, const double* __restrict__ ky) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * nlines) return;
+  const long long l = id % nlines;
+  const int q = int(id / nlines);
+  const double k2 = kx ? kx[l] * kx[l] + ky[l] * ky[l] : 0.0;
+  const int top = ((nc - q) & 1) ? nc - 1 : nc;
+  cpx<double> b1 = {0.0, 0.0};   // b_{m+3} before the update, b_{m+1} after
+  cpx<double> c2 = {0.0, 0.0};   // c_{m+2}
+  cpx<double> a2 = {0.0, 0.0};   // a_{m+2}
+#pragma unroll 4
+  for (int m = top; m >= 0; m -= 2) {
+    const cpx<double> am = a[(long long)m * nlines + l];
+    b1 = cpx<double>{b1.re + 2.0 * (m + 2) * a2.re, b1.im + 2.0 * (m + 2) * a2.im};   // b_{m+1}
+    const double s = (m == 0) ? 0.5 : 1.0;
+    const cpx<double> cm = {(c2.re + 2.0 * (m + 1) * b1.re) * s, (c2.im + 2.0 * (m + 1) * b1.im) * s};
+    out[(long long)m * nlines + l] = cpx<double>{cm.re - k2 * am.re, cm.im - k2 * am.im};
+    c2 = cm;
+    a2 = am;
   }
 }
 
@@ -155,6 +186,7 @@ __global__ void k_helm(const cpx<double>* __restrict__ g, cpx<double>* __restric
   double Xn = 0.0;
   cpx<double> Yn = {0.0, 0.0};
   cpx<double> gm = G(p + 2 * m - 2), g0 = G(p + 2 * m), g2 = G(p + 2 * m + 2);
+#pragma unroll 4
   for (int i = m; i >= 1; --i) {
     const int n = p + 2 * i;
     const double dn = double(n);
@@ -183,6 +215,7 @@ __global__ void k_helm(const cpx<double>* __restrict__ g, cpx<double>* __restric
   // upward sweep 1: a_i = P_i a_0 + Q_i, accumulate the boundary row
   double P = 1.0, SP = 0.0;
   cpx<double> Qv = {0.0, 0.0}, SQ = {0.0, 0.0};
+#pragma unroll 4
   for (int i = 0; i <= m; ++i) {
     const int n = p + 2 * i;
     if (i > 0) {
@@ -199,6 +232,7 @@ __global__ void k_helm(const cpx<double>* __restrict__ g, cpx<double>* __restric
   // a_0, then upward sweep 2
   cpx<double> a = {(s.re - SQ.re) / SP, (s.im - SQ.im) / SP};
   f[(long long)p * nlines + l] = a;
+#pragma unroll 4
   for (int i = 1; i <= m; ++i) {
     const int n = p + 2 * i;
     const double X = xw[(long long)n * nlines + l];
@@ -218,6 +252,7 @@ __global__ void k_influence(cpx<double>* __restrict__ wp, const cpx<double>* __r
   const bool mean = (kx[l] == 0.0 && ky[l] == 0.0);
   cpx<double> dpt = {0, 0}, dpb = {0, 0};
   double dtt = 0, dtb = 0, dbt = 0, dbb = 0;
+#pragma unroll 4
   for (int n = 0; n <= nc; ++n) {
     const double w2 = double(n) * double(n);
     const double sg = (n & 1) ? w2 : -w2;  // (-1)^(n+1) n^2
@@ -232,6 +267,7 @@ __global__ void k_influence(cpx<double>* __restrict__ wp, const cpx<double>* __r
   const double det = dtt * dbb - dbt * dtb;
   const cpx<double> ct = {(-dpt.re * dbb + dbt * dpb.re) / det, (-dpt.im * dbb + dbt * dpb.im) / det};
   const cpx<double> cb = {(-dtt * dpb.re + dtb * dpt.re) / det, (-dtt * dpb.im + dtb * dpt.im) / det};
+#pragma unroll 4
   for (int n = 0; n <= nc; ++n) {
     const long long o = (long long)n * nlines + l;
     cpx<double> w = {0.0, 0.0};
@@ -308,21 +344,27 @@ hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, i
 }
 
 hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st) {
-  k_chebd<<<blocks(nlines, 128), 128, 0, st>>>(a, d, nc, nlines);
+  k_chebd<<<blocks(2 * nlines, 64), 64, 0, st>>>(a, d, nc, nlines);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_lap(const cpx<double>* a, cpx<double>* out, int nc, long long nlines, const double* kx,
+                           const double* ky, hipStream_t st) {
+  k_cheb_lap<<<blocks(2 * nlines, 64), 64, 0, st>>>(a, out, nc, nlines, kx, ky);
   return hipGetLastError();
 }
 
 hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc, long long nlines,
                        const double* beta_line, double beta_add, const double* kx, const double* ky, int neumann,
                        const cpx<double>* bcv, cpx<double> top_c, cpx<double> bot_c, hipStream_t st) {
-  k_helm<<<blocks(2 * nlines, 128), 128, 0, st>>>(g, f, xw, nc, nlines, beta_line, beta_add, kx, ky, neumann, bcv,
+  k_helm<<<blocks(2 * nlines, 64), 64, 0, st>>>(g, f, xw, nc, nlines, beta_line, beta_add, kx, ky, neumann, bcv,
                                                    top_c, bot_c);
   return hipGetLastError();
 }
 
 hipError_t launch_influence(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
                             const double* kx, const double* ky, hipStream_t st) {
-  k_influence<<<blocks(nlines, 128), 128, 0, st>>>(wp, wt, wb, nc, nlines, kx, ky);
+  k_influence<<<blocks(nlines, 64), 64, 0, st>>>(wp, wt, wb, nc, nlines, kx, ky);
   return hipGetLastError();
 }
 

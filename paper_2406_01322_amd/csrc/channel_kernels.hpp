@@ -13,6 +13,9 @@ bool supported_nc(int nc);
 template <typename T>
 hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st);
 hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st);
+// out = D^2 a - (kx^2 + ky^2) a per line (k^2 = 0 if kx is NULL)
+hipError_t launch_cheb_lap(const cpx<double>* a, cpx<double>* out, int nc, long long nlines, const double* kx,
+                           const double* ky, hipStream_t st);
 hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc, long long nlines,
                        const double* beta_line, double beta_add, const double* kx, const double* ky, int neumann,
                        const cpx<double>* bcv, cpx<double> top_c, cpx<double> bot_c, hipStream_t st);

@@ -97,15 +97,6 @@ __global__ void k_ch_s(ChanGeom g, const cpx<double>* __restrict__ R, const cpx<
   }
 }
 
-__global__ void k_ch_lap(ChanGeom g, const cpx<double>* __restrict__ a, const cpx<double>* __restrict__ d2a,
-                         const double* __restrict__ kxl, const double* __restrict__ kyl, cpx<double>* __restrict__ out) {
-  PSMS_GRID_LOOP(id, g.NZL) {
-    const long long l = id % g.NL;
-    const double k2 = kxl[l] * kxl[l] + kyl[l] * kyl[l];
-    out[id] = sub(d2a[id], scl(k2, a[id]));
-  }
-}
-
 __device__ __forceinline__ cpx<double> ab(cpx<double> h, cpx<double> hp, int ab1) {
   return ab1 ? h : cpx<double>{1.5 * h.re - 0.5 * hp.re, 1.5 * h.im - 0.5 * hp.im};
 }
@@ -164,13 +155,6 @@ __global__ void k_ch_init(ChanGeom g, const cpx<double>* __restrict__ U4, const 
   }
 }
 
-__global__ void k_ch_zcut(ChanGeom g, cpx<double>* __restrict__ a, int nf, int kz) {
-  PSMS_GRID_LOOP(id, nf * g.NZL) {
-    const long long n = (id % g.NZL) / g.NL;
-    if (n > kz) a[id] = cpx<double>{0.0, 0.0};
-  }
-}
-
 __global__ void k_ch_mean_io(int nz, const cpx<double>* __restrict__ in, cpx<double>* __restrict__ out, int dir) {
   PSMS_GRID_LOOP(id, 2LL * nz) {
     const long long k = id / nz, n = id % nz;   // caller layout [2][nz]
@@ -204,11 +188,6 @@ hipError_t launch_ch_s(const ChanGeom& g, const cpx<double>* R, const cpx<double
   k_ch_s<<<blocks_for(g.NZL), kThreads, 0, st>>>(g, R, dxz, dyz, dzz, kx, ky, s3, q);
   return hipGetLastError();
 }
-hipError_t launch_ch_lap(const ChanGeom& g, const cpx<double>* a, const cpx<double>* d2a, const double* kx,
-                         const double* ky, cpx<double>* out, hipStream_t st) {
-  k_ch_lap<<<blocks_for(g.NZL), kThreads, 0, st>>>(g, a, d2a, kx, ky, out);
-  return hipGetLastError();
-}
 hipError_t launch_ch_assemble(const ChanGeom& g, const ChanCoef& c, const ChanAssembleArgs& a, hipStream_t st) {
   k_ch_assemble<<<blocks_for(g.NZL), kThreads, 0, st>>>(g, c, a);
   return hipGetLastError();
@@ -216,10 +195,6 @@ hipError_t launch_ch_assemble(const ChanGeom& g, const ChanCoef& c, const ChanAs
 hipError_t launch_ch_init(const ChanGeom& g, const cpx<double>* U4, const double* kx, const double* ky,
                           cpx<double>* om, cpx<double>* w, cpx<double>* phi, cpx<double>* mean, hipStream_t st) {
   k_ch_init<<<blocks_for(g.NZL), kThreads, 0, st>>>(g, U4, kx, ky, om, w, phi, mean);
-  return hipGetLastError();
-}
-hipError_t launch_ch_zcut(const ChanGeom& g, cpx<double>* a, int nf, int kz, hipStream_t st) {
-  k_ch_zcut<<<blocks_for(nf * g.NZL), kThreads, 0, st>>>(g, a, nf, kz);
   return hipGetLastError();
 }
 hipError_t launch_ch_mean_io(const ChanGeom& g, const cpx<double>* in, cpx<double>* out, int dir, hipStream_t st) {

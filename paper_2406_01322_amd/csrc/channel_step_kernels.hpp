@@ -41,9 +41,6 @@ hipError_t launch_ch_promote(const ChanGeom& g, const cpx<T>* in, cpx<double>* o
 hipError_t launch_ch_s(const ChanGeom& g, const cpx<double>* R, const cpx<double>* dxz, const cpx<double>* dyz,
                        const cpx<double>* dzz, const double* kx, const double* ky, cpx<double>* s3, cpx<double>* q,
                        hipStream_t st);
-// out = D2 a - k^2 a
-hipError_t launch_ch_lap(const ChanGeom& g, const cpx<double>* a, const cpx<double>* d2a, const double* kx,
-                         const double* ky, cpx<double>* out, hipStream_t st);
 // H_omega, H_w, S_phi; Adams-Bashforth with the history (then overwritten);
 // the right-hand sides g_om, g_w, g_phi of the wall-normal solves; the mean
 // lines' H and right-hand sides.
@@ -71,8 +68,6 @@ hipError_t launch_ch_assemble(const ChanGeom& g, const ChanCoef& c, const ChanAs
 // initial state from the 4 transformed physical fields u, v, w, phi ([4][NZL], FP64)
 hipError_t launch_ch_init(const ChanGeom& g, const cpx<double>* U4, const double* kx, const double* ky,
                           cpx<double>* om, cpx<double>* w, cpx<double>* phi, cpx<double>* mean, hipStream_t st);
-// zero Chebyshev modes n > kz of nf fields [nf][NZL] (FP64)
-hipError_t launch_ch_zcut(const ChanGeom& g, cpx<double>* a, int nf, int kz, hipStream_t st);
 // mean lines: [2][nc+1] (caller) <-> [nc+1][2] (internal); dir > 0 copies into internal
 hipError_t launch_ch_mean_io(const ChanGeom& g, const cpx<double>* in, cpx<double>* out, int dir, hipStream_t st);
 
