@@ -1224,7 +1224,7 @@ struct ChanLayout {
   size_t kx, ky, twx64, twx32, twy64, twy32;
   size_t state, mean, hist, hmean;
   size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, lapc, lapphi, lapom, psi, lappsi, G;
-  size_t d2mean, gmean, xwm, wall, total;
+  size_t d2mean, gmean, wt, wb, M, psip, xi, xw, total;
 };
 
 psms::ChanGeom chan_geom(const psms_channel_params& p) {
@@ -1285,10 +1285,12 @@ ChanLayout chan_layout(const psms_channel_params& p) {
   take(L.G, 3 * arr);
   take(L.d2mean, 2 * nz * c64);
   take(L.gmean, 2 * nz * c64);
-  take(L.xwm, 2 * nz * sizeof(double));
-  size_t wb = 0;
-  psms_wall_workspace_bytes(p.nc, g.NL, &wb);
-  take(L.wall, wb);
+  take(L.wt, arr);
+  take(L.wb, arr);
+  take(L.M, 4 * size_t(g.NL) * sizeof(double));
+  take(L.psip, arr);
+  take(L.xi, arr);
+  take(L.xw, 4 * nz * size_t(g.NL) * sizeof(double));   // one elimination scratch per batched problem
   L.total = off;
   return L;
 }
@@ -1465,30 +1467,26 @@ hipError_t chan_step_once(psms_channel* c) {
   aa.hmean = C64(L.hmean);
   aa.gmean = C64(L.gmean);
   PSMS_TRY(psms::launch_ch_assemble(g, c->coef, aa, st));
-  // the wall-normal solves of every (kx, ky) pair, and the mean flow
-  psms_wall_args wa{};
-  wa.nc = nc;
-  wa.nlines = nl;
-  wa.d_kx = kx;
-  wa.d_ky = ky;
-  wa.beta_ns = c->coef.beta;
-  wa.beta_a = c->a_fac;
-  wa.beta_b = c->b_fac;
-  wa.d_g_om = reinterpret_cast<const double*>(C64(L.G));
-  wa.d_g_w = reinterpret_cast<const double*>(C64(L.G) + g.NZL);
-  wa.d_g_phi = reinterpret_cast<const double*>(C64(L.G) + 2 * g.NZL);
-  wa.d_om = reinterpret_cast<double*>(om);
-  wa.d_w = reinterpret_cast<double*>(w);
-  wa.d_phi = reinterpret_cast<double*>(phi);
-  wa.d_u = reinterpret_cast<double*>(C64(L.S3));
-  wa.d_v = reinterpret_cast<double*>(C64(L.S3) + g.NZL);
-  size_t wb = 0;
-  psms_wall_workspace_bytes(nc, nl, &wb);
-  const int r = psms_wall_solve(&wa, c->ws + L.wall, wb, st);
-  if (r) return hipErrorLaunchFailure;
+  // the wall-normal solves of every (kx, ky) pair (psms_wall_solve's sequence with
+  // the homogeneous w solutions and their influence matrix precomputed at
+  // creation), and the mean flow; independent problems share a launch
   const cpx<double> z0 = {0.0, 0.0};
-  PSMS_TRY(psms::launch_helm(C64(L.gmean), C64(L.mean), c->at<double>(L.xwm), nc, 2, nullptr, c->coef.beta,
-                             nullptr, nullptr, 0, nullptr, z0, z0, st));
+  double* xw = c->at<double>(L.xw);
+  const long long xws = (long long)(nc + 1) * nl;
+  psms::HelmBatch b1{};
+  b1.np = 4;
+  b1.p[0] = psms::HelmProblem{C64(L.G), om, xw, nl, c->coef.beta, kx, ky, 0, z0, z0};                      // omega_z
+  b1.p[1] = psms::HelmProblem{C64(L.G) + g.NZL, C64(L.psip), xw + xws, nl, c->coef.beta, kx, ky, 0, z0, z0};  // psi_p
+  b1.p[2] = psms::HelmProblem{C64(L.G) + 2 * g.NZL, C64(L.xi), xw + 2 * xws, nl, c->a_fac, kx, ky, 1, z0, z0};  // xi
+  b1.p[3] = psms::HelmProblem{C64(L.gmean), C64(L.mean), xw + 3 * xws, 2, c->coef.beta, nullptr, nullptr, 0, z0,
+                              z0};                                                                        // U, V
+  PSMS_TRY(psms::launch_helm_batch(b1, nc, st));
+  psms::HelmBatch b2{};
+  b2.np = 2;
+  b2.p[0] = psms::HelmProblem{C64(L.psip), w, xw, nl, 0.0, kx, ky, 0, z0, z0};             // w_p
+  b2.p[1] = psms::HelmProblem{C64(L.xi), phi, xw + xws, nl, c->b_fac, kx, ky, 1, z0, z0};  // phi
+  PSMS_TRY(psms::launch_helm_batch(b2, nc, st));
+  PSMS_TRY(psms::launch_influence_apply(w, C64(L.wt), C64(L.wb), c->at<double>(L.M), nc, nl, kx, ky, st));
 #undef PSMS_TRY
   return hipSuccess;
 }
@@ -1571,6 +1569,30 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twx32, x32.data(), x32.size() * sizeof(cpx<float>), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twy64, y64.data(), y64.size() * sizeof(cpx<double>), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twy32, y32.data(), y32.size() * sizeof(cpx<float>), hipMemcpyHostToDevice, st);
+  // homogeneous solutions of the clamped w problem (unit psi at one wall) and
+  // their influence matrix: fixed for the context (k^2 and beta are)
+  if (e == hipSuccess) {
+    const cpx<double> z0 = {0.0, 0.0}, one = {1.0, 0.0};
+    const double* kx = c->at<double>(lay.kx);
+    const double* ky = c->at<double>(lay.ky);
+    cpx<double>* pt = c->at<cpx<double>>(lay.psip);
+    cpx<double>* pb = c->at<cpx<double>>(lay.xi);
+    double* xw = c->at<double>(lay.xw);
+    const long long xws = (long long)(p->nc + 1) * g.NL;
+    psms::HelmBatch b{};
+    b.np = 2;
+    b.p[0] = psms::HelmProblem{nullptr, pt, xw, g.NL, c->coef.beta, kx, ky, 0, one, z0};
+    b.p[1] = psms::HelmProblem{nullptr, pb, xw + xws, g.NL, c->coef.beta, kx, ky, 0, z0, one};
+    e = psms::launch_helm_batch(b, p->nc, st);
+    if (e == hipSuccess) {
+      b.p[0] = psms::HelmProblem{pt, c->at<cpx<double>>(lay.wt), xw, g.NL, 0.0, kx, ky, 0, z0, z0};
+      b.p[1] = psms::HelmProblem{pb, c->at<cpx<double>>(lay.wb), xw + xws, g.NL, 0.0, kx, ky, 0, z0, z0};
+      e = psms::launch_helm_batch(b, p->nc, st);
+    }
+    if (e == hipSuccess)
+      e = psms::launch_influence_pre(c->at<cpx<double>>(lay.wt), c->at<cpx<double>>(lay.wb), p->nc, g.NL,
+                                     c->at<double>(lay.M), st);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete c;

@@ -155,12 +155,12 @@ __global__ void k_cheb_lap(const cpx<double>* __restrict__ a, cpx<double>* __res
 // Boundary values: bcv[2l], bcv[2l+1] (top z=+1, bottom z=-1; if given)
 // plus the constants top_c, bot_c.  g may be NULL (zero).  xw: nc+1 doubles
 // per line of scratch.
-__global__ void k_helm(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f, double* __restrict__ xw,
-                       int nc, long long nlines, const double* __restrict__ beta_line, double beta_add,
-                       const double* __restrict__ kx, const double* __restrict__ ky, int neumann,
-                       const cpx<double>* __restrict__ bcv, cpx<double> top_c, cpx<double> bot_c) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= 2 * nlines) return;
+__device__ __forceinline__ void helm_line(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f,
+                                          double* __restrict__ xw, int nc, long long nlines,
+                                          const double* __restrict__ beta_line, double beta_add,
+                                          const double* __restrict__ kx, const double* __restrict__ ky, int neumann,
+                                          const cpx<double>* __restrict__ bcv, cpx<double> top_c, cpx<double> bot_c,
+                                          long long id) {
   const long long l = id % nlines;
   const int p = int(id / nlines);             // parity
   double be = beta_add;
@@ -242,6 +242,25 @@ __global__ void k_helm(const cpx<double>* __restrict__ g, cpx<double>* __restric
   }
 }
 
+__global__ void k_helm(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f, double* __restrict__ xw,
+                       int nc, long long nlines, const double* __restrict__ beta_line, double beta_add,
+                       const double* __restrict__ kx, const double* __restrict__ ky, int neumann,
+                       const cpx<double>* __restrict__ bcv, cpx<double> top_c, cpx<double> bot_c) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * nlines) return;
+  helm_line(g, f, xw, nc, nlines, beta_line, beta_add, kx, ky, neumann, bcv, top_c, bot_c, id);
+}
+
+// Several independent problems in one launch (blockIdx.y selects the problem):
+// each thread's elimination is a sequential chain, so more chains per launch
+// hide more of their memory latency.
+__global__ void k_helm_batch(HelmBatch b, int nc) {
+  const HelmProblem& P = b.p[blockIdx.y];
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * P.nlines) return;
+  helm_line(P.g, P.f, P.xw, nc, P.nlines, nullptr, P.beta_add, P.kx, P.ky, P.neumann, nullptr, P.top_c, P.bot_c, id);
+}
+
 // w = w_p + c_t w_t + c_b w_b with (c_t, c_b) making w'(+1) = w'(-1) = 0;
 // w = 0 where kx = ky = 0.  Written over w_p.
 __global__ void k_influence(cpx<double>* __restrict__ wp, const cpx<double>* __restrict__ wt,
@@ -269,6 +288,81 @@ __global__ void k_influence(cpx<double>* __restrict__ wp, const cpx<double>* __r
   const cpx<double> cb = {(-dtt * dpb.re + dtb * dpt.re) / det, (-dtt * dpb.im + dtb * dpt.im) / det};
 #pragma unroll 4
   for (int n = 0; n <= nc; ++n) {
+    const long long o = (long long)n * nlines + l;
+    cpx<double> w = {0.0, 0.0};
+    if (!mean) {
+      const cpx<double> a = wp[o];
+      const double t = wt[o].re, b = wb[o].re;
+      w = cpx<double>{a.re + ct.re * t + cb.re * b, a.im + ct.im * t + cb.im * b};
+    }
+    wp[o] = w;
+  }
+}
+
+// The influence matrix of the clamped w problem when the homogeneous solutions
+// w_t, w_b are fixed (they depend only on k^2 and beta): M = (w_t'(+1),
+// w_t'(-1), w_b'(+1), w_b'(-1)) per line, M [4][nlines].
+__global__ void k_influence_pre(const cpx<double>* __restrict__ wt, const cpx<double>* __restrict__ wb, int nc,
+                                long long nlines, double* __restrict__ M) {
+  const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlines) return;
+  double dtt = 0, dtb = 0, dbt = 0, dbb = 0;
+  for (int n = 0; n <= nc; ++n) {
+    const double w2 = double(n) * double(n);
+    const double sg = (n & 1) ? w2 : -w2;  // (-1)^(n+1) n^2
+    const long long o = (long long)n * nlines + l;
+    dtt += w2 * wt[o].re;
+    dtb += sg * wt[o].re;
+    dbt += w2 * wb[o].re;
+    dbb += sg * wb[o].re;
+  }
+  M[l] = dtt;
+  M[nlines + l] = dtb;
+  M[2 * nlines + l] = dbt;
+  M[3 * nlines + l] = dbb;
+}
+
+// w = w_p + c_t w_t + c_b w_b with M from k_influence_pre (written over w_p;
+// w = 0 where kx = ky = 0).  64 lines per workgroup, 4 threads per line share
+// the sums over n through LDS.
+__global__ void __launch_bounds__(256) k_influence_apply(cpx<double>* __restrict__ wp,
+                                                         const cpx<double>* __restrict__ wt,
+                                                         const cpx<double>* __restrict__ wb,
+                                                         const double* __restrict__ M, int nc, long long nlines,
+                                                         const double* __restrict__ kx,
+                                                         const double* __restrict__ ky) {
+  __shared__ cpx<double> part[2][4][64];
+  const int li = threadIdx.x % 64, ch = threadIdx.x / 64;
+  const long long l = (long long)blockIdx.x * 64 + li;
+  const bool ok = l < nlines;
+  cpx<double> dpt = {0.0, 0.0}, dpb = {0.0, 0.0};
+  if (ok) {
+#pragma unroll 4
+    for (int n = ch; n <= nc; n += 4) {
+      const double w2 = double(n) * double(n);
+      const double sg = (n & 1) ? w2 : -w2;
+      const cpx<double> a = wp[(long long)n * nlines + l];
+      dpt.re += w2 * a.re; dpt.im += w2 * a.im;
+      dpb.re += sg * a.re; dpb.im += sg * a.im;
+    }
+  }
+  part[0][ch][li] = dpt;
+  part[1][ch][li] = dpb;
+  __syncthreads();
+  if (!ok) return;
+  dpt = cpx<double>{0.0, 0.0};
+  dpb = cpx<double>{0.0, 0.0};
+  for (int c = 0; c < 4; ++c) {
+    dpt = cadd(dpt, part[0][c][li]);
+    dpb = cadd(dpb, part[1][c][li]);
+  }
+  const double dtt = M[l], dtb = M[nlines + l], dbt = M[2 * nlines + l], dbb = M[3 * nlines + l];
+  const bool mean = (kx[l] == 0.0 && ky[l] == 0.0);
+  const double det = dtt * dbb - dbt * dtb;
+  const cpx<double> ct = {(-dpt.re * dbb + dbt * dpb.re) / det, (-dpt.im * dbb + dbt * dpb.im) / det};
+  const cpx<double> cb = {(-dtt * dpb.re + dtb * dpt.re) / det, (-dtt * dpb.im + dtb * dpt.im) / det};
+#pragma unroll 4
+  for (int n = ch; n <= nc; n += 4) {
     const long long o = (long long)n * nlines + l;
     cpx<double> w = {0.0, 0.0};
     if (!mean) {
@@ -362,9 +456,29 @@ hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc,
   return hipGetLastError();
 }
 
+hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st) {
+  long long most = 0;
+  for (int i = 0; i < b.np; ++i) most = most > b.p[i].nlines ? most : b.p[i].nlines;
+  if (b.np < 1 || b.np > kHelmBatchMax || most == 0) return hipSuccess;
+  k_helm_batch<<<dim3(blocks(2 * most, 64), unsigned(b.np)), 64, 0, st>>>(b, nc);
+  return hipGetLastError();
+}
+
 hipError_t launch_influence(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
                             const double* kx, const double* ky, hipStream_t st) {
   k_influence<<<blocks(nlines, 64), 64, 0, st>>>(wp, wt, wb, nc, nlines, kx, ky);
+  return hipGetLastError();
+}
+
+hipError_t launch_influence_pre(const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines, double* M,
+                                hipStream_t st) {
+  k_influence_pre<<<blocks(nlines, 64), 64, 0, st>>>(wt, wb, nc, nlines, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_influence_apply(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, const double* M,
+                                  int nc, long long nlines, const double* kx, const double* ky, hipStream_t st) {
+  k_influence_apply<<<blocks(nlines, 64), 256, 0, st>>>(wp, wt, wb, M, nc, nlines, kx, ky);
   return hipGetLastError();
 }
 

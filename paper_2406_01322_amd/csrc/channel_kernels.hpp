@@ -19,8 +19,34 @@ hipError_t launch_cheb_lap(const cpx<double>* a, cpx<double>* out, int nc, long 
 hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc, long long nlines,
                        const double* beta_line, double beta_add, const double* kx, const double* ky, int neumann,
                        const cpx<double>* bcv, cpx<double> top_c, cpx<double> bot_c, hipStream_t st);
+// independent tau problems (D^2 - (beta_add + kx^2 + ky^2)) f = g of one launch;
+// kx = NULL means k^2 = 0, g = NULL a zero right-hand side; xw: (nc+1) nlines
+// doubles of scratch per problem
+constexpr int kHelmBatchMax = 4;
+struct HelmProblem {
+  const cpx<double>* g;
+  cpx<double>* f;
+  double* xw;
+  long long nlines;
+  double beta_add;
+  const double* kx;
+  const double* ky;
+  int neumann;
+  cpx<double> top_c, bot_c;
+};
+struct HelmBatch {
+  HelmProblem p[kHelmBatchMax];
+  int np;
+};
+hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st);
 hipError_t launch_influence(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
                             const double* kx, const double* ky, hipStream_t st);
+// influence matrix with fixed homogeneous solutions: M [4][nlines] once, then
+// the combination per solve
+hipError_t launch_influence_pre(const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines, double* M,
+                                hipStream_t st);
+hipError_t launch_influence_apply(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, const double* M,
+                                  int nc, long long nlines, const double* kx, const double* ky, hipStream_t st);
 hipError_t launch_uv(const cpx<double>* om, const cpx<double>* dw, cpx<double>* u, cpx<double>* v, int nc,
                      long long nlines, const double* kx, const double* ky, hipStream_t st);
 
