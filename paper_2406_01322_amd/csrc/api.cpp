@@ -1420,8 +1420,13 @@ hipError_t chan_step_once(psms_channel* c) {
 #define PSMS_TRY(x) \
   if ((e = (x)) != hipSuccess) return e
   // 1-2. fields and the inverse transforms
-  PSMS_TRY(psms::launch_chebd(w, C64(L.dw), nc, nl, st));
-  PSMS_TRY(psms::launch_chebd(phi, C64(L.dphi), nc, nl, st));
+  psms::ChebBatch cb{};
+  cb.n = 2;
+  cb.in[0] = w;
+  cb.out[0] = C64(L.dw);
+  cb.in[1] = phi;
+  cb.out[1] = C64(L.dphi);
+  PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0, st));
   PSMS_TRY(psms::launch_ch_fields<T>(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky,
                                      c->at<cpx<T>>(L.A), st));
   PSMS_TRY(chan_inverse<T>(c, c->at<cpx<T>>(L.A), c->at<T>(L.C), 7));
@@ -1431,19 +1436,27 @@ hipError_t chan_step_once(psms_channel* c) {
   PSMS_TRY(psms::launch_ch_promote<T>(g, c->at<cpx<T>>(L.A), R, st));
   // 5. S = div T, and the wall-normal derivatives the right-hand sides need
   cpx<double>* D3 = C64(L.D3);
-  PSMS_TRY(psms::launch_chebd(R + 4 * g.NZL, D3, nc, nl, st));              // D T_xz
-  PSMS_TRY(psms::launch_chebd(R + 5 * g.NZL, D3 + g.NZL, nc, nl, st));      // D T_yz
-  PSMS_TRY(psms::launch_chebd(R + 2 * g.NZL, D3 + 2 * g.NZL, nc, nl, st));  // D T_zz
+  cb.n = 3;   // D T_xz, D T_yz, D T_zz
+  cb.in[0] = R + 4 * g.NZL;
+  cb.out[0] = D3;
+  cb.in[1] = R + 5 * g.NZL;
+  cb.out[1] = D3 + g.NZL;
+  cb.in[2] = R + 2 * g.NZL;
+  cb.out[2] = D3 + 2 * g.NZL;
+  PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0, st));
   PSMS_TRY(psms::launch_ch_s(g, R, D3, D3 + g.NZL, D3 + 2 * g.NZL, kx, ky, C64(L.S3), C64(L.Q), st));
   PSMS_TRY(psms::launch_chebd(C64(L.Q), C64(L.DQ), nc, nl, st));
-  auto lap = [&](const cpx<double>* a, cpx<double>* out) {   // D^2 a - k^2 a
-    return psms::launch_cheb_lap(a, out, nc, nl, kx, ky, st);
-  };
-  PSMS_TRY(lap(R + 7 * g.NZL, C64(L.lapc)));
-  PSMS_TRY(lap(phi, C64(L.lapphi)));
-  PSMS_TRY(lap(om, C64(L.lapom)));
-  PSMS_TRY(lap(w, C64(L.psi)));
-  PSMS_TRY(lap(C64(L.psi), C64(L.lappsi)));
+  cb.n = 4;   // D^2 - k^2 of c, phi, omega_z and w
+  cb.in[0] = R + 7 * g.NZL;
+  cb.out[0] = C64(L.lapc);
+  cb.in[1] = phi;
+  cb.out[1] = C64(L.lapphi);
+  cb.in[2] = om;
+  cb.out[2] = C64(L.lapom);
+  cb.in[3] = w;
+  cb.out[3] = C64(L.psi);
+  PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 1, st));
+  PSMS_TRY(psms::launch_cheb_lap(C64(L.psi), C64(L.lappsi), nc, nl, kx, ky, st));
   PSMS_TRY(psms::launch_cheb_lap(C64(L.mean), C64(L.d2mean), nc, 2, nullptr, nullptr, st));
   // 6. Adams-Bashforth, Crank-Nicolson / implicit Euler right-hand sides
   c->coef.ab1 = (c->nstep == 0) ? 1 : 0;

@@ -100,9 +100,8 @@ __global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<
 // even and odd outputs are two independent chains: one thread per (line,
 // parity).  The loads do not depend on the recurrence; unrolling lets several
 // be in flight.
-__global__ void k_chebd(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ d, int nc, long long nlines) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= 2 * nlines) return;
+__device__ __forceinline__ void chebd_chain(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ d, int nc,
+                                            long long nlines, long long id) {
   const long long l = id % nlines;
   const int q = int(id / nlines);
   const int top = ((nc - q) & 1) ? nc - 1 : nc;   // largest m <= nc of parity q
@@ -117,14 +116,19 @@ __global__ void k_chebd(const cpx<double>* __restrict__ a, cpx<double>* __restri
   }
 }
 
+__global__ void k_chebd(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ d, int nc, long long nlines) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * nlines) return;
+  chebd_chain(a, d, nc, nlines, id);
+}
+
 // out = D^2 a - k^2 a (k^2 = kx^2 + ky^2 of the line, 0 if kx is NULL) in one
 // backward pass: with b = D a and c = D b, c_m = (c_{m+2} + 2(m+1) b_{m+1})/c_m
 // and b_{m+1} = b_{m+3} + 2(m+2) a_{m+2}; the outputs of parity q need b of the
 // other parity and a of parity q, so each (line, parity) is one thread.
-__global__ void k_cheb_lap(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ out, int nc,
-                           long long nlines, const double* __restrict__ kx, const double* __restrict__ ky) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= 2 * nlines) return;
+__device__ __forceinline__ void cheb_lap_chain(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ out,
+                                               int nc, long long nlines, const double* __restrict__ kx,
+                                               const double* __restrict__ ky, long long id) {
   const long long l = id % nlines;
   const int q = int(id / nlines);
   const double k2 = kx ? kx[l] * kx[l] + ky[l] * ky[l] : 0.0;
@@ -142,6 +146,24 @@ __global__ void k_cheb_lap(const cpx<double>* __restrict__ a, cpx<double>* __res
     c2 = cm;
     a2 = am;
   }
+}
+
+__global__ void k_cheb_lap(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ out, int nc,
+                           long long nlines, const double* __restrict__ kx, const double* __restrict__ ky) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * nlines) return;
+  cheb_lap_chain(a, out, nc, nlines, kx, ky, id);
+}
+
+// several arrays of the same lines in one launch (blockIdx.y selects the
+// array): D (lap = 0) or D^2 - k^2 (lap = 1)
+__global__ void k_cheb_batch(ChebBatch b, int nc, long long nlines, const double* __restrict__ kx,
+                             const double* __restrict__ ky, int lap) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * nlines) return;
+  const int j = blockIdx.y;
+  if (lap) cheb_lap_chain(b.in[j], b.out[j], nc, nlines, kx, ky, id);
+  else chebd_chain(b.in[j], b.out[j], nc, nlines, id);
 }
 
 // Chebyshev-tau Helmholtz solve (D^2 - beta) f = g, one thread per (line,
@@ -439,6 +461,13 @@ hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, i
 
 hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st) {
   k_chebd<<<blocks(2 * nlines, 64), 64, 0, st>>>(a, d, nc, nlines);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
+                             int lap, hipStream_t st) {
+  if (b.n < 1 || b.n > kChebBatchMax || nlines == 0) return hipSuccess;
+  k_cheb_batch<<<dim3(blocks(2 * nlines, 64), unsigned(b.n)), 64, 0, st>>>(b, nc, nlines, kx, ky, lap);
   return hipGetLastError();
 }
 

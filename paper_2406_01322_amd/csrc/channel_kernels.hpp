@@ -13,6 +13,16 @@ bool supported_nc(int nc);
 template <typename T>
 hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st);
 hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st);
+// up to kChebBatchMax arrays of the same lines per launch: out[j] = D in[j]
+// (lap = 0) or D^2 in[j] - k^2 in[j] (lap = 1)
+constexpr int kChebBatchMax = 4;
+struct ChebBatch {
+  const cpx<double>* in[kChebBatchMax];
+  cpx<double>* out[kChebBatchMax];
+  int n;
+};
+hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
+                             int lap, hipStream_t st);
 // out = D^2 a - (kx^2 + ky^2) a per line (k^2 = 0 if kx is NULL)
 hipError_t launch_cheb_lap(const cpx<double>* a, cpx<double>* out, int nc, long long nlines, const double* kx,
                            const double* ky, hipStream_t st);
