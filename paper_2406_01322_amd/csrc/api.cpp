@@ -1221,7 +1221,7 @@ int psms_adjoint_backward(psms_adjoint* a, double* d_dphi0, double* h_dwe) {
 namespace {
 
 struct ChanLayout {
-  size_t kx, ky, twx64, twx32, twy64, twy32;
+  size_t kx, ky, twx64, twx32, twy64, twy32, twz64, twz32;
   size_t state, mean, hist, hmean;
   size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, lapc, lapphi, lapom, psi, lappsi, G;
   size_t d2mean, gmean, wt, wb, M, psip, xi, xw, total;
@@ -1262,6 +1262,8 @@ ChanLayout chan_layout(const psms_channel_params& p) {
   take(L.twx32, size_t(p.nx) * sizeof(cpx<float>));
   take(L.twy64, size_t(p.ny) * c64);
   take(L.twy32, size_t(p.ny) * sizeof(cpx<float>));
+  take(L.twz64, size_t(2 * p.nc) * c64);
+  take(L.twz32, size_t(2 * p.nc) * sizeof(cpx<float>));
   take(L.state, 3 * arr);
   take(L.mean, 2 * nz * c64);
   take(L.hist, 3 * arr);
@@ -1336,6 +1338,10 @@ const cpx<T>* chan_tw(const psms_channel* c, bool x) {
     return reinterpret_cast<const cpx<T>*>(c->ws + (x ? c->lay.twx64 : c->lay.twy64));
   return reinterpret_cast<const cpx<T>*>(c->ws + (x ? c->lay.twx32 : c->lay.twy32));
 }
+template <typename T>
+const cpx<T>* chan_twz(const psms_channel* c) {
+  return reinterpret_cast<const cpx<T>*>(c->ws + (std::is_same<T, double>::value ? c->lay.twz64 : c->lay.twz32));
+}
 
 // physical [nf][z][y][x] (T) -> band [nf][n][line] (T): x rows, y lines (1/(nx ny)), DCT-I
 template <typename T>
@@ -1364,8 +1370,7 @@ hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf) {
   la.dmask = 0;
   la.scale = 1.0 / (double(g.nx) * double(g.ny));
   e = psms::launch_lines<T>(g.ny, -1, B, A2, chan_tw<T>(c, false), la, nf, c->stream);
-  for (int f = 0; f < nf && e == hipSuccess; ++f)
-    e = psms::launch_dct<T>(g.nc, A2 + f * g.NZL, band + f * g.NZL, g.NL, +1, c->stream);
+  if (e == hipSuccess) e = psms::launch_dct_fields<T>(g.nc, A2, band, g.NL, g.NZL, nf, chan_twz<T>(c), +1, c->stream);
   return e;
 }
 
@@ -1376,9 +1381,7 @@ hipError_t chan_inverse(psms_channel* c, const cpx<T>* band, T* phys, int nf) {
   const long long nz = g.nc + 1;
   cpx<T>* B = c->at<cpx<T>>(c->lay.B);
   cpx<T>* A2 = c->at<cpx<T>>(c->lay.A2);
-  hipError_t e = hipSuccess;
-  for (int f = 0; f < nf && e == hipSuccess; ++f)
-    e = psms::launch_dct<T>(g.nc, band + f * g.NZL, A2 + f * g.NZL, g.NL, -1, c->stream);
+  hipError_t e = psms::launch_dct_fields<T>(g.nc, band, A2, g.NL, g.NZL, nf, chan_twz<T>(c), -1, c->stream);
   if (e != hipSuccess) return e;
   psms::LineArgs la{};
   la.n_in = g.Cy;
@@ -1571,10 +1574,11 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
       t32[m] = cpx<float>{float(t64[m].re), float(t64[m].im)};
     }
   };
-  std::vector<cpx<double>> x64, y64;
-  std::vector<cpx<float>> x32, y32;
+  std::vector<cpx<double>> x64, y64, z64;
+  std::vector<cpx<float>> x32, y32, z32;
   tws(p->nx, x64, x32);
   tws(p->ny, y64, y32);
+  tws(2 * p->nc, z64, z32);
   hipStream_t st = c->stream;
   hipError_t e = hipMemcpyAsync(c->ws + lay.kx, hkx.data(), g.NL * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.ky, hky.data(), g.NL * sizeof(double), hipMemcpyHostToDevice, st);
@@ -1582,6 +1586,8 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twx32, x32.data(), x32.size() * sizeof(cpx<float>), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twy64, y64.data(), y64.size() * sizeof(cpx<double>), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twy32, y32.data(), y32.size() * sizeof(cpx<float>), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twz64, z64.data(), z64.size() * sizeof(cpx<double>), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twz32, z32.data(), z32.size() * sizeof(cpx<float>), hipMemcpyHostToDevice, st);
   // homogeneous solutions of the clamped w problem (unit psi at one wall) and
   // their influence matrix: fixed for the context (k^2 and beta are)
   if (e == hipSuccess) {

@@ -40,7 +40,8 @@ struct CTile {
 //   b_0 = a_0, b_nc = a_nc, b_n = a_n / 2.
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
-                                             long long nlines, int dir) {
+                                             long long nlines, int dir, long long fstride,
+                                             const cpx<T>* __restrict__ tw_g) {
   using P = Plan<N>;
   using G = CTile<P>;
   constexpr int E = G::E, L = G::L, LP = L + 1, NC = N / 2;
@@ -49,10 +50,16 @@ __global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<
   __shared__ cpx<T> lds[2][N * LP];
   const int tid = threadIdx.x;
   const int line = tid % L, t = tid / L;
-  for (int i = tid; i < N; i += blockDim.x) {
-    double s, c;
-    sincospi(-2.0 * double(i) / double(N), &s, &c);
-    tw[i] = cpx<T>{T(c), T(s)};
+  in += (long long)blockIdx.y * fstride;   // field blockIdx.y
+  out += (long long)blockIdx.y * fstride;
+  if (tw_g) {
+    for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
+  } else {
+    for (int i = tid; i < N; i += blockDim.x) {
+      double s, c;
+      sincospi(-2.0 * double(i) / double(N), &s, &c);
+      tw[i] = cpx<T>{T(c), T(s)};
+    }
   }
   const long long l = (long long)blockIdx.x * L + line;
   const bool valid = l < nlines;
@@ -438,9 +445,11 @@ bool supported_nc(int nc) {
 
 namespace {
 template <typename T, int N>
-hipError_t dct_n(const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st) {
+hipError_t dct_n(const cpx<T>* in, cpx<T>* out, long long nlines, int dir, long long fstride, int nfield,
+                 const cpx<T>* tw, hipStream_t st) {
   using G = CTile<Plan<N>>;
-  k_dct<T, N><<<unsigned((nlines + G::L - 1) / G::L), unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir);
+  const dim3 grid(unsigned((nlines + G::L - 1) / G::L), unsigned(nfield));
+  k_dct<T, N><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw);
   return hipGetLastError();
 }
 unsigned blocks(long long n, int bs) {
@@ -451,8 +460,15 @@ unsigned blocks(long long n, int bs) {
 
 template <typename T>
 hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st) {
+  return launch_dct_fields<T>(nc, in, out, nlines, 0, 1, nullptr, dir, st);
+}
+
+template <typename T>
+hipError_t launch_dct_fields(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, long long fstride, int nfield,
+                             const cpx<T>* tw, int dir, hipStream_t st) {
+  if (nfield < 1 || nlines == 0) return hipSuccess;
   switch (2 * nc) {
-#define PSMS_CASE(NN) case NN: return dct_n<T, NN>(in, out, nlines, dir, st);
+#define PSMS_CASE(NN) case NN: return dct_n<T, NN>(in, out, nlines, dir, fstride, nfield, tw, st);
     PSMS_FOR_EACH_2NC(PSMS_CASE)
 #undef PSMS_CASE
   }
@@ -520,6 +536,10 @@ hipError_t launch_uv(const cpx<double>* om, const cpx<double>* dw, cpx<double>* 
 }
 
 template hipError_t launch_dct<double>(int, const cpx<double>*, cpx<double>*, long long, int, hipStream_t);
+template hipError_t launch_dct_fields<double>(int, const cpx<double>*, cpx<double>*, long long, long long, int,
+                                              const cpx<double>*, int, hipStream_t);
+template hipError_t launch_dct_fields<float>(int, const cpx<float>*, cpx<float>*, long long, long long, int,
+                                             const cpx<float>*, int, hipStream_t);
 template hipError_t launch_dct<float>(int, const cpx<float>*, cpx<float>*, long long, int, hipStream_t);
 
 }  // namespace psms
