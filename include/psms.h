@@ -93,6 +93,7 @@ typedef struct psms_diag {
   double max_div;    /* max_k |k . u_hat(k)| (continuity, eq. cont) */
   int32_t nonfinite; /* number of modes holding a non-finite value */
   int32_t nstep;     /* steps taken since init_state / set_state(nstep) */
+  double cfl;        /* dt max_x (|u| + |v| + |w|) / dx, dx = 2 pi / n (physical grid) */
 } psms_diag;
 
 typedef struct psms_ctx psms_ctx;

@@ -310,9 +310,10 @@ def half_weights(n: int) -> np.ndarray:
     return w
 
 
-def diagnostics(state: dict, n: int) -> dict:
+def diagnostics(state: dict, n: int, dt: float | None = None) -> dict:
     """Volume averages: mean phi, kinetic energy 1/2 <|u|^2>, <|grad phi|^2>,
-    and max |k.u_hat| (continuity, equation ``cont``)."""
+    and max |k.u_hat| (continuity, equation ``cont``); with dt, also the CFL
+    number dt max_x (|u| + |v| + |w|) / dx on the physical grid, dx = 2 pi / N."""
     uh, ph = state["uh"], state["ph"]
     KX, KY, KZ = kgrid(n)
     k2 = KX * KX + KY * KY + KZ * KZ
@@ -321,5 +322,8 @@ def diagnostics(state: dict, n: int) -> dict:
     grad2 = float(np.sum(w * k2 * np.abs(ph) ** 2))
     div = float(np.max(np.abs(KX * uh[0] + KY * uh[1] + KZ * uh[2])))
     finite = bool(np.all(np.isfinite(uh)) and np.all(np.isfinite(ph)))
-    return dict(mean_phi=float(ph[0, 0, 0].real), ke=ke, grad2=grad2,
-                max_div=div, finite=finite)
+    out = dict(mean_phi=float(ph[0, 0, 0].real), ke=ke, grad2=grad2, max_div=div, finite=finite)
+    if dt is not None:
+        u = inv(uh, n)
+        out["cfl"] = float(dt * np.max(np.abs(u).sum(axis=0)) / (2.0 * math.pi / n))
+    return out

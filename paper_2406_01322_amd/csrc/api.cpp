@@ -34,7 +34,7 @@ int hip_fail(hipError_t e, const char* where) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t state, hist, bufa, bufb, tw64, tw32, diag, diag_out, box, total;
+  size_t state, hist, bufa, bufb, tw64, tw32, diag, diag_out, box, phys, acc, total;
   size_t bufa_bytes, bufb_bytes;
 };
 
@@ -71,6 +71,8 @@ Layout make_layout(const psms_params& p) {
   L.diag = off; off = align256(off + 4 * kDiagBlocks * sizeof(double));
   L.diag_out = off; off = align256(off + 8 * sizeof(double));
   L.box = off; off = align256(off + sizeof(psms::BoxDev));
+  L.phys = off; off = align256(off + n * n * n * sizeof(double));   // CFL: one physical component
+  L.acc = off; off = align256(off + n * n * n * sizeof(double));    // CFL: sum_i |u_i| / dx
   L.total = off;
   return L;
 }
@@ -537,7 +539,39 @@ int psms_diagnostics(psms_ctx* c, psms_diag* h_out) {
   if (!c || !h_out) return fail(PSMS_E_INVAL, "NULL argument");
   if (!c->have_state) return fail(PSMS_E_STATE, "no state");
   hipError_t e = psms::launch_diag(c->state, c->g, c->diag, kDiagBlocks, c->diag_out, c->stream);
-  double h[5];
+  // CFL = dt max_x sum_i |u_i| / dx: each component to physical space (FP64,
+  // through the step's scratch, so the next step re-runs its prologue)
+  const BoxGeom& g = c->g;
+  const int n = g.n, nh = n / 2 + 1;
+  const long long np = (long long)n * n * n;
+  double* phys = reinterpret_cast<double*>(c->ws + c->lay.phys);
+  double* acc = reinterpret_cast<double*>(c->ws + c->lay.acc);
+  cpx<double>* A = static_cast<cpx<double>*>(c->bufa);
+  cpx<double>* B = static_cast<cpx<double>*>(c->bufb);
+  psms::LineArgs ly{};
+  ly.n_in = n;
+  ly.n_out = n;
+  ly.inner = nh;
+  ly.nlines = (long long)n * nh;
+  ly.scale = 1.0;
+  psms::LineArgs lz = ly;
+  lz.inner = (long long)n * nh;
+  psms::RowArgs ra{};
+  ra.nrows = (long long)n * n;
+  ra.n_in = nh;
+  ra.n_out = n;
+  ra.scale = 1.0;
+  c->g_valid = 0;
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    e = psms::launch_expand<double>(c->state + k * g.M, B, g, 1, c->stream);
+    if (e == hipSuccess) e = psms::launch_spec_finish<double>(B, A, g, 1, 0, -1, 1.0, c->stream);
+    if (e == hipSuccess) e = psms::launch_lines<double>(n, +1, A, B, c->tw64, lz, 1, c->stream);
+    if (e == hipSuccess) e = psms::launch_lines<double>(n, +1, B, A, c->tw64, ly, 1, c->stream);
+    if (e == hipSuccess) e = psms::launch_rows<double>(n, +1, A, phys, c->tw64, ra, 1, c->stream);
+    if (e == hipSuccess) e = psms::launch_abs_accum(phys, acc, np, c->p.dt * n / (2.0 * M_PI), k == 0, c->stream);
+  }
+  if (e == hipSuccess) e = psms::launch_max(acc, np, c->diag, kDiagBlocks, c->diag_out + 5, c->stream);
+  double h[6];
   if (e == hipSuccess) e = hipMemcpyAsync(h, c->diag_out, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics");
@@ -547,6 +581,7 @@ int psms_diagnostics(psms_ctx* c, psms_diag* h_out) {
   h_out->max_div = h[3];
   h_out->nonfinite = int32_t(h[4]);
   h_out->nstep = c->nstep;
+  h_out->cfl = h[5];
   return PSMS_OK;
 }
 

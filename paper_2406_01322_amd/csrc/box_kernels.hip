@@ -735,6 +735,44 @@ __global__ void k_index_maps(int* __restrict__ out, BoxGeom g) {
   }
 }
 
+// CFL number dt max_x sum_i |u_i| / dx (dx = 2 pi / n) from the physical
+// velocity components, accumulated one component at a time:
+// acc = (first ? 0 : acc) + scale |f|, then a two-pass maximum.
+__global__ void k_abs_accum(const double* __restrict__ f, double* __restrict__ acc, long long n, double scale,
+                            int first) {
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n; id += (long long)gridDim.x * blockDim.x)
+    acc[id] = (first ? 0.0 : acc[id]) + scale * fabs(f[id]);
+}
+
+__global__ void k_max_partial(const double* __restrict__ a, long long n, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n; id += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, a[id]);
+  const int t = threadIdx.x;
+  sh[t] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_max_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, part[i]);
+  const int t = threadIdx.x;
+  sh[t] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) out[0] = sh[0];
+}
+
 // Diagnostics over the compact state, two-pass deterministic reduction.
 // part[b] = {ke, grad2, max_div, nonfinite}
 __global__ void k_diag_partial(const cpx<double>* __restrict__ st, BoxGeom g, double* __restrict__ part) {
@@ -971,6 +1009,22 @@ hipError_t launch_index_maps(int* out, const BoxGeom& g, hipStream_t st) {
   k_index_maps<<<grid_for(g.M), 256, 0, st>>>(out, g);
   return hipGetLastError();
 }
+hipError_t launch_abs_accum(const double* f, double* acc, long long n, double scale, int first, hipStream_t st) {
+  long long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  k_abs_accum<<<unsigned(b < 1 ? 1 : b), 256, 0, st>>>(f, acc, n, scale, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_max(const double* a, long long n, double* part, int max_blocks, double* out, hipStream_t st) {
+  long long b = (n + 255) / 256;
+  if (b > max_blocks) b = max_blocks;
+  if (b < 1) b = 1;
+  k_max_partial<<<unsigned(b), 256, 0, st>>>(a, n, part);
+  k_max_final<<<1, 256, 0, st>>>(part, int(b), out);
+  return hipGetLastError();
+}
+
 hipError_t launch_diag(const cpx<double>* state, const BoxGeom& g, double* part, int max_blocks, double* out,
                        hipStream_t st) {
   long long nb = (g.M + 255) / 256;

@@ -86,6 +86,10 @@ hipError_t launch_spec_finish(const cpx<T>* in, cpx<T>* out, const BoxGeom& g, i
 hipError_t launch_helmholtz_box(const cpx<double>* rhs, cpx<double>* out, const BoxGeom& g, double lam,
                                 hipStream_t st);
 hipError_t launch_index_maps(int* out, const BoxGeom& g, hipStream_t st);
+// acc = (first ? 0 : acc) + scale |f| over n values
+hipError_t launch_abs_accum(const double* f, double* acc, long long n, double scale, int first, hipStream_t st);
+// out[0] = max of a[0..n) (a >= 0), two passes through part[max_blocks]
+hipError_t launch_max(const double* a, long long n, double* part, int max_blocks, double* out, hipStream_t st);
 hipError_t launch_diag(const cpx<double>* state, const BoxGeom& g, double* part, int max_blocks, double* out,
                        hipStream_t st);
 

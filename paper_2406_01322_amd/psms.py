@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
 
 class Diag(ctypes.Structure):
     _fields_ = [("mean_phi", ctypes.c_double), ("ke", ctypes.c_double), ("grad2", ctypes.c_double),
-                ("max_div", ctypes.c_double), ("nonfinite", ctypes.c_int32), ("nstep", ctypes.c_int32)]
+                ("max_div", ctypes.c_double), ("nonfinite", ctypes.c_int32), ("nstep", ctypes.c_int32),
+                ("cfl", ctypes.c_double)]
 
 
 class WallArgs(ctypes.Structure):
@@ -282,7 +283,7 @@ class Solver:
         d = Diag()
         _check(lib().psms_diagnostics(self.ctx, ctypes.byref(d)))
         return dict(mean_phi=d.mean_phi, ke=d.ke, grad2=d.grad2, max_div=d.max_div,
-                    nonfinite=int(d.nonfinite), nstep=int(d.nstep))
+                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl)
 
     def index_maps(self):
         m = int(lib().psms_band_modes(self.ctx))
@@ -441,7 +442,7 @@ class Batch:
         d = Diag()
         _check(lib().psms_batch_diagnostics(self.h, int(box), ctypes.byref(d)))
         return dict(mean_phi=d.mean_phi, ke=d.ke, grad2=d.grad2, max_div=d.max_div,
-                    nonfinite=int(d.nonfinite), nstep=int(d.nstep))
+                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl)
 
     def groups(self):
         ng = ctypes.c_int32(0)

@@ -130,8 +130,9 @@ def test_init_state_parity(case):
     assert rel_l2(_host(uh), st["uh"]) < 1e-13
     assert rel_l2(_host(ph), st["ph"]) < 1e-13
     d = s.diagnostics()
-    od = box.diagnostics(st, prm.n)
+    od = box.diagnostics(st, prm.n, prm.dt)
     assert abs(d["mean_phi"] - od["mean_phi"]) < 1e-14
+    assert abs(d["cfl"] - od["cfl"]) < 1e-12 * od["cfl"]
     assert abs(d["ke"] - od["ke"]) < 1e-12 * od["ke"]
     assert abs(d["grad2"] - od["grad2"]) < 1e-12 * od["grad2"]
     assert d["max_div"] < 1e-13 and d["nonfinite"] == 0
@@ -275,3 +276,25 @@ def test_graph_replay_matches_eager_steps():
         b = eager.get_state()
         torch.cuda.synchronize()
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_diagnostics_between_steps_leave_the_trajectory_unchanged(precision):
+    """psms_diagnostics reuses the step's scratch for the CFL transforms; the next
+    step must rebuild its input (bitwise the same trajectory, eager and graph)."""
+    p, prm, st = _prepare("drops4_48", 0)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a = _solver(p, precision)
+        _load(a, st)
+        a.step(4)
+        ua = a.get_state()
+        b = _solver(p, precision)
+        _load(b, st)
+        b.step(2)
+        d = b.diagnostics()
+        b.step(2)
+        ub = b.get_state()
+    side.synchronize()
+    assert d["nstep"] == 2 and d["cfl"] > 0.0
+    assert torch.equal(ua[0], ub[0]) and torch.equal(ua[1], ub[1])

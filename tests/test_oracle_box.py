@@ -365,3 +365,17 @@ def test_ns_ab2_cn_under_frozen_capillary_forcing():
     want = F * (1.0 - math.exp(-nu_k2 * t)) / nu_k2
     got = box.inv(st["uh"], n)
     assert np.max(np.abs(got - want)) < 1e-4 * np.max(np.abs(want))
+
+
+def test_cfl_of_single_modes_closed_form():
+    """u = A sin(y), v = 0, w = B cos(2x): max(|u| + |w|) = A + B (attained where
+    sin(y) = cos(2x) = +-1 together on the grid); CFL = dt (A + B) N / (2 pi)."""
+    n = 16
+    x = np.arange(n) * 2 * math.pi / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    A, B, dt = 0.7, 0.3, 1e-3
+    u = np.stack([A * np.sin(Y), np.zeros_like(Y), B * np.cos(2 * X)])
+    prm = box.Params(n=n, re=100.0, we=1.0, ch=0.05, pe=20.0, dt=dt)
+    st = box.init_state(u, np.zeros((n, n, n)), prm)
+    d = box.diagnostics(st, n, dt)
+    assert abs(d["cfl"] - dt * (A + B) * n / (2 * math.pi)) < 1e-14
