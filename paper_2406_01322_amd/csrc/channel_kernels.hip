@@ -24,12 +24,15 @@ namespace psms {
 
 namespace {
 
+// 16 lines per workgroup: the lanes of a position read 16 consecutive lines
+// (128 bytes in FP32), and the LDS tile stays within 160 KB in FP64.
 template <class P>
 struct CTile {
   static constexpr int N = P::N;
   static constexpr int E = P::E;
   static constexpr int TT = N / E;
-  static constexpr int L = (256 / TT) > 0 ? 256 / TT : 1;
+  static constexpr int L = 16;
+  static_assert(L * TT <= 1024, "workgroup size");
 };
 
 }  // namespace
@@ -39,7 +42,7 @@ struct CTile {
 // dir = -1: coefficients -> values, f_j = FFT of the even extension of b with
 //   b_0 = a_0, b_nc = a_nc, b_n = a_n / 2.
 template <typename T, int N>
-__global__ void __launch_bounds__(256) k_dct(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+__global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                              long long nlines, int dir, long long fstride,
                                              const cpx<T>* __restrict__ tw_g) {
   using P = Plan<N>;
