@@ -141,6 +141,26 @@ def mixed_error(n, p, u, phi, nsteps=(1, 20)):
     return out
 
 
+def copy_peak(nbytes=1 << 30, reps=10):
+    """Measured device-to-device copy bandwidth (read + write bytes / time) of a 1 GiB
+    buffer, HIP events around `reps` copies: the practical HBM ceiling beside the
+    8 TB/s peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def bench_batch(steps=100, nbox=96):
     """The batched form: 96 independent boxes, N drawn from {32, 48, 64, 96}, 1-8 drops,
     Re ~ U[50, 400], We ~ U[0.5, 5], MIXED; workgroup sizes autotuned; after the first
@@ -340,6 +360,7 @@ def main():
         "event_ms_per_step": r["event_ms_per_step"],
         "stage_ms": r["stage_ms"],
         "stage_gbs": {k: sb[k] / (r["stage_ms"][k] * 1e-3) / 1e9 for k in STAGES},
+        "copy_peak_gbs": copy_peak(),
         "step_model": {"bytes_per_step": step_bytes,
                        "frac_of_hbm": step_bytes * r["value"] / n ** 3 / (HBM_PEAK_GBS * 1e9)},
     }
