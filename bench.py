@@ -247,19 +247,23 @@ def bench_wall_solve(reps=20):
             "lines_per_s": nl / (ms * 1e-3)}
 
 
-def bench_channel(steps=20, warmup=2):
-    """The channel step at 256 x 128 x 129 (4 pi x 2 pi x 2, Re_tau 150, 64 drops R = 0.2,
-    Ch 0.02, We 3, Pe 50, dt 1e-4), MIXED and FP64: ms per step (HIP events on the
-    stream) after `warmup` steps from the synthetic initial state."""
+def bench_channel(steps=20, warmup=2, case="chan_256"):
+    """The channel step, MIXED and FP64: ms per step (HIP events on the stream) after
+    `warmup` steps from the synthetic initial state.  chan_256: 256 x 128 x 129
+    (4 pi x 2 pi x 2, Re_tau 150, 64 drops R = 0.2, Ch 0.02, We 3, Pe 50, dt 1e-4);
+    chan_sp_256: 256 x 256 x 257 single phase (Re_tau 150, dt 1e-4), the grid of the
+    paper's single-phase timing runs."""
     import torch
     from paper_2406_01322_amd import psms, synth
-    p, u, v, w, phi = synth.channel_case("chan_256")
+    p, u, v, w, phi = synth.channel_case(case)
+    sp = p.get("single_phase", False)
     npts = (p["nc"] + 1) * p["ny"] * p["nx"]
-    out = {"grid": [p["nx"], p["ny"], p["nc"] + 1], "points": npts, "steps": steps}
-    f = [torch.from_numpy(x).cuda() for x in (u, v, w, phi)]
+    out = {"grid": [p["nx"], p["ny"], p["nc"] + 1], "points": npts, "steps": steps, "single_phase": sp}
+    f = [torch.from_numpy(x).cuda() for x in ((u, v, w) if sp else (u, v, w, phi))]
+    del u, v, w, phi
     for prec in ("mixed", "fp64"):
         c = psms.Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=prec,
-                         lx=p["lx"], ly=p["ly"])
+                         lx=p["lx"], ly=p["ly"], single_phase=sp)
         c.init_state(*f)
         c.step(warmup)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -277,22 +281,49 @@ def bench_channel(steps=20, warmup=2):
 
 
 def cpu_baseline(n, p, u, phi, budget_s=20.0):
-    """The FP64 oracle on the host: init, then as many steps as fit in ~budget_s."""
-    import numpy as np  # noqa: F401
+    """The FP64 oracle on the host: init, then as many steps as fit in ~budget_s.
+    Also returns the oracle's states after its first and second steps, from which the
+    GPU's per-step error is measured."""
     from oracle import box
     prm = box.Params(**p)
     st = box.init_state(u, phi, prm)
     t0 = time.perf_counter()
     steps = 0
+    kept = []
     while True:
         st = box.step(st, prm)
         steps += 1
+        if steps <= 2:
+            kept.append(st)
         el = time.perf_counter() - t0
         if el > budget_s or steps >= 20:
             break
     return dict(value=n ** 3 * steps / el, unit="grid-points*timesteps/s", cores=1, kind="oracle",
                 sample="%d FP64 oracle steps of the %d^3 workload after init (numpy pocketfft, "
-                       "single-threaded), %.1f s" % (steps, n, el))
+                       "single-threaded), %.1f s" % (steps, n, el)), kept
+
+
+def oracle_error(n, p, st1, st2):
+    """Per-field rel-L2 of one GPU step (FP64 and MIXED) from the oracle's state after
+    its first step, against the oracle's second step (an AB2 step)."""
+    import numpy as np
+    import torch
+    from paper_2406_01322_amd.psms import Solver
+    hist = np.concatenate([st1["hS"], st1["hphi"][None]])
+    out = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver(n, p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=prec)
+        s.set_state(torch.from_numpy(st1["uh"]).cuda(), torch.from_numpy(st1["ph"]).cuda(),
+                    torch.from_numpy(hist).cuda(), st1["nstep"])
+        s.step(1)
+        uh, ph = (t.cpu().numpy() for t in s.get_state())
+        rel = {}
+        for name, a, b in (("u", uh[0], st2["uh"][0]), ("v", uh[1], st2["uh"][1]), ("w", uh[2], st2["uh"][2]),
+                           ("phi", ph, st2["ph"])):
+            rel[name] = float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+        out[prec] = rel
+        s.close()
+    return out
 
 
 def main():
@@ -373,12 +404,14 @@ def main():
     if not args.no_forms:
         out["forms"] = {}
         for name, fn in (("batched", bench_batch), ("adjoint", bench_adjoint), ("channel_wall_solve", bench_wall_solve),
-                         ("channel_step", bench_channel)):
+                         ("channel_step", bench_channel),
+                         ("channel_single_phase_step", lambda: bench_channel(10, 2, "chan_sp_256"))):
             out["forms"][name] = fn()
             print("[bench] %s: %s" % (name, {k: v for k, v in out["forms"][name].items() if k != "groups"}),
                   file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, p, u, phi)
+        out["cpu_baseline"], kept = cpu_baseline(n, p, u, phi)
+        out["vs_oracle_rel_l2_one_step"] = oracle_error(n, p, kept[0], kept[1])
     print(json.dumps(out), flush=True)
 
 

@@ -264,12 +264,16 @@ int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* s
  * right-hand sides and every solve are FP64.
  * ------------------------------------------------------------------------- */
 typedef struct psms_channel_params {
-  int32_t nx, ny, nc; /* nx, ny as for psms_params.n; nc in {4 6 8 12 16 24 32 48 64 96 128} */
+  int32_t nx, ny, nc; /* nx, ny as for psms_params.n; nc in {4 6 8 12 16 24 32 48 64 96 128 256} */
   int32_t precision;  /* PSMS_FP64 or PSMS_MIXED */
   double lx, ly;      /* periods in x and y */
   double re, we, ch, pe, dt;
   double s;           /* CH splitting coefficient; 0 selects sqrt(4 Pe / (Ch^2 dt)) */
   double forcing;     /* mean pressure gradient -dP/dx (1 in wall units) */
+  int32_t single_phase; /* nonzero: Navier-Stokes only (the single-phase channel
+                           timed in Sec. 3.4): phi is identically zero, the Korteweg stress and
+                           the CH solves are left out, we, ch, pe, s are not used and
+                           init_state accepts d_phi = NULL */
 } psms_channel_params;
 typedef struct psms_channel psms_channel;
 

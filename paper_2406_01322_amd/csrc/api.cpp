@@ -1275,6 +1275,9 @@ psms::ChanGeom chan_geom(const psms_channel_params& p) {
   g.NL = (long long)g.Cy * g.Hx;
   g.NZL = (long long)(p.nc + 1) * g.NL;
   g.P = (long long)(p.nc + 1) * p.ny * p.nx;
+  g.sp = p.single_phase ? 1 : 0;
+  g.nf_in = g.sp ? 3 : 7;
+  g.nf_out = g.sp ? 6 : 8;
   return g;
 }
 
@@ -1337,10 +1340,12 @@ int chan_validate(const psms_channel_params* p) {
   if (p->precision != PSMS_FP64 && p->precision != PSMS_MIXED) return fail(PSMS_E_INVAL, "precision");
   if (!psms::supported_n(p->nx) || !psms::supported_n(p->ny))
     return fail(PSMS_E_NOTSUP, "nx, ny must be one of 8 12 16 24 32 48 64 96 128 192 256");
-  if (!psms::supported_nc(p->nc)) return fail(PSMS_E_NOTSUP, "nc must be one of 4 6 8 12 16 24 32 48 64 96 128");
-  if (!(p->lx > 0) || !(p->ly > 0) || !(p->re > 0) || !(p->we > 0) || !(p->ch > 0) || !(p->pe > 0) || !(p->dt > 0) ||
-      !(p->s >= 0) || !std::isfinite(p->forcing))
-    return fail(PSMS_E_INVAL, "lx, ly, re, we, ch, pe, dt must be > 0, s >= 0, forcing finite");
+  if (!psms::supported_nc(p->nc)) return fail(PSMS_E_NOTSUP, "nc must be one of 4 6 8 12 16 24 32 48 64 96 128 256");
+  if (!(p->lx > 0) || !(p->ly > 0) || !(p->re > 0) || !(p->dt > 0) || !std::isfinite(p->forcing))
+    return fail(PSMS_E_INVAL, "lx, ly, re, dt must be > 0, forcing finite");
+  if (p->single_phase) return PSMS_OK;   // we, ch, pe, s are not used
+  if (!(p->we > 0) || !(p->ch > 0) || !(p->pe > 0) || !(p->s >= 0))
+    return fail(PSMS_E_INVAL, "we, ch, pe must be > 0, s >= 0");
   const double s = (p->s > 0.0) ? p->s : std::sqrt(4.0 * p->pe / (p->ch * p->ch * p->dt));
   if (s * s < 4.0 * p->pe / (p->ch * p->ch * p->dt) * (1.0 - 1e-12))
     return fail(PSMS_E_INVAL, "s^2 < 4 Pe / (Ch^2 dt): the CH operator has no real factors");
@@ -1459,7 +1464,7 @@ hipError_t chan_step_once(psms_channel* c) {
   if ((e = (x)) != hipSuccess) return e
   // 1-2. fields and the inverse transforms
   psms::ChebBatch cb{};
-  cb.n = 2;
+  cb.n = g.sp ? 1 : 2;
   cb.in[0] = w;
   cb.out[0] = C64(L.dw);
   cb.in[1] = phi;
@@ -1467,10 +1472,10 @@ hipError_t chan_step_once(psms_channel* c) {
   PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0, st));
   PSMS_TRY(psms::launch_ch_fields<T>(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky,
                                      c->at<cpx<T>>(L.A), st));
-  PSMS_TRY(chan_inverse<T>(c, c->at<cpx<T>>(L.A), c->at<T>(L.C), 7));
+  PSMS_TRY(chan_inverse<T>(c, c->at<cpx<T>>(L.A), c->at<T>(L.C), g.nf_in));
   // 3-4. products and the forward transforms, 2/3 rule in x, y and z
   PSMS_TRY(psms::launch_ch_products<T>(g, c->at<T>(L.C), c->coef.csig, st));
-  PSMS_TRY(chan_forward<T>(c, c->at<T>(L.C), c->at<cpx<T>>(L.A), 8));
+  PSMS_TRY(chan_forward<T>(c, c->at<T>(L.C), c->at<cpx<T>>(L.A), g.nf_out));
   PSMS_TRY(psms::launch_ch_promote<T>(g, c->at<cpx<T>>(L.A), R, st));
   // 5. S = div T, and the wall-normal derivatives the right-hand sides need
   cpx<double>* D3 = C64(L.D3);
@@ -1484,15 +1489,15 @@ hipError_t chan_step_once(psms_channel* c) {
   PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0, st));
   PSMS_TRY(psms::launch_ch_s(g, R, D3, D3 + g.NZL, D3 + 2 * g.NZL, kx, ky, C64(L.S3), C64(L.Q), st));
   PSMS_TRY(psms::launch_chebd(C64(L.Q), C64(L.DQ), nc, nl, st));
-  cb.n = 4;   // D^2 - k^2 of c, phi, omega_z and w
-  cb.in[0] = R + 7 * g.NZL;
-  cb.out[0] = C64(L.lapc);
-  cb.in[1] = phi;
-  cb.out[1] = C64(L.lapphi);
-  cb.in[2] = om;
-  cb.out[2] = C64(L.lapom);
-  cb.in[3] = w;
-  cb.out[3] = C64(L.psi);
+  cb.n = g.sp ? 2 : 4;   // D^2 - k^2 of omega_z, w, c and phi
+  cb.in[0] = om;
+  cb.out[0] = C64(L.lapom);
+  cb.in[1] = w;
+  cb.out[1] = C64(L.psi);
+  cb.in[2] = R + 7 * g.NZL;
+  cb.out[2] = C64(L.lapc);
+  cb.in[3] = phi;
+  cb.out[3] = C64(L.lapphi);
   PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 1, st));
   PSMS_TRY(psms::launch_cheb_lap(C64(L.psi), C64(L.lappsi), nc, nl, kx, ky, st));
   PSMS_TRY(psms::launch_cheb_lap(C64(L.mean), C64(L.d2mean), nc, 2, nullptr, nullptr, st));
@@ -1525,15 +1530,15 @@ hipError_t chan_step_once(psms_channel* c) {
   double* xw = c->at<double>(L.xw);
   const long long xws = (long long)(nc + 1) * nl;
   psms::HelmBatch b1{};
-  b1.np = 4;
+  b1.np = g.sp ? 3 : 4;
   b1.p[0] = psms::HelmProblem{C64(L.G), om, xw, nl, c->coef.beta, kx, ky, 0, z0, z0};                      // omega_z
   b1.p[1] = psms::HelmProblem{C64(L.G) + g.NZL, C64(L.psip), xw + xws, nl, c->coef.beta, kx, ky, 0, z0, z0};  // psi_p
-  b1.p[2] = psms::HelmProblem{C64(L.G) + 2 * g.NZL, C64(L.xi), xw + 2 * xws, nl, c->a_fac, kx, ky, 1, z0, z0};  // xi
-  b1.p[3] = psms::HelmProblem{C64(L.gmean), C64(L.mean), xw + 3 * xws, 2, c->coef.beta, nullptr, nullptr, 0, z0,
+  b1.p[2] = psms::HelmProblem{C64(L.gmean), C64(L.mean), xw + 2 * xws, 2, c->coef.beta, nullptr, nullptr, 0, z0,
                               z0};                                                                        // U, V
+  b1.p[3] = psms::HelmProblem{C64(L.G) + 2 * g.NZL, C64(L.xi), xw + 3 * xws, nl, c->a_fac, kx, ky, 1, z0, z0};  // xi
   PSMS_TRY(psms::launch_helm_batch(b1, nc, st));
   psms::HelmBatch b2{};
-  b2.np = 2;
+  b2.np = g.sp ? 1 : 2;
   b2.p[0] = psms::HelmProblem{C64(L.psip), w, xw, nl, 0.0, kx, ky, 0, z0, z0};             // w_p
   b2.p[1] = psms::HelmProblem{C64(L.xi), phi, xw + xws, nl, c->b_fac, kx, ky, 1, z0, z0};  // phi
   PSMS_TRY(psms::launch_helm_batch(b2, nc, st));
@@ -1575,19 +1580,22 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
   c->lay = lay;
   c->ws = static_cast<char*>(d_workspace);
   c->stream = static_cast<hipStream_t>(stream);
-  const double s = (p->s > 0.0) ? p->s : std::sqrt(4.0 * p->pe / (p->ch * p->ch * p->dt));
-  const double ab = p->pe / (p->dt * p->ch * p->ch);
-  const double d = std::sqrt(std::max(s * s - 4.0 * ab, 0.0));
-  c->a_fac = 0.5 * (s - d);
-  c->b_fac = 0.5 * (s + d);
+  c->coef = psms::ChanCoef{};
+  if (!p->single_phase) {
+    const double s = (p->s > 0.0) ? p->s : std::sqrt(4.0 * p->pe / (p->ch * p->ch * p->dt));
+    const double ab = p->pe / (p->dt * p->ch * p->ch);
+    const double d = std::sqrt(std::max(s * s - 4.0 * ab, 0.0));
+    c->a_fac = 0.5 * (s - d);
+    c->b_fac = 0.5 * (s + d);
+    c->coef.inv_pe = 1.0 / p->pe;
+    c->coef.e_coef = (1.0 + s * p->ch * p->ch) / p->pe;
+    c->coef.g_phi_scale = ab;
+    c->coef.csig = 3.0 / std::sqrt(8.0) * p->ch / p->we;
+  }
   c->coef.re = p->re;
   c->coef.beta = 2.0 * p->re / p->dt;
-  c->coef.inv_pe = 1.0 / p->pe;
-  c->coef.e_coef = (1.0 + s * p->ch * p->ch) / p->pe;
-  c->coef.g_phi_scale = ab;
   c->coef.dt = p->dt;
   c->coef.forcing = p->forcing;
-  c->coef.csig = 3.0 / std::sqrt(8.0) * p->ch / p->we;
   c->coef.ab1 = 1;
   c->nstep = 0;
   c->have_state = 0;
@@ -1658,18 +1666,20 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
 
 int psms_channel_init_state(psms_channel* c, const double* d_u, const double* d_v, const double* d_w,
                             const double* d_phi) {
-  if (!c || !d_u || !d_v || !d_w || !d_phi) return fail(PSMS_E_INVAL, "NULL argument");
+  if (!c || !d_u || !d_v || !d_w || (!d_phi && !c->g.sp)) return fail(PSMS_E_INVAL, "NULL argument");
   const psms::ChanGeom& g = c->g;
   const ChanLayout& L = c->lay;
-  // FP64 forward chain of the 4 fields through the step's buffers: in MIXED the
-  // physical, y-expanded and band buffers hold 8 FP32 fields, i.e. 4 FP64 ones
+  // FP64 forward chain of the 4 fields (3 in single phase) through the step's
+  // buffers: in MIXED the physical, y-expanded and band buffers hold 8 FP32
+  // fields, i.e. 4 FP64 ones
   double* C = c->at<double>(L.C);
   cpx<double>* A = c->at<cpx<double>>(L.R);
   hipError_t e = hipSuccess;
   const double* src[4] = {d_u, d_v, d_w, d_phi};
-  for (int f = 0; f < 4 && e == hipSuccess; ++f)
+  const int nf = g.sp ? 3 : 4;
+  for (int f = 0; f < nf && e == hipSuccess; ++f)
     e = hipMemcpyAsync(C + f * g.P, src[f], size_t(g.P) * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) e = chan_forward<double>(c, C, A, 4);
+  if (e == hipSuccess) e = chan_forward<double>(c, C, A, nf);
   if (e == hipSuccess)
     e = psms::launch_ch_init(g, A, c->at<double>(L.kx), c->at<double>(L.ky), c->at<cpx<double>>(L.state),
                              c->at<cpx<double>>(L.state) + g.NZL, c->at<cpx<double>>(L.state) + 2 * g.NZL,
@@ -1707,6 +1717,13 @@ int psms_channel_set_state(psms_channel* c, const double* d_state, const double*
       e = hipMemsetAsync(c->ws + L.hist, 0, sz, c->stream);
       if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.hmean, 0, 2 * size_t(g.nc + 1) * sizeof(cpx<double>), c->stream);
     }
+  }
+  if (e == hipSuccess && g.sp) {   // phi and its history are identically zero
+    e = hipMemsetAsync(c->ws + L.state + size_t(2 * g.NZL) * sizeof(cpx<double>), 0,
+                       size_t(g.NZL) * sizeof(cpx<double>), c->stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(c->ws + L.hist + size_t(2 * g.NZL) * sizeof(cpx<double>), 0,
+                         size_t(g.NZL) * sizeof(cpx<double>), c->stream);
   }
   if (e != hipSuccess) return hip_fail(e, "channel_set_state");
   c->nstep = nstep;

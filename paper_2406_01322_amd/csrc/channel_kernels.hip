@@ -24,15 +24,17 @@ namespace psms {
 
 namespace {
 
-// 16 lines per workgroup: the lanes of a position read 16 consecutive lines
-// (128 bytes in FP32), and the LDS tile stays within 160 KB in FP64.
+// 16 lines per workgroup (8 for the 512-point extension, nc = 256): the lanes
+// of a position read 16 consecutive lines (128 bytes in FP32), and the LDS
+// tile stays within 160 KB in FP64.
 template <class P>
 struct CTile {
   static constexpr int N = P::N;
   static constexpr int E = P::E;
   static constexpr int TT = N / E;
-  static constexpr int L = 16;
+  static constexpr int L = (16 * TT <= 1024) ? 16 : 1024 / TT;
   static_assert(L * TT <= 1024, "workgroup size");
+  static_assert(2 * N * (L + 1) * 16 + N * 16 <= 160 * 1024, "LDS tile");
 };
 
 }  // namespace
@@ -433,7 +435,7 @@ __global__ void k_uv(const cpx<double>* __restrict__ om, const cpx<double>* __re
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define PSMS_FOR_EACH_2NC(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+#define PSMS_FOR_EACH_2NC(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(512)
 
 bool supported_nc(int nc) {
   switch (2 * nc) {

@@ -46,15 +46,33 @@ __global__ void k_ch_fields(ChanGeom g, const cpx<double>* __restrict__ om, cons
       u = scl(ik2, ti(1.0, add(scl(kx, d), scl(ky, o))));
       v = scl(ik2, ti(1.0, sub(scl(ky, d), scl(kx, o))));
     }
-    const cpx<double> p = phi[id];
-    const cpx<double> f[7] = {u, v, w[id], p, ti(kx, p), ti(ky, p), dphi[id]};
+    const cpx<double> ww = w[id];
+    out[id] = cpx<T>{T(u.re), T(u.im)};
+    out[g.NZL + id] = cpx<T>{T(v.re), T(v.im)};
+    out[2 * g.NZL + id] = cpx<T>{T(ww.re), T(ww.im)};
+    if (!g.sp) {
+      const cpx<double> p = phi[id];
+      const cpx<double> f[4] = {p, ti(kx, p), ti(ky, p), dphi[id]};
 #pragma unroll
-    for (int k = 0; k < 7; ++k) out[k * g.NZL + id] = cpx<T>{T(f[k].re), T(f[k].im)};
+      for (int k = 0; k < 4; ++k) out[(k + 3) * g.NZL + id] = cpx<T>{T(f[k].re), T(f[k].im)};
+    }
   }
 }
 
 template <typename T>
 __global__ void k_ch_products(ChanGeom g, T* __restrict__ f, T cs) {
+  if (g.sp) {
+    PSMS_GRID_LOOP(id, g.P) {
+      const T u = f[id], v = f[g.P + id], w = f[2 * g.P + id];
+      f[id] = -u * u;
+      f[g.P + id] = -v * v;
+      f[2 * g.P + id] = -w * w;
+      f[3 * g.P + id] = -u * v;
+      f[4 * g.P + id] = -u * w;
+      f[5 * g.P + id] = -v * w;
+    }
+    return;
+  }
   PSMS_GRID_LOOP(id, g.P) {
     const T u = f[id], v = f[g.P + id], w = f[2 * g.P + id], p = f[3 * g.P + id];
     const T gx = f[4 * g.P + id], gy = f[5 * g.P + id], gz = f[6 * g.P + id];
@@ -71,7 +89,7 @@ __global__ void k_ch_products(ChanGeom g, T* __restrict__ f, T cs) {
 
 template <typename T>
 __global__ void k_ch_promote(ChanGeom g, const cpx<T>* __restrict__ in, cpx<double>* __restrict__ out) {
-  PSMS_GRID_LOOP(id, 8 * g.NZL) {
+  PSMS_GRID_LOOP(id, g.nf_out * g.NZL) {
     const long long n = (id % g.NZL) / g.NL;
     const cpx<T> x = in[id];
     out[id] = (n > g.Kz) ? cpx<double>{0.0, 0.0} : cpx<double>{double(x.re), double(x.im)};
@@ -109,19 +127,21 @@ __global__ void k_ch_assemble(ChanGeom g, ChanCoef c, ChanAssembleArgs a) {
     const cpx<double> sx = a.s3[id], sy = a.s3[g.NZL + id], sz = a.s3[2 * g.NZL + id];
     const cpx<double> h_om = sub(ti(kx, sy), ti(ky, sx));                    // (curl S)_z
     const cpx<double> h_w = sub(scl(-k2, sz), a.dq[id]);                     // lap_h S_z - D(div_h S)
-    const cpx<double> s_phi = add(sub(scl(c.inv_pe, a.lapc[id]), a.R[6 * g.NZL + id]),
-                                  scl(-c.e_coef, a.lapphi[id]));            // -a + lap c / Pe - (1 + s Ch^2)/Pe lap phi
     const cpx<double> e_om = ab(h_om, a.hist[id], c.ab1);
     const cpx<double> e_w = ab(h_w, a.hist[g.NZL + id], c.ab1);
-    const cpx<double> e_phi = ab(s_phi, a.hist[2 * g.NZL + id], c.ab1);
     a.hist[id] = h_om;
     a.hist[g.NZL + id] = h_w;
-    a.hist[2 * g.NZL + id] = s_phi;
     const double r2 = 2.0 * c.re;
     const cpx<double> om = a.om[id], psi = a.psi[id];
     a.g[id] = sub(scl(-1.0, add(a.lapom[id], scl(c.beta, om))), scl(r2, e_om));
     a.g[g.NZL + id] = sub(scl(-1.0, add(a.lappsi[id], scl(c.beta, psi))), scl(r2, e_w));
-    a.g[2 * g.NZL + id] = scl(c.g_phi_scale, add(a.phi[id], scl(c.dt, e_phi)));
+    if (!g.sp) {
+      const cpx<double> s_phi = add(sub(scl(c.inv_pe, a.lapc[id]), a.R[6 * g.NZL + id]),
+                                    scl(-c.e_coef, a.lapphi[id]));  // -a + lap c / Pe - (1 + s Ch^2)/Pe lap phi
+      const cpx<double> e_phi = ab(s_phi, a.hist[2 * g.NZL + id], c.ab1);
+      a.hist[2 * g.NZL + id] = s_phi;
+      a.g[2 * g.NZL + id] = scl(c.g_phi_scale, add(a.phi[id], scl(c.dt, e_phi)));
+    }
     if (l == 0) {  // mean flow: S_x, S_y of the mean line, driving -dP/dx = forcing on T_0
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
@@ -151,7 +171,7 @@ __global__ void k_ch_init(ChanGeom g, const cpx<double>* __restrict__ U4, const 
       om[id] = sub(ti(kxl[l], v), ti(kyl[l], u));
       w[id] = U4[2 * g.NZL + id];
     }
-    phi[id] = U4[3 * g.NZL + id];
+    phi[id] = g.sp ? cpx<double>{0.0, 0.0} : U4[3 * g.NZL + id];
   }
 }
 
@@ -179,7 +199,7 @@ hipError_t launch_ch_products(const ChanGeom& g, T* f, double csig, hipStream_t 
 }
 template <typename T>
 hipError_t launch_ch_promote(const ChanGeom& g, const cpx<T>* in, cpx<double>* out, hipStream_t st) {
-  k_ch_promote<T><<<blocks_for(8 * g.NZL), kThreads, 0, st>>>(g, in, out);
+  k_ch_promote<T><<<blocks_for(g.nf_out * g.NZL), kThreads, 0, st>>>(g, in, out);
   return hipGetLastError();
 }
 hipError_t launch_ch_s(const ChanGeom& g, const cpx<double>* R, const cpx<double>* dxz, const cpx<double>* dyz,

@@ -17,6 +17,8 @@ struct ChanGeom {
   long long NL;            // lines Cy * Hx
   long long NZL;           // (nc + 1) * NL
   long long P;             // (nc + 1) * ny * nx physical points
+  int sp;                  // single phase: phi = 0, no Korteweg stress, no CH terms
+  int nf_in, nf_out;       // fields transformed to physical space / back (7, 8; 3, 6 single phase)
 };
 
 struct ChanCoef {
@@ -26,15 +28,17 @@ struct ChanCoef {
   int ab1;
 };
 
-// the 7 spectral fields u, v, w, phi, i kx phi, i ky phi, D phi (precision T)
+// the 7 spectral fields u, v, w, phi, i kx phi, i ky phi, D phi (precision T);
+// u, v, w only in single phase
 template <typename T>
 hipError_t launch_ch_fields(const ChanGeom& g, const cpx<double>* om, const cpx<double>* w, const cpx<double>* phi,
                             const cpx<double>* dw, const cpx<double>* dphi, const cpx<double>* mean, const double* kx,
                             const double* ky, cpx<T>* out, hipStream_t st);
-// pointwise products, 7 physical fields in, 8 out (in place, [8][P])
+// pointwise products, 7 physical fields in, 8 out (in place, [8][P]); single
+// phase 3 in, the 6 components of -u_i u_j out
 template <typename T>
 hipError_t launch_ch_products(const ChanGeom& g, T* f, double csig, hipStream_t st);
-// 8 transformed products (precision T) -> FP64 with Chebyshev modes n > Kz zeroed
+// g.nf_out transformed products (precision T) -> FP64 with Chebyshev modes n > Kz zeroed
 template <typename T>
 hipError_t launch_ch_promote(const ChanGeom& g, const cpx<T>* in, cpx<double>* out, hipStream_t st);
 // S_x, S_y, S_z and Q = i kx S_x + i ky S_y from the products and D T_xz, D T_yz, D T_zz
@@ -65,7 +69,8 @@ struct ChanAssembleArgs {
   cpx<double>* gmean;         // [nc+1][2]
 };
 hipError_t launch_ch_assemble(const ChanGeom& g, const ChanCoef& c, const ChanAssembleArgs& a, hipStream_t st);
-// initial state from the 4 transformed physical fields u, v, w, phi ([4][NZL], FP64)
+// initial state from the 4 transformed physical fields u, v, w, phi ([4][NZL], FP64;
+// 3 in single phase, phi set to zero)
 hipError_t launch_ch_init(const ChanGeom& g, const cpx<double>* U4, const double* kx, const double* ky,
                           cpx<double>* om, cpx<double>* w, cpx<double>* phi, cpx<double>* mean, hipStream_t st);
 // mean lines: [2][nc+1] (caller) <-> [nc+1][2] (internal); dir > 0 copies into internal

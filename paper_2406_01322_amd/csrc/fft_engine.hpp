@@ -90,6 +90,7 @@ template <> struct PlanSel<32>  { using type = PlanT<32, 4, 4, 4, 2>; };
 template <> struct PlanSel<64>  { using type = PlanT<64, 4, 4, 4, 4>; };
 template <> struct PlanSel<128> { using type = PlanT<128, 4, 4, 4, 4, 2>; };
 template <> struct PlanSel<256> { using type = PlanT<256, 4, 4, 4, 4, 4>; };
+template <> struct PlanSel<512> { using type = PlanT<512, 4, 4, 4, 4, 4, 2>; };
 template <> struct PlanSel<12>  { using type = PlanT<12, 6, 3, 2, 2>; };
 template <> struct PlanSel<24>  { using type = PlanT<24, 6, 3, 2, 2, 2>; };
 template <> struct PlanSel<48>  { using type = PlanT<48, 6, 3, 2, 2, 2, 2>; };

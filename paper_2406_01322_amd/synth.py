@@ -272,11 +272,18 @@ def channel_case(name: str):
       chan_small: 16 x 12 x 17, Re_tau 20, 2 drops R = 0.4, Ch 0.1 (seed 11);
       chan_mid:   32 x 24 x 33, Re_tau 50, 4 drops R = 0.3, Ch 0.05 (seed 12);
       chan_256:   256 x 128 x 129 on 4 pi x 2 pi x 2, Re_tau 150, 64 drops R = 0.2,
-                  Ch 0.02, We 3, Pe 50, dt 1e-4 (seed 3)."""
+                  Ch 0.02, We 3, Pe 50, dt 1e-4 (seed 3).
+    Single-phase cases (no drops, phi = 0; params carry single_phase=True and
+    placeholder we = ch = pe = 1, which do not enter a step with phi = 0):
+      chan_sp_small: 16 x 12 x 257, Re_tau 150, dt 1e-4 (seed 13);
+      chan_sp_256:   256 x 256 x 257 on 4 pi x 2 pi x 2, Re_tau 150, dt 1e-4 (seed 7),
+                     the grid of the single-phase timing runs of Sec. 3.4."""
     table = {
         "chan_small": (dict(nx=16, ny=12, nc=16, re=20.0, we=1.0, ch=0.1, pe=10.0, dt=1e-3), 2, 0.4, 11),
         "chan_mid": (dict(nx=32, ny=24, nc=32, re=50.0, we=2.0, ch=0.05, pe=20.0, dt=5e-4), 4, 0.3, 12),
         "chan_256": (dict(nx=256, ny=128, nc=128, re=150.0, we=3.0, ch=0.02, pe=50.0, dt=1e-4), 64, 0.2, 3),
+        "chan_sp_small": (dict(nx=16, ny=12, nc=256, re=150.0, we=1.0, ch=1.0, pe=1.0, dt=1e-4), 0, 0.0, 13),
+        "chan_sp_256": (dict(nx=256, ny=256, nc=256, re=150.0, we=1.0, ch=1.0, pe=1.0, dt=1e-4), 0, 0.0, 7),
     }
     p, nd, radius, seed = table[name]
     p = dict(p, lx=4.0 * math.pi, ly=2.0 * math.pi)
@@ -286,5 +293,8 @@ def channel_case(name: str):
     uc = p["re"] / 2.0
     up, vp, wp = channel_perturbation(X, Y, Z, p["lx"], p["ly"], rng, mmax, 0.1 * uc)
     u = uc * (1.0 - Z ** 2) + up
+    if nd == 0:
+        p["single_phase"] = True
+        return p, u, vp, wp, np.zeros_like(u)
     phi = channel_drops(X, Y, Z, p["lx"], p["ly"], rng, nd, radius, p["ch"])
     return p, u, vp, wp, phi

@@ -16,7 +16,7 @@ from oracle import channel as ch
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-NCS = [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128]
+NCS = [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256]
 BETA_NS = 2.0 * 150.0 / 1e-4
 BETA_CH = math.sqrt(50.0 / (1e-4 * 0.02 ** 2))
 
@@ -54,7 +54,7 @@ def test_cheb_transform_parity(nc, nl):
     assert np.max(np.abs(a32 - want32)) < 3e-7 * max(1.0, math.log2(nc)) * np.max(np.abs(want32))
 
 
-@pytest.mark.parametrize("nc", [4, 16, 128])
+@pytest.mark.parametrize("nc", [4, 16, 128, 256])
 def test_cheb_deriv_parity(nc):
     from paper_2406_01322_amd import psms
     a = _lines(nc, 53, 7, decay=0.05)
@@ -64,7 +64,7 @@ def test_cheb_deriv_parity(nc):
 
 
 @pytest.mark.parametrize("kind", ["dirichlet", "neumann"])
-@pytest.mark.parametrize("nc", [8, 32, 128])
+@pytest.mark.parametrize("nc", [8, 32, 128, 256])
 @pytest.mark.parametrize("beta_scale", [1.0, 1e3, BETA_CH, BETA_NS])
 def test_cheb_helmholtz_parity(kind, nc, beta_scale):
     from paper_2406_01322_amd import psms
@@ -91,7 +91,7 @@ def _kgrid(nkx, nky):
     return kx, ky
 
 
-@pytest.mark.parametrize("nc,nkx,nky", [(16, 3, 5), (32, 4, 7), (128, 3, 3)])
+@pytest.mark.parametrize("nc,nkx,nky", [(16, 3, 5), (32, 4, 7), (128, 3, 3), (256, 2, 3)])
 def test_wall_solve_parity(nc, nkx, nky):
     from paper_2406_01322_amd import psms
     kx, ky = _kgrid(nkx, nky)              # includes the mean line kx = ky = 0

@@ -19,10 +19,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _gpu(p, precision):
+def _gpu(p, precision, single_phase=None):
     from paper_2406_01322_amd.psms import Channel
+    sp = p.get("single_phase", False) if single_phase is None else single_phase
     return Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision,
-                   lx=p["lx"], ly=p["ly"])
+                   lx=p["lx"], ly=p["ly"], single_phase=sp)
 
 
 def _dev(a):
@@ -52,7 +53,7 @@ def _rel_l2(a, b):
 
 def _case(name):
     p, u, v, w, phi = synth.channel_case(name)
-    return p, cs.ChannelParams(**p), (u, v, w, phi)
+    return p, cs.ChannelParams(**{k: x for k, x in p.items() if k != "single_phase"}), (u, v, w, phi)
 
 
 @pytest.mark.parametrize("name", ["chan_small", "chan_mid"])
@@ -142,3 +143,94 @@ def test_channel_step_before_init_is_rejected():
     with pytest.raises(PsmsError) as e:
         c.step(1)
     assert e.value.code == -6
+
+
+# ---------------------------------------------------------------------------
+# single phase (Navier-Stokes alone): the oracle's step with phi = 0, in which
+# every Korteweg and CH term vanishes identically
+# ---------------------------------------------------------------------------
+
+def test_single_phase_equals_two_phase_with_zero_phi():
+    """The single-phase path (3 fields to physical space, 6 products back, no CH
+    solves) gives the two-phase step with phi = 0, up to rounding."""
+    p, prm, f = _case("chan_small")
+    u, v, w, _ = f
+    zero = np.zeros_like(u)
+    out = []
+    for sp in (False, True):
+        c = _gpu(p, "fp64", single_phase=sp)
+        c.init_state(_dev(u), _dev(v), _dev(w), _dev(zero) if not sp else None)
+        c.step(3)
+        out.append([_host(t) for t in c.get_state(with_history=True)])
+    for a, b in zip(out[0], out[1]):
+        assert _rel_max(b, a) < 1e-13
+    assert np.all(out[1][0][2] == 0.0)
+
+
+@pytest.mark.parametrize("nprev", [0, 1])
+def test_single_phase_nc256_parity_fp64(nprev):
+    """16 x 12 x 257 (the 512-point Chebyshev extension), Re_tau 150, dt 1e-4.
+    The history holds H_w = lap_h S_z - D div_h S: the norm of D grows as nc^2, so the
+    rounding of the transformed products reaches it 4 times amplified from nc = 128,
+    where the bound is 1e-9: 4e-9 here."""
+    p, prm, f = _case("chan_sp_small")
+    st = cs.run(cs.init_state(*f, prm), prm, nprev)
+    ref = cs.step(st, prm)
+    c = _gpu(p, "fp64")
+    _load(c, st)
+    c.step(1)
+    state, mean, hist, hmean = (_host(t) for t in c.get_state(with_history=True))
+    tol = 1e-9 * (p["nc"] / 128) ** 2
+    for i, k in enumerate(("om", "w")):
+        assert _rel_max(state[i], ref[k]) < tol, (k, _rel_max(state[i], ref[k]))
+        assert _rel_max(hist[i], ref["h_" + k]) < tol, (k, _rel_max(hist[i], ref["h_" + k]))
+    assert np.all(state[2] == 0.0)
+    assert _rel_max(mean, ref["mean"]) < tol
+    assert _rel_max(hmean, ref["h_mean"]) < tol
+
+
+def test_single_phase_nc256_parity_mixed():
+    p, prm, f = _case("chan_sp_small")
+    st = cs.run(cs.init_state(*f, prm), prm, 1)
+    ref = cs.step(st, prm)
+    c = _gpu(p, "mixed")
+    _load(c, st)
+    c.step(1)
+    state, mean = (_host(t) for t in c.get_state())
+    for i, k in enumerate(("om", "w")):
+        assert _rel_l2(state[i], ref[k]) < 1e-5, (k, _rel_l2(state[i], ref[k]))
+    assert _rel_l2(mean, ref["mean"]) < 1e-5
+
+
+@pytest.fixture(scope="module")
+def sp256():
+    """256 x 256 x 257 single phase: the oracle's first (Adams-Bashforth 1) step from
+    the initial state, on sampled lines."""
+    p, prm, f = _case("chan_sp_256")
+    st = cs.init_state(*f, prm)
+    lines = [(0, 0), (1, 0), (0, 1), (1, 1), (85, 85), (84, 85), (3, 84), (40, 20)]
+    ref = cs.step(st, prm, lines=lines)
+    return p, f, lines, ref
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 4e-9), ("mixed", 1e-5)])
+def test_single_phase_256_sampled_lines(sp256, precision, tol):
+    """FP64: each sampled line to its own scale (the nc = 256 bound above); the
+    band-edge lines, which the first step from modes |k| <= 4 leaves at zero up to
+    rounding, to the rounding level of the field (1e-14 of its largest line)."""
+    p, f, lines, ref = sp256
+    c = _gpu(p, precision)
+    c.init_state(*[_dev(x) for x in f[:3]])
+    c.step(1)
+    state, mean = (_host(t) for t in c.get_state())
+    for i, k in enumerate(("om", "w")):
+        a = np.stack([state[i][:, iy, ix] for iy, ix in lines])
+        b = np.stack([ref[k][:, iy, ix] for iy, ix in lines])
+        if precision == "fp64":
+            floor = 1e-14 * np.max(np.abs(b))
+            for j, (iy, ix) in enumerate(lines):
+                scale = np.max(np.abs(b[j]))
+                assert np.max(np.abs(a[j] - b[j])) <= tol * scale + floor, (k, iy, ix)
+        else:
+            assert _rel_l2(a, b) < tol, (k, _rel_l2(a, b))
+    assert _rel_max(mean, ref["mean"]) < tol
