@@ -61,9 +61,10 @@ def step_model_bytes(n, mixed):
     8 RHS fields written and read)."""
     P = n ** 3
     M = band(n)[4]
-    w_phys = 4 if mixed else 8
-    w_rhs = 8 if mixed else 16
-    return w_phys * 30 * P + 16 * 2 * 20 * M + w_rhs * 2 * 16 * M
+    w_phys = 4 if mixed else 8      # bytes per real word, physical fields
+    w_rhs = 4 if mixed else 8       # bytes per real word, RHS fields
+    w_state = 8                     # FP64 state and history
+    return w_phys * 30 * P + w_state * 2 * 20 * M + w_rhs * 2 * 16 * M
 
 
 def measured_traffic(stage):

@@ -25,6 +25,8 @@
 // blockIdx.z, so one launch advances every box of a given size.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 
 #include "box_kernels.hpp"
 #include "fft_engine.hpp"
@@ -245,6 +247,76 @@ __global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in,
 template <typename T, int N>
 constexpr int kXstepWaves = (sizeof(T) == 4 && N <= 128 && (N & (N - 1)) == 0) ? 4 : 1;
 
+// Staging of the x stage's inputs through LDS by direct global->LDS copies.
+// A wavefront transforms LPW = 64 / TT consecutive row pairs, i.e. 2 LPW
+// consecutive rows of H retained complex values each: one contiguous run of
+// BYTES bytes per field, copied in 16-byte pieces (lane l of copy i moves
+// piece 64 i + l to byte 16 (64 i + l) of the staging area).
+template <typename T, int N, int TT, int H>
+struct XStage {
+  static_assert(TT <= 64 && 64 % TT == 0, "a wavefront holds whole lines");
+  static constexpr int LPW = 64 / TT;
+  static constexpr int BYTES = LPW * 2 * H * int(sizeof(cpx<T>));
+  static_assert(BYTES % 16 == 0, "16-byte pieces");
+  static constexpr int PIECES = BYTES / 16;
+  static constexpr int NI = (PIECES + 63) / 64;
+};
+// Used where one wavefront holds one line (N = 256): measured faster there,
+// and slower than register loads for the shorter lines.
+template <typename T, int N>
+constexpr bool kXstepDma = (N >= 256);
+
+// Copy the pieces of one field that lie within `left` bytes of src.  dst is
+// the wavefront's staging area (wave-uniform); each active lane's 16 bytes
+// land at dst + 1024 i + 16 lane.
+template <class XS>
+__device__ __forceinline__ void xstage_copy(const char* src, char* dst, int lane, long long left) {
+#pragma unroll
+  for (int i = 0; i < XS::NI; ++i) {
+    const int j = i * 64 + lane;
+    if (j < XS::PIECES && (long long)(j + 1) * 16 <= left)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + 16 * j),
+                                       (__attribute__((address_space(3))) void*)(dst + 1024 * i), 16, 0, 0);
+  }
+}
+// the copies issued by this wavefront have landed in LDS (vmcnt = 0)
+__device__ __forceinline__ void xstage_wait() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unconstrained
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+// this wavefront's reads of the staging area have completed (lgkmcnt = 0), so
+// the next copies may overwrite it
+__device__ __forceinline__ void xstage_release() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Product F of the x stage (divergence form, eqs. NSE, kort, CHE) at slot e,
+// component c (0: row 2l, 1: row 2l + 1) of the 7 physical fields u, v, w,
+// phi, dx phi, dy phi, dz phi.
+template <int F, typename T, int E>
+__device__ __forceinline__ T xproduct(const cpx<T> (&ph)[7][E], int e, int c, T cs) {
+  const T u = c ? ph[0][e].im : ph[0][e].re;
+  const T vv = c ? ph[1][e].im : ph[1][e].re;
+  const T w = c ? ph[2][e].im : ph[2][e].re;
+  const T p3 = c ? ph[3][e].im : ph[3][e].re;
+  const T gx = c ? ph[4][e].im : ph[4][e].re;
+  const T gy = c ? ph[5][e].im : ph[5][e].re;
+  const T gz = c ? ph[6][e].im : ph[6][e].re;
+  if constexpr (F == 0) return -u * u + cs * (gy * gy + gz * gz);      // T_xx
+  else if constexpr (F == 1) return -vv * vv + cs * (gx * gx + gz * gz);  // T_yy
+  else if constexpr (F == 2) return -w * w + cs * (gx * gx + gy * gy);    // T_zz
+  else if constexpr (F == 3) return -u * vv - cs * gx * gy;               // T_xy
+  else if constexpr (F == 4) return -u * w - cs * gx * gz;                // T_xz
+  else if constexpr (F == 5) return -vv * w - cs * gy * gz;               // T_yz
+  else if constexpr (F == 6) return u * gx + vv * gy + w * gz;            // u . grad phi
+  else return p3 * p3 * p3;                                               // phi^3
+}
+
 template <typename T, int N, int V>
 __global__ void __launch_bounds__(64 << V) __attribute__((amdgpu_waves_per_eu(kXstepWaves<T, N>)))
 k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ tw_g) {
@@ -259,9 +331,11 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
   constexpr int RP = last_radix<P, 1>();    // inverse ends / forward starts with R[0]
   constexpr int RO = last_radix<P, -1>();   // forward ends with R[NST-1]
   constexpr long long ROWS = (long long)N * N;
+  constexpr bool XDMA = kXstepDma<T, N>;
   __shared__ cpx<T> twf[tw_size<P, -1>()];
   __shared__ cpx<T> twi[tw_size<P, 1>()];
   __shared__ cpx<T> lds[2][L * LP];
+  __shared__ __attribute__((aligned(16))) char xstage_lds[XDMA ? (64 << V) / 64 * 2 * XStage<T, N, TT, H>::BYTES : 16];
   const int tid = threadIdx.x;
   const int t = tid % TT, line = tid / TT;
   build_twiddles<T, P, -1>(twf, [&](int m) { return tw_g[m]; }, tid, int(blockDim.x));
@@ -317,8 +391,30 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
   };
   constexpr int FS = L * LP;  // buffer of the second transform of a pair
   constexpr bool PF = kXstepWaves<T, N> == 1;  // registers to spare for prefetching
+  // Direct-to-LDS staging: the rows of one field that a wavefront transforms
+  // are one contiguous run of XS::BYTES bytes, copied by a few 16-byte
+  // global_load_lds instructions into the wavefront's staging area while the
+  // previous pair is transformed (no registers held in flight).
+  using XS = XStage<T, N, TT, H>;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  char* stg = xstage_lds + wv * 2 * XS::BYTES;
+  // first row of the wavefront (uniform across it)
+  const int wrow0 = __builtin_amdgcn_readfirstlane(int(r0) - 2 * ((tid & 63) / TT));
+  auto dma_pair = [&](int vf0) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int vf = vf0 + g;
+      if (vf >= 7) continue;
+      const int fin = (vf <= 3) ? vf : vf - 1;
+      const char* src = reinterpret_cast<const char*>(yin + (long long)fin * ROWS * H + (long long)wrow0 * H);
+      const long long left = (ROWS - wrow0) * H * (long long)sizeof(cpx<T>);   // bytes of the field from here
+      xstage_copy<XS>(src, stg + g * XS::BYTES, lane, left);
+    }
+  };
   cpx<T> ra[2][E], rb[2][E];
-  if (PF) {
+  if (XDMA) {
+    dma_pair(0);
+  } else if (PF) {
     load_raw(0, ra[0], rb[0]);
     load_raw(1, ra[1], rb[1]);
   }
@@ -326,7 +422,27 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
   for (int vf = 0; vf < 7; vf += 2) {
     const int nf = (vf + 1 < 7) ? 2 : 1;
     cpx<T> v[2][E];
-    if (PF) {
+    if (XDMA) {
+      xstage_wait();
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (g < nf) {
+          const cpx<T>* sg = reinterpret_cast<const cpx<T>*>(stg + g * XS::BYTES) + ((tid & 63) / TT) * 2 * H;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int p = slot_pos<P, RI>(t, e / RI, e % RI);
+            const int k = (p <= N / 2) ? p : N - p;
+            cpx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
+            if (valid && k <= K) {
+              A = sg[k];
+              B = sg[H + k];
+            }
+            pack_slot(vf + g, e, A, B, v[g][e]);
+          }
+        }
+      xstage_release();
+      if (vf + 2 < 7) dma_pair(vf + 2);
+    } else if (PF) {
 #pragma unroll
       for (int g = 0; g < 2; ++g)
         if (g < nf) pack(vf + g, ra[g], rb[g], v[g]);
@@ -358,43 +474,19 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
         for (int e = 0; e < E; ++e) ph[vf + g][e] = v[g][e];
   }
 
-  // products and x-forward, two fields at a time
+  // products and x-forward, two fields at a time; the field indices are
+  // compile-time constants, so the products are straight-line code with no
+  // per-element branching
   const T cs = T(csig_d);
   const T h = T(0.5);
   static_assert(RP == first_radix<P, -1>(), "mirrored radix order");
-#pragma unroll 1
-  for (int f0 = 0; f0 < 8; f0 += 2) {
+  auto fwd_pair = [&](auto fac, auto fbc) {
+    constexpr int fa = decltype(fac)::value, fb = decltype(fbc)::value;
     cpx<T> v[2][E];
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const int f = f0 + g;
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        T res[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const T u = c ? ph[0][e].im : ph[0][e].re;
-          const T vv = c ? ph[1][e].im : ph[1][e].re;
-          const T w = c ? ph[2][e].im : ph[2][e].re;
-          const T p3 = c ? ph[3][e].im : ph[3][e].re;
-          const T gx = c ? ph[4][e].im : ph[4][e].re;
-          const T gy = c ? ph[5][e].im : ph[5][e].re;
-          const T gz = c ? ph[6][e].im : ph[6][e].re;
-          T x;
-          switch (f) {
-            case 0: x = -u * u + cs * (gy * gy + gz * gz); break;     // T_xx
-            case 1: x = -vv * vv + cs * (gx * gx + gz * gz); break;   // T_yy
-            case 2: x = -w * w + cs * (gx * gx + gy * gy); break;     // T_zz
-            case 3: x = -u * vv - cs * gx * gy; break;                // T_xy
-            case 4: x = -u * w - cs * gx * gz; break;                 // T_xz
-            case 5: x = -vv * w - cs * gy * gz; break;                // T_yz
-            case 6: x = u * gx + vv * gy + w * gz; break;             // u . grad phi
-            default: x = p3 * p3 * p3; break;                         // phi^3
-          }
-          res[c] = x;
-        }
-        v[g][e] = cpx<T>{res[0], res[1]};
-      }
+    for (int e = 0; e < E; ++e) {
+      v[0][e] = cpx<T>{xproduct<fa>(ph, e, 0, cs), xproduct<fa>(ph, e, 1, cs)};
+      v[1][e] = cpx<T>{xproduct<fb>(ph, e, 0, cs), xproduct<fb>(ph, e, 1, cs)};
     }
     fft_lines<T, P, -1, 2>(v, lds[0], FS, 0, par, t, idx, twf);
     // natural order through the pair's buffers, then the retained kx of both rows
@@ -407,7 +499,7 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
     wave_lds_sync();  // the line's threads are one wavefront's lanes
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
-      cpx<T>* dst = xout + (long long)(f0 + g) * ROWS * H;
+      cpx<T>* dst = xout + (long long)(g ? fb : fa) * ROWS * H;
       for (int k = t; valid && k < H; k += TT) {
         const cpx<T> zk = lds[g][idx(k)];
         const cpx<T> zm = lds[g][idx((N - k) % N)];
@@ -415,7 +507,14 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
         st_global(dst + (r0 + 1) * H + k, cpx<T>{h * (zk.im + zm.im), h * (zm.re - zk.re)});
       }
     }
-  }
+  };
+  // phi^3 and u . grad phi first: phi is then dead for the other three pairs,
+  // and this order fits the four-wavefront register budget without spills
+  using std::integral_constant;
+  fwd_pair(integral_constant<int, 7>(), integral_constant<int, 6>());
+  fwd_pair(integral_constant<int, 0>(), integral_constant<int, 1>());
+  fwd_pair(integral_constant<int, 2>(), integral_constant<int, 3>());
+  fwd_pair(integral_constant<int, 4>(), integral_constant<int, 5>());
 }
 
 // ---------------------------------------------------------------------------
