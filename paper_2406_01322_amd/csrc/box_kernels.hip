@@ -583,12 +583,14 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
 #pragma unroll
       for (int r = 0; r < RF; ++r)
         nx[b * RF + r] = valid ? ld_global(rhs + (long long)slot_pos<P, RF>(t, b, r) * Q + q) : cpx<T>{T(0), T(0)};
-#pragma unroll 1
-    for (int f = 0; f < 8; ++f) {
+    // one forward transform per product; the product index is a compile-time
+    // constant in each call, so its accumulation is straight-line code
+    auto fwd_field = [&](auto fc) {
+      constexpr int f = decltype(fc)::value;
       cpx<T> v[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = nx[e];
-      if (f < 7) {  // prefetch the next field while this one is transformed
+      if constexpr (f < 7) {  // prefetch the next field while this one is transformed
         const cpx<T>* src = rhs + (long long)(f + 1) * N * Q;
 #pragma unroll
         for (int b = 0; b < E / RF; ++b)
@@ -604,28 +606,37 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
           const cpx<double> ikx = {-kx * w.im, kx * w.re};
           const cpx<double> iky = {-ky * w.im, ky * w.re};
           const cpx<double> ikz = {-kz[e] * w.im, kz[e] * w.re};
-          if (f == 0) acc[0][e] = cadd(acc[0][e], ikx);                 // d_x T_xx
-          else if (f == 1) acc[1][e] = cadd(acc[1][e], iky);            // d_y T_yy
-          else if (f == 2) acc[2][e] = cadd(acc[2][e], ikz);            // d_z T_zz
-          else if (f == 3) {                                             // T_xy
+          if constexpr (f == 0) acc[0][e] = cadd(acc[0][e], ikx);                 // d_x T_xx
+          else if constexpr (f == 1) acc[1][e] = cadd(acc[1][e], iky);            // d_y T_yy
+          else if constexpr (f == 2) acc[2][e] = cadd(acc[2][e], ikz);            // d_z T_zz
+          else if constexpr (f == 3) {                                             // T_xy
             acc[0][e] = cadd(acc[0][e], iky);
             acc[1][e] = cadd(acc[1][e], ikx);
-          } else if (f == 4) {                                           // T_xz
+          } else if constexpr (f == 4) {                                           // T_xz
             acc[0][e] = cadd(acc[0][e], ikz);
             acc[2][e] = cadd(acc[2][e], ikx);
-          } else if (f == 5) {                                           // T_yz
+          } else if constexpr (f == 5) {                                           // T_yz
             acc[1][e] = cadd(acc[1][e], ikz);
             acc[2][e] = cadd(acc[2][e], iky);
-          } else if (f == 6) {                                           // -u.grad(phi)
+          } else if constexpr (f == 6) {                                           // -u.grad(phi)
             acc[3][e] = csub(acc[3][e], w);
-          } else {                                                       // lap(phi^3) / Pe
+          } else {                                                                 // lap(phi^3) / Pe
             const double k2 = kx * kx + ky * ky + kz[e] * kz[e];
             acc[3][e].re -= k2 * sc.inv_pe * w.re;
             acc[3][e].im -= k2 * sc.inv_pe * w.im;
           }
         }
       }
-    }
+    };
+    using std::integral_constant;
+    fwd_field(integral_constant<int, 0>());
+    fwd_field(integral_constant<int, 1>());
+    fwd_field(integral_constant<int, 2>());
+    fwd_field(integral_constant<int, 3>());
+    fwd_field(integral_constant<int, 4>());
+    fwd_field(integral_constant<int, 5>());
+    fwd_field(integral_constant<int, 6>());
+    fwd_field(integral_constant<int, 7>());
     // spectral update of the owned modes (FP64)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -687,17 +698,14 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
   }
 
   // z-inverse of u, v, w, phi and i kz phi
-#pragma unroll 1
-  for (int gf = 0; gf < 5; ++gf) {
+  auto inv_field = [&](auto gc) {
+    constexpr int gf = decltype(gc)::value;
     cpx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       cpx<double> x = {0.0, 0.0};
       if (inb[e]) {
-        if (gf == 0) x = acc[0][e];
-        else if (gf == 1) x = acc[1][e];
-        else if (gf == 2) x = acc[2][e];
-        else if (gf == 3) x = acc[3][e];
+        if constexpr (gf < 4) x = acc[gf][e];
         else x = cpx<double>{-kz[e] * acc[3][e].im, kz[e] * acc[3][e].re};
       }
       v[e] = to_cpx<T>(x);
@@ -710,7 +718,12 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
 #pragma unroll
         for (int r = 0; r < RF; ++r) st_global(dst + (long long)slot_pos<P, RF>(t, b, r) * Q + q, v[b * RF + r]);
     }
-  }
+  };
+  inv_field(std::integral_constant<int, 0>());
+  inv_field(std::integral_constant<int, 1>());
+  inv_field(std::integral_constant<int, 2>());
+  inv_field(std::integral_constant<int, 3>());
+  inv_field(std::integral_constant<int, 4>());
 }
 
 // ---------------------------------------------------------------------------
