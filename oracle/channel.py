@@ -79,21 +79,30 @@ def d2_matrix(nc: int) -> np.ndarray:
     return D2
 
 
-def bc_rows(nc: int, kind: str):
-    """Rows evaluating f(+1), f(-1) (Dirichlet) or f'(+1), f'(-1) (Neumann)."""
+def _wall_row(nc: int, kind: str, wall: int) -> np.ndarray:
+    """Row evaluating f (Dirichlet) or f' (Neumann) at z = wall (+1 or -1):
+    T_n(+-1) = (+-1)^n, T_n'(+-1) = (+-1)^(n+1) n^2."""
     n = np.arange(nc + 1, dtype=float)
     if kind == "dirichlet":
-        return np.ones(nc + 1), (-1.0) ** n
+        return np.ones(nc + 1) if wall > 0 else (-1.0) ** n
     if kind == "neumann":
-        return n * n, (-1.0) ** (n + 1) * n * n
+        return n * n if wall > 0 else (-1.0) ** (n + 1) * n * n
     raise ValueError(kind)
 
 
-def helmholtz(g: np.ndarray, beta: float, kind: str = "dirichlet", top=0.0, bottom=0.0) -> np.ndarray:
+def bc_rows(nc: int, kind):
+    """Rows of the top (z = +1) and bottom (z = -1) conditions.  kind is one
+    condition for both walls ("dirichlet" or "neumann") or a pair (top, bottom)."""
+    kt, kb = (kind, kind) if isinstance(kind, str) else kind
+    return _wall_row(nc, kt, +1), _wall_row(nc, kb, -1)
+
+
+def helmholtz(g: np.ndarray, beta: float, kind="dirichlet", top=0.0, bottom=0.0) -> np.ndarray:
     """Chebyshev-tau solution of (D^2 - beta) f = g on [-1, 1] with
     f(+1) = top, f(-1) = bottom (Dirichlet) or f'(+1) = top, f'(-1) = bottom
-    (Neumann).  g holds nc+1 Chebyshev coefficients (entries n > nc-2 are
-    dropped, as the tau method does).  Dense LU."""
+    (Neumann); kind may also be a pair (top kind, bottom kind).  g holds nc+1
+    Chebyshev coefficients (entries n > nc-2 are dropped, as the tau method
+    does).  Dense LU."""
     g = np.asarray(g)
     nc = g.shape[0] - 1
     A = d2_matrix(nc) - beta * np.eye(nc + 1)
@@ -113,15 +122,27 @@ def wall_values(a: np.ndarray):
     return (np.sum(a), np.sum((-1.0) ** n * a), np.sum(n * n * a), np.sum((-1.0) ** (n + 1) * n * n * a))
 
 
-def wall_normal_solve(g_om, g_w, g_phi, kx, ky, beta_ns, beta_a, beta_b):
+def wall_kinds(walls) -> tuple:
+    """Condition of omega_z and of the mean velocities at each wall (top, bottom):
+    zero value at a no-slip wall, zero normal derivative at a free-slip wall."""
+    return tuple("dirichlet" if w == "noslip" else "neumann" for w in walls)
+
+
+def wall_normal_solve(g_om, g_w, g_phi, kx, ky, beta_ns, beta_a, beta_b, walls=("noslip", "noslip")):
     """The implicit wall-normal solves of one (kx, ky) pair (Sec. 2.2, items iv and v).
 
-    omega_z: (D^2 - beta_ns) omega = g_om,  omega(+-1) = 0.
-    w:       (D^2 - beta_ns) psi = g_w, (D^2 - k^2) w = psi, w(+-1) = w'(+-1) = 0
-             (k^2 = kx^2 + ky^2); psi has no boundary values of its own, so
-             psi = psi_p + c+ psi_+ + c- psi_- with homogeneous solutions taking
-             unit values at one wall, and c+- chosen so that w'(+-1) = 0
-             (influence matrix).  For k = 0, w = 0 (continuity).
+    walls = (top, bottom), each "noslip" (u = v = w = 0) or "freeslip"
+    (w = 0, du/dz = dv/dz = 0; Sec. 2.1 allows either, or one of each).
+    omega_z: (D^2 - beta_ns) omega = g_om,  omega = 0 at a no-slip wall,
+             omega' = 0 at a free-slip wall (the z-derivative of
+             dv/dx - du/dy).
+    w:       (D^2 - beta_ns) psi = g_w, (D^2 - k^2) w = psi, w(+-1) = 0
+             (k^2 = kx^2 + ky^2), and w' = 0 at a no-slip wall, w'' = 0 at a
+             free-slip wall (continuity with du/dz = dv/dz = 0), i.e. psi = 0
+             there.  psi = psi_p + sum c_j psi_j: psi_p vanishes at both
+             walls, each homogeneous psi_j takes the unit value at one no-slip
+             wall and 0 at the other wall, and the c_j make w' = 0 at the
+             no-slip walls (influence matrix).  For k = 0, w = 0 (continuity).
     phi:     (D^2 - beta_a) xi = g_phi, (D^2 - beta_b) phi = xi, both with zero
              normal derivative at the walls (no-flux: phi' = phi''' = 0).
     u, v:    from continuity and eq. omegadef:
@@ -131,23 +152,26 @@ def wall_normal_solve(g_om, g_w, g_phi, kx, ky, beta_ns, beta_a, beta_b):
     """
     nc = len(g_om) - 1
     k2 = float(kx * kx + ky * ky)
-    om = helmholtz(g_om, beta_ns, "dirichlet")
+    om = helmholtz(g_om, beta_ns, wall_kinds(walls))
     if k2 == 0.0:
         w = np.zeros(nc + 1, complex)
     else:
         zero = np.zeros(nc + 1)
         psi_p = helmholtz(g_w, beta_ns, "dirichlet")
         w_p = helmholtz(psi_p, k2, "dirichlet")
-        psi_t = helmholtz(zero, beta_ns, "dirichlet", 1.0, 0.0)
-        w_t = helmholtz(psi_t, k2, "dirichlet")
-        psi_b = helmholtz(zero, beta_ns, "dirichlet", 0.0, 1.0)
-        w_b = helmholtz(psi_b, k2, "dirichlet")
-        _, _, dpt, dpb = wall_values(w_p)
-        _, _, dtt, dtb = wall_values(w_t)
-        _, _, dbt, dbb = wall_values(w_b)
-        M = np.array([[dtt, dbt], [dtb, dbb]])
-        c = np.linalg.solve(M, -np.array([dpt, dpb]))
-        w = w_p + c[0] * w_t + c[1] * w_b
+        # one homogeneous solution per no-slip wall; the condition w' = 0 there
+        clamped = [j for j in range(2) if walls[j] == "noslip"]
+        if clamped:
+            w_h = []
+            for j in clamped:
+                psi_j = helmholtz(zero, beta_ns, "dirichlet", 1.0 if j == 0 else 0.0, 1.0 if j == 1 else 0.0)
+                w_h.append(helmholtz(psi_j, k2, "dirichlet"))
+            dwall = lambda a: (wall_values(a)[2], wall_values(a)[3])   # w'(+1), w'(-1)
+            M = np.array([[dwall(wh)[i] for wh in w_h] for i in clamped])
+            c = np.linalg.solve(M, -np.array([dwall(w_p)[i] for i in clamped]))
+            w = w_p + sum(cj * wh for cj, wh in zip(c, w_h))
+        else:
+            w = w_p
     xi = helmholtz(g_phi, beta_a, "neumann")
     phi = helmholtz(xi, beta_b, "neumann")
     if k2 == 0.0:

@@ -32,6 +32,8 @@ equation (eq. phisplit).  One step (Sec. 2.2):
    beta = 2 Re / dt, and the mean flow
      (D^2 - beta) U = -(D^2 + beta) U^n - 2 Re (AB(S_x(0)) + F), U(+-1) = 0
    (V likewise without the driving F = -dP/dx, here 1 in wall units).
+   Each wall is no-slip (the conditions above) or free-slip (Sec. 2.1: w = 0
+   and du/dz = dv/dz = 0, hence omega_z' = 0, w'' = 0 and U' = V' = 0 there).
 
 Readings fixed here (the paper is silent): the momentum nonlinearity is taken
 in divergence form (in the channel the Chebyshev products are aliased, so the
@@ -66,6 +68,7 @@ class ChannelParams:
     lx: float = 4.0 * math.pi
     ly: float = 2.0 * math.pi
     forcing: float = 1.0  # mean pressure gradient -dP/dx
+    walls: tuple = ("noslip", "noslip")   # (top z = +1, bottom z = -1): "noslip" or "freeslip"
 
     @property
     def split_s(self) -> float:
@@ -256,7 +259,7 @@ def step(st: dict, p: ChannelParams, lines=None) -> dict:
     for iy, ix in lines:
         kk = kx[ix] ** 2 + ky[iy] ** 2
         r = ch.wall_normal_solve(g_om[:, iy, ix], g_w[:, iy, ix], g_phi[:, iy, ix], kx[ix], ky[iy],
-                                 kk + beta, kk + a, kk + b)
+                                 kk + beta, kk + a, kk + b, p.walls)
         om[:, iy, ix] = r["omega"]
         w[:, iy, ix] = r["w"]
         ph[:, iy, ix] = r["phi"]
@@ -266,7 +269,7 @@ def step(st: dict, p: ChannelParams, lines=None) -> dict:
     drive[0] = p.forcing          # the constant -dP/dx is the coefficient of T_0
     for c in range(2):
         g = -(d2[c] + beta * st["mean"][c]) - 2.0 * p.re * (e_mean[c] + (drive if c == 0 else 0.0))
-        mean[c] = ch.helmholtz(g, beta, "dirichlet")
+        mean[c] = ch.helmholtz(g, beta, ch.wall_kinds(p.walls))
     return dict(om=om, w=w, phi=ph, mean=mean, h_om=h_om, h_w=h_w, h_phi=sphi, h_mean=h_mean,
                 nstep=st["nstep"] + 1)
 

@@ -64,6 +64,27 @@ def test_helmholtz_manufactured_polynomial_is_exact(kind, beta):
     assert np.max(np.abs(f - u)) < 1e-12 * max(1.0, np.max(np.abs(u)))
 
 
+@pytest.mark.parametrize("kinds", [("dirichlet", "neumann"), ("neumann", "dirichlet")])
+@pytest.mark.parametrize("beta", [0.5, 40.0, 3e6])
+def test_helmholtz_mixed_conditions_manufactured_polynomial_is_exact(kinds, beta):
+    """A different condition at each wall (a no-slip and a free-slip wall): the tau
+    solution of a manufactured polynomial is exact; the wall values come from numpy's
+    Chebyshev evaluation, not from the oracle's boundary rows."""
+    nc = 32
+    rng = np.random.default_rng(5)
+    u = np.zeros(nc + 1, complex)
+    u[: nc - 1] = rng.standard_normal(nc - 1) + 1j * rng.standard_normal(nc - 1)
+    u[: nc - 1] /= (1.0 + np.arange(nc - 1)) ** 2
+    d2 = npcheb.chebder(u, 2)
+    g = -beta * u
+    g[: d2.shape[0]] += d2
+    du = npcheb.chebder(u)
+    val = {("dirichlet", 1): npcheb.chebval(1.0, u), ("dirichlet", -1): npcheb.chebval(-1.0, u),
+           ("neumann", 1): npcheb.chebval(1.0, du), ("neumann", -1): npcheb.chebval(-1.0, du)}
+    f = ch.helmholtz(g, beta, kinds, val[(kinds[0], 1)], val[(kinds[1], -1)])
+    assert np.max(np.abs(f - u)) < 1e-12 * max(1.0, np.max(np.abs(u)))
+
+
 @pytest.mark.parametrize("beta", [1.0, 25.0])
 def test_helmholtz_exponential_solutions(beta):
     """g = 0: Dirichlet f(+1)=1, f(-1)=0 -> sinh(k(1+z))/sinh(2k); Neumann f'(+1)=1,
@@ -123,6 +144,57 @@ def test_wall_normal_solve_invariants_and_dense_fourth_order():
     xi = D2 @ phi - beta_b * phi
     res = D2 @ xi - beta_a * xi - g_phi
     assert np.max(np.abs(res[: nc - 3])) < 1e-9 * np.max(np.abs(g_phi))
+
+
+def _wall_derivative_rows(nc, order):
+    """Rows evaluating the order-th z-derivative at z = +1 and z = -1, from numpy's
+    Chebyshev derivative of each basis polynomial."""
+    rows = np.zeros((2, nc + 1))
+    for n in range(nc + 1):
+        e = np.zeros(nc + 1)
+        e[n] = 1.0
+        d = npcheb.chebder(e, order) if order else e
+        rows[0, n] = npcheb.chebval(1.0, d)
+        rows[1, n] = npcheb.chebval(-1.0, d)
+    return rows
+
+
+@pytest.mark.parametrize("walls", [("freeslip", "noslip"), ("noslip", "freeslip"), ("freeslip", "freeslip")])
+def test_wall_normal_solve_free_slip_walls(walls):
+    """Free-slip walls (Sec. 2.1): omega' = 0 and w = w'' = 0 there; w' = 0 and
+    omega = 0 at a no-slip wall; w agrees with one dense fourth-order tau system
+    whose four boundary rows are written from numpy's Chebyshev derivatives."""
+    nc = 48
+    rng = np.random.default_rng(17)
+    cplx = lambda: (rng.standard_normal(nc + 1) + 1j * rng.standard_normal(nc + 1)) * np.exp(-0.6 * np.arange(nc + 1))
+    g_om, g_w, g_phi = cplx(), cplx(), cplx()
+    kx, ky = 1.0, 2.0
+    k2 = kx * kx + ky * ky
+    beta_ns = k2 + 100.0
+    r = ch.wall_normal_solve(g_om, g_w, g_phi, kx, ky, beta_ns, k2 + 30.0, k2 + 50.0, walls)
+    om, w = r["omega"], r["w"]
+    R0, R1, R2 = (_wall_derivative_rows(nc, k) for k in (0, 1, 2))
+    scale_o, scale_w = np.max(np.abs(om)), np.max(np.abs(w))
+    for j, wall in enumerate(walls):
+        if wall == "noslip":
+            assert abs(R0[j] @ om) < 1e-12 * scale_o
+            assert abs(R1[j] @ w) < 1e-10 * scale_w
+        else:
+            assert abs(R1[j] @ om) < 1e-10 * scale_o
+            assert abs(R2[j] @ w) < 1e-9 * scale_w
+        assert abs(R0[j] @ w) < 1e-12 * scale_w
+    D2 = ch.d2_matrix(nc)
+    I = np.eye(nc + 1)
+    A = (D2 - k2 * I) @ (D2 - beta_ns * I)
+    rows = [R0[0], R0[1]] + [(R1 if wall == "noslip" else R2)[j] for j, wall in enumerate(walls)]
+    A[nc - 3:] = np.array(rows)
+    rhs = np.array(g_w, dtype=complex)
+    rhs[nc - 3:] = 0.0
+    wd = np.linalg.solve(A, rhs)
+    assert np.max(np.abs(w - wd)) < 1e-11 * np.max(np.abs(wd))
+    # u, v still satisfy continuity and the definition of omega_z
+    dw = ch.deriv(w)
+    assert np.max(np.abs(1j * kx * r["u"] + 1j * ky * r["v"] + dw)) < 1e-12 * np.max(np.abs(dw))
 
 
 def test_mean_mode_has_no_wall_normal_velocity():

@@ -57,6 +57,23 @@ def test_laminar_poiseuille_is_a_fixed_point():
     assert np.max(np.abs(st["phi"] - st0["phi"])) < 1e-13
 
 
+def test_open_channel_profile_is_a_fixed_point():
+    """A free-slip top wall over a no-slip bottom wall (Sec. 2.1): the laminar profile
+    U = Re (1 + z)(3 - z) / 2 solves U'' = -Re with U(-1) = 0 and U'(+1) = 0, and is a
+    fixed point of the step."""
+    p = _params(walls=("freeslip", "noslip"))
+    z, Z, Y, X = _grid(p)
+    u = p.re * (1 + Z) * (3 - Z) / 2
+    zero = np.zeros_like(u)
+    st0 = cs.init_state(u, zero, zero, -np.ones_like(u), p)
+    st = cs.run(st0, p, 3)
+    assert np.max(np.abs(st["mean"][0] - st0["mean"][0])) < 1e-12 * np.max(np.abs(st0["mean"][0]))
+    # and the no-slip profile is not: it is accelerated at the free-slip wall
+    st1 = cs.step(cs.init_state(p.re * (1 - Z ** 2) / 2, zero, zero, -np.ones_like(u), p), p)
+    top = np.sum(st1["mean"][0])
+    assert top.real > 1e-3 * p.re * p.dt
+
+
 def test_mean_flow_crank_nicolson_decay():
     p = _params(nc=24)
     z, Z, Y, X = _grid(p)
