@@ -274,6 +274,10 @@ typedef struct psms_channel_params {
                            timed in Sec. 3.4): phi is identically zero, the Korteweg stress and
                            the CH solves are left out, we, ch, pe, s are not used and
                            init_state accepts d_phi = NULL */
+  int32_t free_slip;    /* bit 0: the top wall (z = +1), bit 1: the bottom wall
+                           (z = -1) is free-slip (Sec. 2.1: w = 0, du/dz = dv/dz = 0,
+                           hence omega_z' = 0, w'' = 0 and U' = V' = 0 there)
+                           instead of no-slip; 0 is the no-slip channel */
 } psms_channel_params;
 typedef struct psms_channel psms_channel;
 

@@ -1343,6 +1343,7 @@ int chan_validate(const psms_channel_params* p) {
   if (!psms::supported_nc(p->nc)) return fail(PSMS_E_NOTSUP, "nc must be one of 4 6 8 12 16 24 32 48 64 96 128 256");
   if (!(p->lx > 0) || !(p->ly > 0) || !(p->re > 0) || !(p->dt > 0) || !std::isfinite(p->forcing))
     return fail(PSMS_E_INVAL, "lx, ly, re, dt must be > 0, forcing finite");
+  if (p->free_slip < 0 || p->free_slip > 3) return fail(PSMS_E_INVAL, "free_slip must be 0..3 (bit 0 top, bit 1 bottom)");
   if (p->single_phase) return PSMS_OK;   // we, ch, pe, s are not used
   if (!(p->we > 0) || !(p->ch > 0) || !(p->pe > 0) || !(p->s >= 0))
     return fail(PSMS_E_INVAL, "we, ch, pe must be > 0, s >= 0");
@@ -1531,18 +1532,19 @@ hipError_t chan_step_once(psms_channel* c) {
   const long long xws = (long long)(nc + 1) * nl;
   psms::HelmBatch b1{};
   b1.np = g.sp ? 3 : 4;
-  b1.p[0] = psms::HelmProblem{C64(L.G), om, xw, nl, c->coef.beta, kx, ky, 0, z0, z0};                      // omega_z
+  const int fs = c->p.free_slip & 3;   // omega_z and U, V: Neumann at a free-slip wall
+  b1.p[0] = psms::HelmProblem{C64(L.G), om, xw, nl, c->coef.beta, kx, ky, fs, z0, z0};                     // omega_z
   b1.p[1] = psms::HelmProblem{C64(L.G) + g.NZL, C64(L.psip), xw + xws, nl, c->coef.beta, kx, ky, 0, z0, z0};  // psi_p
-  b1.p[2] = psms::HelmProblem{C64(L.gmean), C64(L.mean), xw + 2 * xws, 2, c->coef.beta, nullptr, nullptr, 0, z0,
+  b1.p[2] = psms::HelmProblem{C64(L.gmean), C64(L.mean), xw + 2 * xws, 2, c->coef.beta, nullptr, nullptr, fs, z0,
                               z0};                                                                        // U, V
-  b1.p[3] = psms::HelmProblem{C64(L.G) + 2 * g.NZL, C64(L.xi), xw + 3 * xws, nl, c->a_fac, kx, ky, 1, z0, z0};  // xi
+  b1.p[3] = psms::HelmProblem{C64(L.G) + 2 * g.NZL, C64(L.xi), xw + 3 * xws, nl, c->a_fac, kx, ky, 3, z0, z0};  // xi
   PSMS_TRY(psms::launch_helm_batch(b1, nc, st));
   psms::HelmBatch b2{};
   b2.np = g.sp ? 1 : 2;
   b2.p[0] = psms::HelmProblem{C64(L.psip), w, xw, nl, 0.0, kx, ky, 0, z0, z0};             // w_p
-  b2.p[1] = psms::HelmProblem{C64(L.xi), phi, xw + xws, nl, c->b_fac, kx, ky, 1, z0, z0};  // phi
+  b2.p[1] = psms::HelmProblem{C64(L.xi), phi, xw + xws, nl, c->b_fac, kx, ky, 3, z0, z0};  // phi
   PSMS_TRY(psms::launch_helm_batch(b2, nc, st));
-  PSMS_TRY(psms::launch_influence_apply(w, C64(L.wt), C64(L.wb), c->at<double>(L.M), nc, nl, kx, ky, st));
+  PSMS_TRY(psms::launch_influence_apply(w, C64(L.wt), C64(L.wb), c->at<double>(L.M), nc, nl, kx, ky, fs, st));
 #undef PSMS_TRY
   return hipSuccess;
 }
@@ -1653,7 +1655,7 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
     }
     if (e == hipSuccess)
       e = psms::launch_influence_pre(c->at<cpx<double>>(lay.wt), c->at<cpx<double>>(lay.wb), p->nc, g.NL,
-                                     c->at<double>(lay.M), st);
+                                     c->at<double>(lay.M), p->free_slip & 3, st);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {

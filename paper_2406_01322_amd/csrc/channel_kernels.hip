@@ -184,39 +184,28 @@ __global__ void k_cheb_batch(ChebBatch b, int nc, long long nlines, const double
 //   A_n = c_{n-2} beta / (4 n (n-1)),  B_n = -(1 + e_n beta / (2 (n^2 - 1))),
 //   C_n = e_{n+2} beta / (4 n (n+1)),
 //   R_n = -c_{n-2} g_{n-2} / (4 n (n-1)) + e_n g_n / (2 (n^2 - 1)) - e_{n+2} g_{n+2} / (4 n (n+1)),
-// e_m = 1 if m <= nc-2 else 0; the boundary rows split into one row per parity.
+// e_m = 1 if m <= nc-2 else 0: a tridiagonal chain per parity.  The boundary
+// rows evaluate f (Dirichlet) or f' (Neumann) at each wall: bit 0 of bc makes
+// the top wall (z = +1) Neumann, bit 1 the bottom wall.  With the same
+// condition at both walls the rows split into one row per parity; with
+// different conditions (a no-slip and a free-slip wall) they couple the two
+// parities, and the thread of parity 0 solves both chains and the 2 x 2
+// system for their first coefficients.
 // beta = beta_line[l] (if given) + beta_add + (kx_l^2 + ky_l^2 if kx given).
 // Boundary values: bcv[2l], bcv[2l+1] (top z=+1, bottom z=-1; if given)
 // plus the constants top_c, bot_c.  g may be NULL (zero).  xw: nc+1 doubles
 // per line of scratch.
-__device__ __forceinline__ void helm_line(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f,
-                                          double* __restrict__ xw, int nc, long long nlines,
-                                          const double* __restrict__ beta_line, double beta_add,
-                                          const double* __restrict__ kx, const double* __restrict__ ky, int neumann,
-                                          const cpx<double>* __restrict__ bcv, cpx<double> top_c, cpx<double> bot_c,
-                                          long long id) {
-  const long long l = id % nlines;
-  const int p = int(id / nlines);             // parity
-  double be = beta_add;
-  if (beta_line) be += beta_line[l];
-  if (kx) be += kx[l] * kx[l] + ky[l] * ky[l];
-  cpx<double> top = top_c, bot = bot_c;
-  if (bcv) {
-    top = cadd(top, bcv[2 * l]);
-    bot = cadd(bot, bcv[2 * l + 1]);
-  }
-  // boundary row of this parity: sum_i w_i a_i = s
-  cpx<double> s;
-  if (!neumann) s = (p == 0) ? cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)}
-                             : cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)};
-  else s = (p == 0) ? cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)}
-                    : cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)};
-  const int m = (nc - p) / 2;                 // indices n_i = p + 2 i, i = 0..m
+
+// downward sweep of parity p: a_i = X_i a_{i-1} + Y_i for the indices
+// n = p + 2 i, i = m..1 (X in xw, Y in f)
+__device__ __forceinline__ void helm_down(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f,
+                                          double* __restrict__ xw, int nc, long long nlines, double be, int p,
+                                          long long l) {
+  const int m = (nc - p) / 2;
   auto G = [&](int n) -> cpx<double> {
     if (!g || n > nc - 2 || n < 0) return cpx<double>{0.0, 0.0};
     return g[(long long)n * nlines + l];
   };
-  // downward sweep: a_i = X_i a_{i-1} + Y_i
   double Xn = 0.0;
   cpx<double> Yn = {0.0, 0.0};
   cpx<double> gm = G(p + 2 * m - 2), g0 = G(p + 2 * m), g2 = G(p + 2 * m + 2);
@@ -246,9 +235,25 @@ __device__ __forceinline__ void helm_line(const cpx<double>* __restrict__ g, cpx
     g0 = gm;
     gm = G(n - 4);
   }
-  // upward sweep 1: a_i = P_i a_0 + Q_i, accumulate the boundary row
-  double P = 1.0, SP = 0.0;
-  cpx<double> Qv = {0.0, 0.0}, SQ = {0.0, 0.0};
+}
+
+// wall weights of coefficient n: f(+1), f'(+1), f(-1), f'(-1)
+__device__ __forceinline__ double helm_top_w(int n, bool neu) { return neu ? double(n) * double(n) : 1.0; }
+__device__ __forceinline__ double helm_bot_w(int n, bool neu) {
+  const double s = (n & 1) ? -1.0 : 1.0;   // (-1)^n
+  return neu ? -s * double(n) * double(n) : s;
+}
+
+// upward sweep 1 of parity p: a_i = P_i a_p + Q_i; sums of the top and bottom
+// rows over the chain
+__device__ __forceinline__ void helm_up1(const cpx<double>* __restrict__ f, const double* __restrict__ xw, int nc,
+                                         long long nlines, int p, long long l, bool ntop, bool nbot, double& SPt,
+                                         cpx<double>& SQt, double& SPb, cpx<double>& SQb) {
+  const int m = (nc - p) / 2;
+  double P = 1.0;
+  cpx<double> Qv = {0.0, 0.0};
+  SPt = SPb = 0.0;
+  SQt = SQb = cpx<double>{0.0, 0.0};
 #pragma unroll 4
   for (int i = 0; i <= m; ++i) {
     const int n = p + 2 * i;
@@ -258,13 +263,20 @@ __device__ __forceinline__ void helm_line(const cpx<double>* __restrict__ g, cpx
       P = X * P;
       Qv = cpx<double>{X * Qv.re + Y.re, X * Qv.im + Y.im};
     }
-    const double w = neumann ? double(n) * double(n) : 1.0;
-    SP += w * P;
-    SQ.re += w * Qv.re;
-    SQ.im += w * Qv.im;
+    const double wt = helm_top_w(n, ntop), wb = helm_bot_w(n, nbot);
+    SPt += wt * P;
+    SQt.re += wt * Qv.re;
+    SQt.im += wt * Qv.im;
+    SPb += wb * P;
+    SQb.re += wb * Qv.re;
+    SQb.im += wb * Qv.im;
   }
-  // a_0, then upward sweep 2
-  cpx<double> a = {(s.re - SQ.re) / SP, (s.im - SQ.im) / SP};
+}
+
+// upward sweep 2 of parity p from its first coefficient a
+__device__ __forceinline__ void helm_up2(cpx<double>* __restrict__ f, const double* __restrict__ xw, int nc,
+                                         long long nlines, int p, long long l, cpx<double> a) {
+  const int m = (nc - p) / 2;
   f[(long long)p * nlines + l] = a;
 #pragma unroll 4
   for (int i = 1; i <= m; ++i) {
@@ -276,13 +288,61 @@ __device__ __forceinline__ void helm_line(const cpx<double>* __restrict__ g, cpx
   }
 }
 
+__device__ __forceinline__ void helm_line(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f,
+                                          double* __restrict__ xw, int nc, long long nlines,
+                                          const double* __restrict__ beta_line, double beta_add,
+                                          const double* __restrict__ kx, const double* __restrict__ ky, int bc,
+                                          const cpx<double>* __restrict__ bcv, cpx<double> top_c, cpx<double> bot_c,
+                                          long long id) {
+  const long long l = id % nlines;
+  const int p = int(id / nlines);             // parity
+  const bool ntop = bc & 1, nbot = (bc >> 1) & 1;
+  if (ntop != nbot && p == 1) return;         // both chains on the thread of parity 0
+  double be = beta_add;
+  if (beta_line) be += beta_line[l];
+  if (kx) be += kx[l] * kx[l] + ky[l] * ky[l];
+  cpx<double> top = top_c, bot = bot_c;
+  if (bcv) {
+    top = cadd(top, bcv[2 * l]);
+    bot = cadd(bot, bcv[2 * l + 1]);
+  }
+  if (ntop == nbot) {
+    // the rows (top +- bottom)/2 restricted to this parity: sum_i w_i a_i = s
+    cpx<double> s;
+    const bool plus = (p == 0) != ntop;       // Dirichlet even, Neumann odd: (top + bottom) / 2
+    s = plus ? cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)}
+             : cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)};
+    helm_down(g, f, xw, nc, nlines, be, p, l);
+    double SPt, SPb;
+    cpx<double> SQt, SQb;
+    helm_up1(f, xw, nc, nlines, p, l, ntop, nbot, SPt, SQt, SPb, SQb);
+    helm_up2(f, xw, nc, nlines, p, l, cpx<double>{(s.re - SQt.re) / SPt, (s.im - SQt.im) / SPt});
+    return;
+  }
+  // different conditions at the two walls: both parities, then
+  //   SPt0 a_0 + SPt1 a_1 = top - SQt0 - SQt1,  SPb0 a_0 + SPb1 a_1 = bot - SQb0 - SQb1
+  double SPt[2], SPb[2];
+  cpx<double> SQt[2], SQb[2];
+  for (int q = 0; q < 2; ++q) {
+    helm_down(g, f, xw, nc, nlines, be, q, l);
+    helm_up1(f, xw, nc, nlines, q, l, ntop, nbot, SPt[q], SQt[q], SPb[q], SQb[q]);
+  }
+  const cpx<double> rt = {top.re - SQt[0].re - SQt[1].re, top.im - SQt[0].im - SQt[1].im};
+  const cpx<double> rb = {bot.re - SQb[0].re - SQb[1].re, bot.im - SQb[0].im - SQb[1].im};
+  const double det = SPt[0] * SPb[1] - SPt[1] * SPb[0];
+  const cpx<double> a0 = {(rt.re * SPb[1] - SPt[1] * rb.re) / det, (rt.im * SPb[1] - SPt[1] * rb.im) / det};
+  const cpx<double> a1 = {(SPt[0] * rb.re - SPb[0] * rt.re) / det, (SPt[0] * rb.im - SPb[0] * rt.im) / det};
+  helm_up2(f, xw, nc, nlines, 0, l, a0);
+  helm_up2(f, xw, nc, nlines, 1, l, a1);
+}
+
 __global__ void k_helm(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f, double* __restrict__ xw,
                        int nc, long long nlines, const double* __restrict__ beta_line, double beta_add,
                        const double* __restrict__ kx, const double* __restrict__ ky, int neumann,
                        const cpx<double>* __restrict__ bcv, cpx<double> top_c, cpx<double> bot_c) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= 2 * nlines) return;
-  helm_line(g, f, xw, nc, nlines, beta_line, beta_add, kx, ky, neumann, bcv, top_c, bot_c, id);
+  helm_line(g, f, xw, nc, nlines, beta_line, beta_add, kx, ky, neumann ? 3 : 0, bcv, top_c, bot_c, id);
 }
 
 // Several independent problems in one launch (blockIdx.y selects the problem):
@@ -292,7 +352,7 @@ __global__ void k_helm_batch(HelmBatch b, int nc) {
   const HelmProblem& P = b.p[blockIdx.y];
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= 2 * P.nlines) return;
-  helm_line(P.g, P.f, P.xw, nc, P.nlines, nullptr, P.beta_add, P.kx, P.ky, P.neumann, nullptr, P.top_c, P.bot_c, id);
+  helm_line(P.g, P.f, P.xw, nc, P.nlines, nullptr, P.beta_add, P.kx, P.ky, P.bc, nullptr, P.top_c, P.bot_c, id);
 }
 
 // w = w_p + c_t w_t + c_b w_b with (c_t, c_b) making w'(+1) = w'(-1) = 0;
@@ -337,7 +397,7 @@ __global__ void k_influence(cpx<double>* __restrict__ wp, const cpx<double>* __r
 // w_t, w_b are fixed (they depend only on k^2 and beta): M = (w_t'(+1),
 // w_t'(-1), w_b'(+1), w_b'(-1)) per line, M [4][nlines].
 __global__ void k_influence_pre(const cpx<double>* __restrict__ wt, const cpx<double>* __restrict__ wb, int nc,
-                                long long nlines, double* __restrict__ M) {
+                                long long nlines, double* __restrict__ M, int free_slip) {
   const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nlines) return;
   double dtt = 0, dtb = 0, dbt = 0, dbb = 0;
@@ -349,6 +409,14 @@ __global__ void k_influence_pre(const cpx<double>* __restrict__ wt, const cpx<do
     dtb += sg * wt[o].re;
     dbt += w2 * wb[o].re;
     dbb += sg * wb[o].re;
+  }
+  if (free_slip & 1) {   // top row: c_t = 0
+    dtt = 1.0;
+    dbt = 0.0;
+  }
+  if (free_slip & 2) {   // bottom row: c_b = 0
+    dtb = 0.0;
+    dbb = 1.0;
   }
   M[l] = dtt;
   M[nlines + l] = dtb;
@@ -364,7 +432,7 @@ __global__ void __launch_bounds__(256) k_influence_apply(cpx<double>* __restrict
                                                          const cpx<double>* __restrict__ wb,
                                                          const double* __restrict__ M, int nc, long long nlines,
                                                          const double* __restrict__ kx,
-                                                         const double* __restrict__ ky) {
+                                                         const double* __restrict__ ky, int free_slip) {
   __shared__ cpx<double> part[2][4][64];
   const int li = threadIdx.x % 64, ch = threadIdx.x / 64;
   const long long l = (long long)blockIdx.x * 64 + li;
@@ -390,6 +458,8 @@ __global__ void __launch_bounds__(256) k_influence_apply(cpx<double>* __restrict
     dpt = cadd(dpt, part[0][c][li]);
     dpb = cadd(dpb, part[1][c][li]);
   }
+  if (free_slip & 1) dpt = cpx<double>{0.0, 0.0};
+  if (free_slip & 2) dpb = cpx<double>{0.0, 0.0};
   const double dtt = M[l], dtb = M[nlines + l], dbt = M[2 * nlines + l], dbb = M[3 * nlines + l];
   const bool mean = (kx[l] == 0.0 && ky[l] == 0.0);
   const double det = dtt * dbb - dbt * dtb;
@@ -521,14 +591,15 @@ hipError_t launch_influence(cpx<double>* wp, const cpx<double>* wt, const cpx<do
 }
 
 hipError_t launch_influence_pre(const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines, double* M,
-                                hipStream_t st) {
-  k_influence_pre<<<blocks(nlines, 64), 64, 0, st>>>(wt, wb, nc, nlines, M);
+                                int free_slip, hipStream_t st) {
+  k_influence_pre<<<blocks(nlines, 64), 64, 0, st>>>(wt, wb, nc, nlines, M, free_slip);
   return hipGetLastError();
 }
 
 hipError_t launch_influence_apply(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, const double* M,
-                                  int nc, long long nlines, const double* kx, const double* ky, hipStream_t st) {
-  k_influence_apply<<<blocks(nlines, 64), 256, 0, st>>>(wp, wt, wb, M, nc, nlines, kx, ky);
+                                  int nc, long long nlines, const double* kx, const double* ky, int free_slip,
+                                  hipStream_t st) {
+  k_influence_apply<<<blocks(nlines, 64), 256, 0, st>>>(wp, wt, wb, M, nc, nlines, kx, ky, free_slip);
   return hipGetLastError();
 }
 

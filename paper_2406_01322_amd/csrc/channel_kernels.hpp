@@ -46,7 +46,7 @@ struct HelmProblem {
   double beta_add;
   const double* kx;
   const double* ky;
-  int neumann;
+  int bc;   // bit 0: Neumann at the top wall (z = +1), bit 1: at the bottom wall; else Dirichlet
   cpx<double> top_c, bot_c;
 };
 struct HelmBatch {
@@ -57,11 +57,14 @@ hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st);
 hipError_t launch_influence(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
                             const double* kx, const double* ky, hipStream_t st);
 // influence matrix with fixed homogeneous solutions: M [4][nlines] once, then
-// the combination per solve
+// the combination per solve.  free_slip bit 0 (top wall) / bit 1 (bottom wall):
+// that wall imposes w'' = 0 through psi = 0 instead of w' = 0, so its
+// homogeneous solution takes no part (its row of M is the identity).
 hipError_t launch_influence_pre(const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines, double* M,
-                                hipStream_t st);
+                                int free_slip, hipStream_t st);
 hipError_t launch_influence_apply(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, const double* M,
-                                  int nc, long long nlines, const double* kx, const double* ky, hipStream_t st);
+                                  int nc, long long nlines, const double* kx, const double* ky, int free_slip,
+                                  hipStream_t st);
 hipError_t launch_uv(const cpx<double>* om, const cpx<double>* dw, cpx<double>* u, cpx<double>* v, int nc,
                      long long nlines, const double* kx, const double* ky, hipStream_t st);
 

@@ -55,7 +55,7 @@ class ChannelParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nc", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("re", ctypes.c_double), ("we", ctypes.c_double),
                 ("ch", ctypes.c_double), ("pe", ctypes.c_double), ("dt", ctypes.c_double), ("s", ctypes.c_double),
-                ("forcing", ctypes.c_double), ("single_phase", ctypes.c_int32)]
+                ("forcing", ctypes.c_double), ("single_phase", ctypes.c_int32), ("free_slip", ctypes.c_int32)]
 
 
 DIRICHLET, NEUMANN = 1, 2
@@ -581,17 +581,22 @@ class Channel:
     ky in band order 0..Ky, -Ky..-1, kx = 0..Kx); mean lines [2, nc+1] (U, V);
     physical fields float64 [nc+1, ny, nx] at z_j = cos(pi j / nc).
     single_phase=True steps Navier-Stokes alone (phi stays zero; we, ch, pe, s unused).
+    walls = (top, bottom) wall conditions, each "noslip" or "freeslip".
     """
 
     def __init__(self, nx, ny, nc, re, we, ch, pe, dt, s=0.0, precision="fp64", lx=4 * 3.141592653589793,
-                 ly=2 * 3.141592653589793, forcing=1.0, single_phase=False, device="cuda", stream=None):
+                 ly=2 * 3.141592653589793, forcing=1.0, single_phase=False, walls=("noslip", "noslip"),
+                 device="cuda", stream=None):
         import torch
         self.torch = torch
         prec = {"fp64": FP64, "mixed": MIXED}[precision]
         self.single_phase = bool(single_phase)
         self.params = ChannelParams(int(nx), int(ny), int(nc), prec, float(lx), float(ly), float(re),
                                     float(we or 0.0), float(ch or 0.0), float(pe or 0.0), float(dt), float(s or 0.0),
-                                    float(forcing), int(self.single_phase))
+                                    float(forcing), int(self.single_phase),
+                                    sum(1 << j for j, wl in enumerate(walls) if wl == "freeslip"))
+        if any(wl not in ("noslip", "freeslip") for wl in walls) or len(walls) != 2:
+            raise ValueError("walls = (top, bottom), each 'noslip' or 'freeslip'")
         self.nx, self.ny, self.nc = int(nx), int(ny), int(nc)
         self.band = (self.nc + 1, 2 * ((self.ny - 1) // 3) + 1, (self.nx - 1) // 3 + 1)
         self.device = torch.device(device)

@@ -19,11 +19,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _gpu(p, precision, single_phase=None):
+def _gpu(p, precision, single_phase=None, walls=("noslip", "noslip")):
     from paper_2406_01322_amd.psms import Channel
     sp = p.get("single_phase", False) if single_phase is None else single_phase
     return Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision,
-                   lx=p["lx"], ly=p["ly"], single_phase=sp)
+                   lx=p["lx"], ly=p["ly"], single_phase=sp, walls=walls)
 
 
 def _dev(a):
@@ -234,3 +234,68 @@ def test_single_phase_256_sampled_lines(sp256, precision, tol):
         else:
             assert _rel_l2(a, b) < tol, (k, _rel_l2(a, b))
     assert _rel_max(mean, ref["mean"]) < tol
+
+
+# ---------------------------------------------------------------------------
+# free-slip walls (a different tau row at that wall: omega_z' = 0, psi = 0,
+# U' = 0), alone or with a no-slip wall (the two parities of the tau chains
+# couple)
+# ---------------------------------------------------------------------------
+
+WALLS = [("freeslip", "noslip"), ("noslip", "freeslip"), ("freeslip", "freeslip")]
+
+
+@pytest.mark.parametrize("walls", WALLS)
+@pytest.mark.parametrize("nprev", [0, 1])
+def test_free_slip_walls_one_step_parity_fp64(walls, nprev):
+    import dataclasses
+    p, prm, f = _case("chan_mid")
+    prm = dataclasses.replace(prm, walls=walls)
+    st = cs.run(cs.init_state(*f, prm), prm, nprev)
+    ref = cs.step(st, prm)
+    c = _gpu(p, "fp64", walls=walls)
+    _load(c, st)
+    c.step(1)
+    state, mean, hist, hmean = (_host(t) for t in c.get_state(with_history=True))
+    for i, k in enumerate(("om", "w", "phi")):
+        assert _rel_max(state[i], ref[k]) < 1e-9, (k, _rel_max(state[i], ref[k]))
+    assert _rel_max(mean, ref["mean"]) < 1e-9
+    assert _rel_max(hmean, ref["h_mean"]) < 1e-9
+
+
+@pytest.mark.parametrize("walls", WALLS)
+def test_free_slip_walls_one_step_parity_mixed(walls):
+    import dataclasses
+    p, prm, f = _case("chan_small")
+    prm = dataclasses.replace(prm, walls=walls)
+    st = cs.run(cs.init_state(*f, prm), prm, 1)
+    ref = cs.step(st, prm)
+    c = _gpu(p, "mixed", walls=walls)
+    _load(c, st)
+    c.step(1)
+    state, mean = (_host(t) for t in c.get_state())
+    for i, k in enumerate(("om", "w", "phi")):
+        assert _rel_l2(state[i], ref[k]) < 1e-5, (k, _rel_l2(state[i], ref[k]))
+    assert _rel_l2(mean, ref["mean"]) < 1e-5
+
+
+def test_free_slip_ten_steps_fp64():
+    import dataclasses
+    p, prm, f = _case("chan_small")
+    walls = ("freeslip", "noslip")
+    prm = dataclasses.replace(prm, walls=walls)
+    ref = cs.run(cs.init_state(*f, prm), prm, 10)
+    c = _gpu(p, "fp64", walls=walls)
+    c.init_state(*[_dev(x) for x in f])
+    c.step(10)
+    state, mean = (_host(t) for t in c.get_state())
+    for i, k in enumerate(("om", "w", "phi")):
+        assert _rel_max(state[i], ref[k]) < 1e-8, (k, _rel_max(state[i], ref[k]))
+    assert _rel_max(mean, ref["mean"]) < 1e-8
+
+
+def test_bad_wall_flags_are_rejected():
+    from paper_2406_01322_amd.psms import Channel
+    p, prm, f = _case("chan_small")
+    with pytest.raises(ValueError):
+        Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], walls=("slip", "noslip"))
