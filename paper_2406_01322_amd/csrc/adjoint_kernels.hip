@@ -97,22 +97,23 @@ __global__ void __launch_bounds__(256) k_zadj_in(cpx<double>* __restrict__ lam, 
     }
   __syncthreads();
 
-  // cotangents of F(T_xx), F(T_yy), F(T_zz), F(T_xy), F(T_xz), F(T_yz), F(a), F(c)
-#pragma unroll 1
-  for (int f = 0; f < 8; ++f) {
+  // cotangents of F(T_xx), F(T_yy), F(T_zz), F(T_xy), F(T_xz), F(T_yz), F(a), F(c);
+  // the field index is a compile-time constant in each body
+  static_for<0, 8>([&](auto fc) {
+    constexpr int f = decltype(fc)::value;
     cpx<double> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       // -i k s  ->  (k s.im, -k s.re)
       const double kze = kz[e];
       cpx<double> x;
-      if (f == 0) x = {kx * sb[0][e].im, -kx * sb[0][e].re};
-      else if (f == 1) x = {ky * sb[1][e].im, -ky * sb[1][e].re};
-      else if (f == 2) x = {kze * sb[2][e].im, -kze * sb[2][e].re};
-      else if (f == 3) x = {ky * sb[0][e].im + kx * sb[1][e].im, -ky * sb[0][e].re - kx * sb[1][e].re};
-      else if (f == 4) x = {kze * sb[0][e].im + kx * sb[2][e].im, -kze * sb[0][e].re - kx * sb[2][e].re};
-      else if (f == 5) x = {kze * sb[1][e].im + ky * sb[2][e].im, -kze * sb[1][e].re - ky * sb[2][e].re};
-      else if (f == 6) x = {-sb[3][e].re, -sb[3][e].im};
+      if constexpr (f == 0) x = {kx * sb[0][e].im, -kx * sb[0][e].re};
+      else if constexpr (f == 1) x = {ky * sb[1][e].im, -ky * sb[1][e].re};
+      else if constexpr (f == 2) x = {kze * sb[2][e].im, -kze * sb[2][e].re};
+      else if constexpr (f == 3) x = {ky * sb[0][e].im + kx * sb[1][e].im, -ky * sb[0][e].re - kx * sb[1][e].re};
+      else if constexpr (f == 4) x = {kze * sb[0][e].im + kx * sb[2][e].im, -kze * sb[0][e].re - kx * sb[2][e].re};
+      else if constexpr (f == 5) x = {kze * sb[1][e].im + ky * sb[2][e].im, -kze * sb[1][e].re - ky * sb[2][e].re};
+      else if constexpr (f == 6) x = {-sb[3][e].re, -sb[3][e].im};
       else {
         const double k2 = kx * kx + ky * ky + kze * kze;
         x = {-k2 * ac.inv_pe * sb[3][e].re, -k2 * ac.inv_pe * sb[3][e].im};
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(256) k_zadj_in(cpx<double>* __restrict__ lam, 
 #pragma unroll
         for (int r = 0; r < RO; ++r) dst[(long long)slot_pos<P, RO>(t, b, r) * Q + q] = v[b * RO + r];
     }
-  }
+  });
 }
 
 // -------------------------------------------------------------------------
@@ -228,8 +229,8 @@ __global__ void __launch_bounds__(256) k_xadj(const cpx<double>* __restrict__ yf
     for (int e = 0; e < E; ++e) acc[c][e] = cpx<double>{0.0, 0.0};
   double dwe = 0.0;
   const double c2 = 2.0 * csig;
-#pragma unroll 1
-  for (int f = 0; f < 7; ++f) {
+  static_for<0, 7>([&](auto fc) {
+    constexpr int f = decltype(fc)::value;
     cpx<double> tb[E];
     xinv(yb + f * FS, false, tb);
 #pragma unroll
@@ -241,15 +242,13 @@ __global__ void __launch_bounds__(256) k_xadj(const cpx<double>* __restrict__ yf
         const double gy = h ? fw[4][e].im : fw[4][e].re, gz = h ? fw[5][e].im : fw[5][e].re;
         const double x = h ? tb[e].im : tb[e].re;
         double du = 0, dv = 0, dw = 0, dgx = 0, dgy = 0, dgz = 0;
-        switch (f) {
-          case 0: du = -2.0 * u * x; dgy = c2 * gy * x; dgz = c2 * gz * x; dwe += x * (gy * gy + gz * gz); break;
-          case 1: dv = -2.0 * v * x; dgx = c2 * gx * x; dgz = c2 * gz * x; dwe += x * (gx * gx + gz * gz); break;
-          case 2: dw = -2.0 * w * x; dgx = c2 * gx * x; dgy = c2 * gy * x; dwe += x * (gx * gx + gy * gy); break;
-          case 3: du = -v * x; dv = -u * x; dgx = -csig * gy * x; dgy = -csig * gx * x; dwe -= x * gx * gy; break;
-          case 4: du = -w * x; dw = -u * x; dgx = -csig * gz * x; dgz = -csig * gx * x; dwe -= x * gx * gz; break;
-          case 5: dv = -w * x; dw = -v * x; dgy = -csig * gz * x; dgz = -csig * gy * x; dwe -= x * gy * gz; break;
-          default: du = gx * x; dv = gy * x; dw = gz * x; dgx = u * x; dgy = v * x; dgz = w * x; break;
-        }
+        if constexpr (f == 0) { du = -2.0 * u * x; dgy = c2 * gy * x; dgz = c2 * gz * x; dwe += x * (gy * gy + gz * gz); }
+        else if constexpr (f == 1) { dv = -2.0 * v * x; dgx = c2 * gx * x; dgz = c2 * gz * x; dwe += x * (gx * gx + gz * gz); }
+        else if constexpr (f == 2) { dw = -2.0 * w * x; dgx = c2 * gx * x; dgy = c2 * gy * x; dwe += x * (gx * gx + gy * gy); }
+        else if constexpr (f == 3) { du = -v * x; dv = -u * x; dgx = -csig * gy * x; dgy = -csig * gx * x; dwe -= x * gx * gy; }
+        else if constexpr (f == 4) { du = -w * x; dw = -u * x; dgx = -csig * gz * x; dgz = -csig * gx * x; dwe -= x * gx * gz; }
+        else if constexpr (f == 5) { dv = -w * x; dw = -v * x; dgy = -csig * gz * x; dgz = -csig * gy * x; dwe -= x * gy * gz; }
+        else { du = gx * x; dv = gy * x; dw = gz * x; dgx = u * x; dgy = v * x; dgz = w * x; }
         if (h) {
           acc[0][e].im += du; acc[1][e].im += dv; acc[2][e].im += dw;
           acc[3][e].im += dgx; acc[4][e].im += dgy; acc[5][e].im += dgz;
@@ -259,7 +258,7 @@ __global__ void __launch_bounds__(256) k_xadj(const cpx<double>* __restrict__ yf
         }
       }
     }
-  }
+  });
   if (!valid) dwe = 0.0;
   xfwd(acc[0], out + 0 * FS);
   xfwd(acc[1], out + 1 * FS);

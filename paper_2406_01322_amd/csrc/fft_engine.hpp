@@ -23,6 +23,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace psms {
 
 template <typename T>
@@ -55,6 +57,16 @@ __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
 // wait of a transform would drain them; these helpers issue global loads and
 // stores instead.  p must point to device global memory, 2 * sizeof(T)
 // aligned.
+// f(std::integral_constant<int, I>{}) for I = 0 .. COUNT-1, in order: the
+// body sees its index as a compile-time constant.
+template <int I, int COUNT, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < COUNT) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, COUNT>(f);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T> ld_global(const cpx<T>* p) {
   typedef T T2 __attribute__((ext_vector_type(2)));
