@@ -298,3 +298,27 @@ def channel_case(name: str):
         return p, u, vp, wp, np.zeros_like(u)
     phi = channel_drops(X, Y, Z, p["lx"], p["ly"], rng, nd, radius, p["ch"])
     return p, u, vp, wp, phi
+
+
+def band_limited_box(n: int, seed: int = 21):
+    """u = curl A with A made of a few Fourier modes |k_i| <= 2, phi = -0.2 plus modes
+    |k_i| <= 3, on the n^3 grid: every product the step forms (quadratic terms up to
+    |k_i| = 5, phi^3 up to 9) is represented exactly from n = 32 up, and lies in the
+    2/3 band there, so one step gives the same spectral state at every such n.  Each
+    field is Re(sum_k c_k exp(i k.x)), synthesised by one inverse FFT."""
+    rng = np.random.default_rng(seed)
+    modes = [(kz, ky, kx) for kz in range(-2, 3) for ky in range(-2, 3) for kx in range(0, 3)
+             if (kz, ky, kx) != (0, 0, 0)]
+    U = np.zeros((4, n, n, n), complex)
+    for kz, ky, kx in modes[::3]:
+        k = (kx, ky, kz)
+        ab = [0.1 * rng.standard_normal(2) for _ in range(3)]   # A_c = a_c cos(k.x) + b_c sin(k.x)
+        # u_c = d_j1 A_c1 - d_j2 A_c2 with d_j A_c = k_j (b_c cos - a_c sin)
+        for c, (j1, c1), (j2, c2) in ((0, (1, 2), (2, 1)), (1, (2, 0), (0, 2)), (2, (0, 1), (1, 0))):
+            cc = k[j1] * ab[c1][1] - k[j2] * ab[c2][1]
+            ss = -(k[j1] * ab[c1][0] - k[j2] * ab[c2][0])
+            U[c, kz % n, ky % n, kx % n] += cc - 1j * ss      # Re((cc - i ss) e^{i k.x})
+    for (kz, ky, kx), a in (((0, 0, 0), -0.2), ((0, 2, 1), 0.3), ((3, -1, 0), -0.2j), ((-3, 0, 2), 0.1)):
+        U[3, kz % n, ky % n, kx % n] += a
+    f = np.real(np.fft.ifftn(U, axes=(1, 2, 3))) * float(n) ** 3
+    return f[:3], f[3]

@@ -379,3 +379,23 @@ def test_cfl_of_single_modes_closed_form():
     st = box.init_state(u, np.zeros((n, n, n)), prm)
     d = box.diagnostics(st, n, dt)
     assert abs(d["cfl"] - dt * (A + B) * n / (2 * math.pi)) < 1e-14
+
+
+def test_band_limited_step_is_independent_of_n():
+    """A state whose products all lie within the 2/3 band (u from modes |k_i| <= 2,
+    phi from |k_i| <= 3) steps to the same spectral state at N = 32 and N = 48: the
+    transform normalisation, the dealiasing cut-off and the wavenumbers scale
+    correctly with N."""
+    p = dict(re=200.0, we=2.0, ch=0.05, pe=20.0, dt=2e-3)
+    out = []
+    for n in (32, 48):
+        prm = box.Params(n=n, **p)
+        u, phi = synth.band_limited_box(n)
+        st = box.step(box.init_state(u, phi, prm), prm)
+        idx = list(range(0, 11)) + [n - m for m in range(10, 0, -1)]
+        sub = lambda a: a[..., idx, :, :][..., :, idx, :][..., :, :, :11]
+        out.append((sub(st["uh"]), sub(st["ph"]), np.max(np.abs(st["uh"][..., 11:])), np.max(np.abs(st["ph"][..., 11:]))))
+    (u32, p32, _, _), (u48, p48, ru, rp) = out
+    assert np.max(np.abs(u48 - u32)) < 1e-15 * 100 * np.max(np.abs(u32))
+    assert np.max(np.abs(p48 - p32)) < 1e-15 * 100 * np.max(np.abs(p32))
+    assert ru < 1e-15 and rp < 1e-15
