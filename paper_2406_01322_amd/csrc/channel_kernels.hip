@@ -355,6 +355,102 @@ __global__ void k_helm_batch(HelmBatch b, int nc) {
   helm_line(P.g, P.f, P.xw, nc, P.nlines, nullptr, P.beta_add, P.kx, P.ky, P.bc, nullptr, P.top_c, P.bot_c, id);
 }
 
+// The same problems with the elimination held on chip: one workgroup of 64
+// lines per (problem, parity) (blockIdx.z = parity, uniform in the
+// workgroup), X_i of each chain in registers (the loops over i are unrolled
+// for the compile-time NC, and i > m is skipped uniformly) and Y_i in LDS, so
+// that HBM sees only the right-hand side read and the solution written (32
+// bytes per coefficient instead of 104 through the scratch chains).  Same
+// condition at both walls only (bc 0 or 3); the arithmetic is that of
+// helm_line, in the same order.
+template <int NC>
+__global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
+  constexpr int MM = NC / 2;                 // longest chain: parity 0, i = 0..MM
+  __shared__ cpx<double> Ys[MM + 1][64];
+  const HelmProblem& P = b.p[blockIdx.y];
+  const int p = blockIdx.z;
+  const int tid = threadIdx.x;
+  const long long l = (long long)blockIdx.x * 64 + tid;
+  if (l >= P.nlines) return;                 // no barrier below: each chain is one thread's
+  const long long nl = P.nlines;
+  const int m = (NC - p) / 2;
+  const bool neu = P.bc == 3;
+  double be = P.beta_add;
+  if (P.kx) be += P.kx[l] * P.kx[l] + P.ky[l] * P.ky[l];
+  const cpx<double> top = P.top_c, bot = P.bot_c;
+  const bool plus = (p == 0) != neu;
+  const cpx<double> s = plus ? cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)}
+                             : cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)};
+  const cpx<double>* __restrict__ g = P.g;
+  auto G = [&](int n) -> cpx<double> {
+    if (!g || n > NC - 2 || n < 0) return cpx<double>{0.0, 0.0};
+    return g[(long long)n * nl + l];
+  };
+  // downward sweep: a_i = X_i a_{i-1} + Y_i
+  double X[MM + 1];
+  double Xn = 0.0;
+  cpx<double> Yn = {0.0, 0.0};
+  cpx<double> gm = G(p + 2 * m - 2), g0 = G(p + 2 * m), g2 = G(p + 2 * m + 2);
+#pragma unroll
+  for (int i = MM; i >= 1; --i) {
+    if (i <= m) {
+      const int n = p + 2 * i;
+      const double dn = double(n);
+      const double cm2 = (n - 2 == 0) ? 2.0 : 1.0;
+      const double en = (n <= NC - 2) ? 1.0 : 0.0;
+      const double en2 = (n + 2 <= NC - 2) ? 1.0 : 0.0;
+      const double q1 = 1.0 / (4.0 * dn * (dn - 1.0));
+      const double q2 = 1.0 / (2.0 * (dn * dn - 1.0));
+      const double q3 = 1.0 / (4.0 * dn * (dn + 1.0));
+      const double A = cm2 * be * q1;
+      const double B = -(1.0 + en * be * q2);
+      const double C = en2 * be * q3;
+      const cpx<double> R = {-cm2 * gm.re * q1 + en * g0.re * q2 - en2 * g2.re * q3,
+                             -cm2 * gm.im * q1 + en * g0.im * q2 - en2 * g2.im * q3};
+      const double den = 1.0 / (B + C * Xn);
+      const double Xv = -A * den;
+      const cpx<double> Y = {(R.re - C * Yn.re) * den, (R.im - C * Yn.im) * den};
+      X[i] = Xv;
+      Ys[i][tid] = Y;
+      Xn = Xv;
+      Yn = Y;
+      g2 = g0;
+      g0 = gm;
+      gm = G(n - 4);
+    }
+  }
+  // upward sweep 1: a_i = P_i a_0 + Q_i and the boundary row of this parity
+  double Pc = 1.0, SP = 0.0;
+  cpx<double> Qv = {0.0, 0.0}, SQ = {0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i <= MM; ++i) {
+    if (i <= m) {
+      const int n = p + 2 * i;
+      if (i > 0) {
+        const cpx<double> Y = Ys[i][tid];
+        Pc = X[i] * Pc;
+        Qv = cpx<double>{X[i] * Qv.re + Y.re, X[i] * Qv.im + Y.im};
+      }
+      const double w = neu ? double(n) * double(n) : 1.0;
+      SP += w * Pc;
+      SQ.re += w * Qv.re;
+      SQ.im += w * Qv.im;
+    }
+  }
+  // a_0, then upward sweep 2
+  cpx<double> a = {(s.re - SQ.re) / SP, (s.im - SQ.im) / SP};
+  cpx<double>* __restrict__ f = P.f;
+  f[(long long)p * nl + l] = a;
+#pragma unroll
+  for (int i = 1; i <= MM; ++i) {
+    if (i <= m) {
+      const cpx<double> Y = Ys[i][tid];
+      a = cpx<double>{X[i] * a.re + Y.re, X[i] * a.im + Y.im};
+      f[(long long)(p + 2 * i) * nl + l] = a;
+    }
+  }
+}
+
 // w = w_p + c_t w_t + c_b w_b with (c_t, c_b) making w'(+1) = w'(-1) = 0;
 // w = 0 where kx = ky = 0.  Written over w_p.
 __global__ void k_influence(cpx<double>* __restrict__ wp, const cpx<double>* __restrict__ wt,
@@ -578,8 +674,23 @@ hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc,
 
 hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st) {
   long long most = 0;
-  for (int i = 0; i < b.np; ++i) most = most > b.p[i].nlines ? most : b.p[i].nlines;
+  bool same_walls = true;
+  for (int i = 0; i < b.np; ++i) {
+    most = most > b.p[i].nlines ? most : b.p[i].nlines;
+    same_walls = same_walls && (b.p[i].bc == 0 || b.p[i].bc == 3);
+  }
   if (b.np < 1 || b.np > kHelmBatchMax || most == 0) return hipSuccess;
+  if (same_walls) {
+    const dim3 grid(blocks(most, 64), unsigned(b.np), 2);
+    switch (nc) {
+#define PSMS_CASE(NC) \
+  case NC: k_helm_batch_reg<NC><<<grid, 64, 0, st>>>(b); return hipGetLastError();
+      PSMS_CASE(4) PSMS_CASE(6) PSMS_CASE(8) PSMS_CASE(12) PSMS_CASE(16) PSMS_CASE(24) PSMS_CASE(32)
+      PSMS_CASE(48) PSMS_CASE(64) PSMS_CASE(96) PSMS_CASE(128)
+#undef PSMS_CASE
+      default: break;   // longer chains (nc = 256) through the scratch path
+    }
+  }
   k_helm_batch<<<dim3(blocks(2 * most, 64), unsigned(b.np)), 64, 0, st>>>(b, nc);
   return hipGetLastError();
 }

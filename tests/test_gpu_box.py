@@ -5,6 +5,8 @@ MIXED path (FP32 transforms and products, FP64 state, RHS assembly and
 projection) rel-L2 <= 1e-5 per field per step.  Index maps are compared
 bit-exactly.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -238,6 +240,54 @@ def test_step_is_deterministic():
         s.step(3)
         outs.append([_host(t) for t in s.get_state()])
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@functools.lru_cache(maxsize=2)
+def _low_mode_fields(n):
+    return synth.band_limited_box(n, seed=21)
+
+
+def _low_modes(a, k_to):
+    """Entries |k_i| <= k_to (kx = 0..k_to) of a half-spectrum array [..., N, N, N/2+1],
+    in the order ky, kz = 0..k_to, -k_to..-1, and the largest entry elsewhere."""
+    n = a.shape[-2]
+    idx = list(range(0, k_to + 1)) + [n - m for m in range(k_to, 0, -1)]
+    sub = a[..., idx, :, :][..., :, idx, :][..., :, :, : k_to + 1]
+    rest = a.copy()
+    rest[..., : k_to + 1] = np.where(np.isin(np.arange(n), idx)[:, None, None] & np.isin(np.arange(n), idx)[None, :, None],
+                                     0.0, rest[..., : k_to + 1])
+    return sub, np.max(np.abs(rest))
+
+
+@pytest.mark.parametrize("n", [192, 256])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_large_n_band_limited_steps_match_the_oracle_at_32(n, precision, tol):
+    """N = 192 and 256 (the radix-3 plans and the x stage's direct-to-LDS staging at
+    N = 256): a band-limited state steps to the same spectral state as at N = 32,
+    where the oracle computes it; two steps (Adams-Bashforth 1, then 2).  After the
+    first step every mode outside |k_i| <= 10 is zero; the second step's products
+    reach beyond the N = 32 band, whose phi^3 then aliases at the 4e-14 level (checked
+    on the oracle at N = 48 and 64), so only the modes |k_i| <= 10 are compared."""
+    p = _params(32, re=200.0, we=2.0, ch=0.05, pe=20.0, dt=2e-3)
+    prm = box.Params(**p)
+    u32, phi32 = _low_mode_fields(32)
+    st1 = box.step(box.init_state(u32, phi32, prm), prm)
+    st2 = box.step(st1, prm)
+    u, phi = _low_mode_fields(n)
+    s = _solver(dict(p, n=n), precision=precision)
+    s.init_state(_dev(u), _dev(phi))
+    K32 = (32 - 1) // 3
+    for i, ref in enumerate((st1, st2)):
+        s.step(1)
+        uh, ph = (_host(t) for t in s.get_state())
+        su, ru = _low_modes(uh, K32)
+        sp, rp = _low_modes(ph, K32)
+        wu, _ = _low_modes(ref["uh"], K32)
+        wp, _ = _low_modes(ref["ph"], K32)
+        assert rel_l2(su, wu) < tol, rel_l2(su, wu)
+        assert rel_l2(sp, wp) < tol, rel_l2(sp, wp)
+        if i == 0:
+            assert ru < tol * np.max(np.abs(wu)) and rp < tol * np.max(np.abs(wp))
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
