@@ -598,7 +598,7 @@ int psms_index_maps(psms_ctx* c, int32_t* d_out) {
 
 int psms_cheb_transform(int32_t nc, int64_t nlines, int32_t dir, int32_t precision, const void* d_in, void* d_out,
                         void* stream) {
-  if (!psms::supported_nc(nc)) return fail(PSMS_E_INVAL, "nc must be one of 4,6,8,12,16,24,32,48,64,96,128");
+  if (!psms::supported_nc(nc)) return fail(PSMS_E_INVAL, "nc must be one of 4,6,8,12,16,24,32,48,64,96,128,256");
   if (nlines < 0 || (dir != 1 && dir != -1)) return fail(PSMS_E_INVAL, "bad nlines or dir");
   if (precision != PSMS_FP64 && precision != PSMS_MIXED) return fail(PSMS_E_INVAL, "bad precision");
   if (nlines == 0) return PSMS_OK;
@@ -654,7 +654,8 @@ WallLayout wall_layout(int nc, long long nlines) {
   L.psib = off; off += arr;
   L.xi = off; off += arr;
   L.dw = off; off += arr;
-  L.xw = off; off += align256(size_t(nc + 1) * size_t(nlines) * sizeof(double));
+  // elimination scratch of up to four problems solved in one launch
+  L.xw = off; off += 4 * align256(size_t(nc + 1) * size_t(nlines) * sizeof(double));
   L.total = off;
   return L;
 }
@@ -690,28 +691,27 @@ int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* s
   hipError_t e;
 #define PSMS_TRY(x) \
   if ((e = (x)) != hipSuccess) return hip_fail(e, "wall_solve")
-  // omega_z
-  PSMS_TRY(psms::launch_helm(CC(a->d_g_om), CM(a->d_om), xw, nc, nl, nullptr, a->beta_ns, a->d_kx, a->d_ky, 0,
-                             nullptr, z0, z0, st));
-  // w: particular and homogeneous solutions, then the influence-matrix combination
-  PSMS_TRY(psms::launch_helm(CC(a->d_g_w), C(L.psi), xw, nc, nl, nullptr, a->beta_ns, a->d_kx, a->d_ky, 0, nullptr,
-                             z0, z0, st));
-  PSMS_TRY(psms::launch_helm(C(L.psi), CM(a->d_w), xw, nc, nl, nullptr, 0.0, a->d_kx, a->d_ky, 0, nullptr, z0, z0,
-                             st));
-  PSMS_TRY(psms::launch_helm(nullptr, C(L.psit), xw, nc, nl, nullptr, a->beta_ns, a->d_kx, a->d_ky, 0, nullptr, one,
-                             z0, st));
-  PSMS_TRY(psms::launch_helm(C(L.psit), C(L.wt), xw, nc, nl, nullptr, 0.0, a->d_kx, a->d_ky, 0, nullptr, z0, z0,
-                             st));
-  PSMS_TRY(psms::launch_helm(nullptr, C(L.psib), xw, nc, nl, nullptr, a->beta_ns, a->d_kx, a->d_ky, 0, nullptr, z0,
-                             one, st));
-  PSMS_TRY(psms::launch_helm(C(L.psib), C(L.wb), xw, nc, nl, nullptr, 0.0, a->d_kx, a->d_ky, 0, nullptr, z0, z0,
-                             st));
+  // the independent problems share a launch: omega_z and the three psi
+  // problems of w (particular, unit value at the top, at the bottom); then w
+  // from each psi and the first CH factor; then phi; then the influence-matrix
+  // combination
+  const long long xs = (long long)(align256(size_t(nc + 1) * size_t(nl) * sizeof(double)) / sizeof(double));
+  psms::HelmBatch b{};
+  b.np = 4;
+  b.p[0] = psms::HelmProblem{CC(a->d_g_om), CM(a->d_om), xw, nl, a->beta_ns, a->d_kx, a->d_ky, 0, z0, z0};
+  b.p[1] = psms::HelmProblem{CC(a->d_g_w), C(L.psi), xw + xs, nl, a->beta_ns, a->d_kx, a->d_ky, 0, z0, z0};
+  b.p[2] = psms::HelmProblem{nullptr, C(L.psit), xw + 2 * xs, nl, a->beta_ns, a->d_kx, a->d_ky, 0, one, z0};
+  b.p[3] = psms::HelmProblem{nullptr, C(L.psib), xw + 3 * xs, nl, a->beta_ns, a->d_kx, a->d_ky, 0, z0, one};
+  PSMS_TRY(psms::launch_helm_batch(b, nc, st));
+  b.p[0] = psms::HelmProblem{C(L.psi), CM(a->d_w), xw, nl, 0.0, a->d_kx, a->d_ky, 0, z0, z0};
+  b.p[1] = psms::HelmProblem{C(L.psit), C(L.wt), xw + xs, nl, 0.0, a->d_kx, a->d_ky, 0, z0, z0};
+  b.p[2] = psms::HelmProblem{C(L.psib), C(L.wb), xw + 2 * xs, nl, 0.0, a->d_kx, a->d_ky, 0, z0, z0};
+  b.p[3] = psms::HelmProblem{CC(a->d_g_phi), C(L.xi), xw + 3 * xs, nl, a->beta_a, a->d_kx, a->d_ky, 3, z0, z0};
+  PSMS_TRY(psms::launch_helm_batch(b, nc, st));
+  b.np = 1;
+  b.p[0] = psms::HelmProblem{C(L.xi), CM(a->d_phi), xw, nl, a->beta_b, a->d_kx, a->d_ky, 3, z0, z0};
+  PSMS_TRY(psms::launch_helm_batch(b, nc, st));
   PSMS_TRY(psms::launch_influence(CM(a->d_w), C(L.wt), C(L.wb), nc, nl, a->d_kx, a->d_ky, st));
-  // phi: two Neumann problems
-  PSMS_TRY(psms::launch_helm(CC(a->d_g_phi), C(L.xi), xw, nc, nl, nullptr, a->beta_a, a->d_kx, a->d_ky, 1, nullptr,
-                             z0, z0, st));
-  PSMS_TRY(psms::launch_helm(C(L.xi), CM(a->d_phi), xw, nc, nl, nullptr, a->beta_b, a->d_kx, a->d_ky, 1, nullptr, z0,
-                             z0, st));
   // u, v
   PSMS_TRY(psms::launch_chebd(CM(a->d_w), C(L.dw), nc, nl, st));
   PSMS_TRY(psms::launch_uv(CM(a->d_om), C(L.dw), CM(a->d_u), CM(a->d_v), nc, nl, a->d_kx, a->d_ky, st));
