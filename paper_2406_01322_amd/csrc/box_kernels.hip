@@ -49,7 +49,8 @@ __device__ __forceinline__ void lines_body(const cpx<T>* __restrict__ src, cpx<T
                                            const cpx<T>* __restrict__ tw_g, const LineArgs& a, bool deriv) {
   using G = Tile<P, V>;
   constexpr int N = P::N;
-  constexpr int E = G::E, L = G::L, LP = L + 1;
+  constexpr bool SWZ = N >= 256;   // see the LDS index functors
+  constexpr int E = G::E, L = G::L, LP = SWZ ? L : L + 1;
   constexpr int RI = first_radix<P, S>(), RO = last_radix<P, S>();
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> lds[2][N * LP];
@@ -80,7 +81,10 @@ __device__ __forceinline__ void lines_body(const cpx<T>* __restrict__ src, cpx<T
   }
   __syncthreads();
   int par = 0;
-  fft_line<T, P, S>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
+  if constexpr (SWZ)
+    fft_line<T, P, S>(v, lds[0], lds[1], par, t, IdxPosSwz{LP, line}, tw);
+  else
+    fft_line<T, P, S>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
   const T sc = T(a.scale);
 #pragma unroll
   for (int b = 0; b < E / RO; ++b) {
@@ -535,7 +539,7 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
   cpx<double>* __restrict__ hist = bx.hist;
   cpx<T>* __restrict__ gout = static_cast<cpx<T>*>(bx.bufb);
   const StepCoef sc = bx.sc;
-  constexpr int E = G::E, L = G::L, LP = L + 1, K = G::K, C = G::C, H = G::H;
+  constexpr int E = G::E, L = G::L, LP = L, K = G::K, C = G::C, H = G::H;   // swizzled tile
   constexpr int Q = C * H;
   constexpr long long M = (long long)C * Q;
   constexpr int RF = first_radix<P, -1>();   // forward starts with R[0]
@@ -551,7 +555,7 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
   const int iy = valid ? q / H : 0, ix = valid ? q % H : 0;
   const double kx = double(ix);
   const double ky = double(iy <= K ? iy : iy - C);
-  const IdxPosMajor idx{LP, line};
+  const IdxPosSwz idx{LP, line};
   int par = 0;
 
   // band membership and wavenumber of the slots the forward leaves in registers

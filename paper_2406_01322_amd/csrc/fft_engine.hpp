@@ -228,8 +228,16 @@ __device__ __forceinline__ void stage_regs(cpx<T>* v, int t, const cpx<T>* tw) {
 // LDS index functors.  kWaveLocal also selects the twiddle layout (per-stage
 // tables for row tiles, the plain table for strided tiles).
 //  * strided tiles (lanes run over lines first): element (pos, line) at
-//    pos * (L + 1) + line; a line's threads span the workgroup, so the
-//    exchanges synchronise the workgroup;
+//    pos * (L + 1) + line (IdxPosMajor), or at swz(pos) * L + line
+//    (IdxPosSwz), swz(p) = p ^ (((p >> 2) ^ (p >> 4) ^ (p >> 6) ^ (p >> 8)) & 3),
+//    a bijection on any multiple of 4 positions: a half wavefront's lanes
+//    touch 4 positions of the L lines, at position strides 1, R, R^2, ...
+//    depending on the stage, and the XOR sends each such set of positions to
+//    4 different groups of banks, where the padding of one line per position
+//    lets the bank groups of stride-4 positions overlap pairwise.  Measured:
+//    the swizzle pays in the z stage and for N = 256 lines, the padding is
+//    as fast or faster elsewhere.  A line's threads span the workgroup, so
+//    the exchanges synchronise the workgroup;
 //  * row tiles (lanes run over positions first): element (line, pos) at
 //    line * kRowStride<N> + pos + 3 (pos >> 4), the padding spreading the
 //    stride-R writes of the early stages over the banks; a line's TT <= 64
@@ -241,6 +249,13 @@ struct IdxPosMajor {
   static constexpr bool kWaveLocal = false;
   int lp, line;  // lp = L + 1
   __device__ __forceinline__ int operator()(int pos) const { return pos * lp + line; }
+};
+struct IdxPosSwz {
+  static constexpr bool kWaveLocal = false;
+  int l, line;  // l = L
+  __device__ __forceinline__ int operator()(int pos) const {
+    return (pos ^ (((pos >> 2) ^ (pos >> 4) ^ (pos >> 6) ^ (pos >> 8)) & 3)) * l + line;
+  }
 };
 template <int N, int TT = N>
 struct IdxLineMajor {
