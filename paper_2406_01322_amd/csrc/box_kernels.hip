@@ -1007,6 +1007,12 @@ hipError_t rows_n(int dir, const void* in, void* out, const cpx<T>* tw, const Ro
   return hipGetLastError();
 }
 
+// The y stages' largest variant: 512 threads in FP32 (twice the lines per
+// workgroup, so each position's row segment is 128 bytes, a whole cache line;
+// measured faster), 256 in FP64 (measured slower at 512).
+template <typename T, int V>
+constexpr int kYVariant = (V == 2 && sizeof(T) == 4) ? 3 : V;
+
 template <typename T, int N, int V>
 hipError_t step_nv(int stage, const BoxDev* boxes, int box0, int nbox, const cpx<T>* tw, int do_update,
                    hipStream_t st) {
@@ -1015,8 +1021,9 @@ hipError_t step_nv(int stage, const BoxDev* boxes, int box0, int nbox, const cpx
   const unsigned threads = unsigned(G::L * G::TT);
   switch (stage) {
     case 0: {  // y-inverse, 6 output fields
-      const dim3 grid(unsigned(((long long)N * G::H + G::L - 1) / G::L), 6, unsigned(nbox));
-      k_ystep<T, N, 1, V><<<grid, threads, 0, st>>>(boxes, box0, tw);
+      using GY = Tile<P, kYVariant<T, V>>;
+      const dim3 grid(unsigned(((long long)N * GY::H + GY::L - 1) / GY::L), 6, unsigned(nbox));
+      k_ystep<T, N, 1, kYVariant<T, V>><<<grid, unsigned(GY::L * GY::TT), 0, st>>>(boxes, box0, tw);
       break;
     }
     case 1: {  // x stage with products
@@ -1026,8 +1033,9 @@ hipError_t step_nv(int stage, const BoxDev* boxes, int box0, int nbox, const cpx
       break;
     }
     case 2: {  // y-forward, 8 fields
-      const dim3 grid(unsigned(((long long)N * G::H + G::L - 1) / G::L), 8, unsigned(nbox));
-      k_ystep<T, N, -1, V><<<grid, threads, 0, st>>>(boxes, box0, tw);
+      using GY = Tile<P, kYVariant<T, V>>;
+      const dim3 grid(unsigned(((long long)N * GY::H + GY::L - 1) / GY::L), 8, unsigned(nbox));
+      k_ystep<T, N, -1, kYVariant<T, V>><<<grid, unsigned(GY::L * GY::TT), 0, st>>>(boxes, box0, tw);
       break;
     }
     default: {  // z stage with the update
