@@ -349,7 +349,7 @@ def main():
                     help="first copy a buffer of this many MiB 3 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr, flush=True)
         sys.exit(2)
     import torch
