@@ -299,3 +299,24 @@ def test_bad_wall_flags_are_rejected():
     p, prm, f = _case("chan_small")
     with pytest.raises(ValueError):
         Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], walls=("slip", "noslip"))
+
+
+def test_single_phase_open_channel_parity_fp64():
+    """Single phase under a free-slip top wall (both switches at once), one AB2 step
+    against the oracle's step with phi = 0 and the same walls."""
+    import dataclasses
+    p, prm, f = _case("chan_mid")
+    walls = ("freeslip", "noslip")
+    prm = dataclasses.replace(prm, walls=walls)
+    u, v, w, _ = f
+    zero = np.zeros_like(u)
+    st = cs.run(cs.init_state(u, v, w, zero, prm), prm, 1)
+    ref = cs.step(st, prm)
+    c = _gpu(p, "fp64", single_phase=True, walls=walls)
+    _load(c, st)
+    c.step(1)
+    state, mean = (_host(t) for t in c.get_state())
+    for i, k in enumerate(("om", "w")):
+        assert _rel_max(state[i], ref[k]) < 1e-9, (k, _rel_max(state[i], ref[k]))
+    assert np.all(state[2] == 0.0)
+    assert _rel_max(mean, ref["mean"]) < 1e-9
