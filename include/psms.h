@@ -240,7 +240,8 @@ int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* s
 
 /* ---------------------------------------------------------------------------
  * The channel step (Sec. 2.1-2.2): x, y periodic (lengths lx, ly; Fourier, nx
- * and ny points), z in [-1, 1] between no-slip walls (Chebyshev-Gauss-Lobatto
+ * and ny points), z in [-1, 1] between no-slip walls, or free-slip ones (see
+ * free_slip) (Chebyshev-Gauss-Lobatto
  * points z_j = cos(pi j / nc), j = 0..nc).  The velocity is carried as the
  * wall-normal vorticity omega_z and velocity w (eqs. omegaz, ww, omegadef)
  * plus the mean velocities U(z), V(z); phi obeys the split CH equation
@@ -252,7 +253,9 @@ int psms_wall_solve(const psms_wall_args* a, void* d_work, size_t bytes, void* s
  * Adams-Bashforth (order 1 on the first step) with Crank-Nicolson viscous terms
  * and implicit Euler for the split CH operator, i.e. the wall-normal solves of
  * psms_wall_solve with beta_ns = 2 re / dt and the two CH factors, and the
- * Dirichlet mean-flow problem driven by -dP/dx = forcing.  re is Re_tau = 1/nu.
+ * Dirichlet (Neumann at a free-slip wall) mean-flow problem driven by
+ * -dP/dx = forcing.  re is Re_tau = 1/nu.  In single phase, phi and its
+ * history read back as zero.
  *
  * Spectral arrays are complex double [field][n][ky][kx] over the band
  * kx = 0..Kx, ky = 0..Ky, -Ky..-1 (Kx = floor((nx-1)/3), Ky = floor((ny-1)/3)),
@@ -288,7 +291,8 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
  * grid); the next step is Adams-Bashforth 1.  Synchronises. */
 int psms_channel_init_state(psms_channel* c, const double* d_u, const double* d_v, const double* d_w,
                             const double* d_phi);
-/* State, mean lines and (for nstep > 0) history in the layouts above. */
+/* State, mean lines and (for nstep > 0) history in the layouts above (in
+ * single phase the phi parts are ignored and set to zero). */
 int psms_channel_set_state(psms_channel* c, const double* d_state, const double* d_mean, const double* d_hist,
                            const double* d_hmean, int32_t nstep);
 int psms_channel_step(psms_channel* c, int32_t nsteps);
