@@ -1384,9 +1384,10 @@ const cpx<T>* chan_twz(const psms_channel* c) {
   return reinterpret_cast<const cpx<T>*>(c->ws + (std::is_same<T, double>::value ? c->lay.twz64 : c->lay.twz32));
 }
 
-// physical [nf][z][y][x] (T) -> band [nf][n][line] (T): x rows, y lines (1/(nx ny)), DCT-I
+// physical [nf][z][y][x] (T) -> band [nf][n][line] (T): x rows, y lines (1/(nx ny)), DCT-I;
+// with band64, the DCT-I writes FP64 coefficients there instead, n > Kz zeroed
 template <typename T>
-hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf) {
+hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf, cpx<double>* band64 = nullptr) {
   const psms::ChanGeom& g = c->g;
   const long long nz = g.nc + 1;
   cpx<T>* B = c->at<cpx<T>>(c->lay.B);
@@ -1411,7 +1412,8 @@ hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf) {
   la.dmask = 0;
   la.scale = 1.0 / (double(g.nx) * double(g.ny));
   e = psms::launch_lines<T>(g.ny, -1, B, A2, chan_tw<T>(c, false), la, nf, c->stream);
-  if (e == hipSuccess) e = psms::launch_dct_fields<T>(g.nc, A2, band, g.NL, g.NZL, nf, chan_twz<T>(c), +1, c->stream);
+  if (e == hipSuccess)
+    e = psms::launch_dct_fields<T>(g.nc, A2, band, g.NL, g.NZL, nf, chan_twz<T>(c), +1, c->stream, band64, g.Kz);
   return e;
 }
 
@@ -1476,8 +1478,7 @@ hipError_t chan_step_once(psms_channel* c) {
   PSMS_TRY(chan_inverse<T>(c, c->at<cpx<T>>(L.A), c->at<T>(L.C), g.nf_in));
   // 3-4. products and the forward transforms, 2/3 rule in x, y and z
   PSMS_TRY(psms::launch_ch_products<T>(g, c->at<T>(L.C), c->coef.csig, st));
-  PSMS_TRY(chan_forward<T>(c, c->at<T>(L.C), c->at<cpx<T>>(L.A), g.nf_out));
-  PSMS_TRY(psms::launch_ch_promote<T>(g, c->at<cpx<T>>(L.A), R, st));
+  PSMS_TRY(chan_forward<T>(c, c->at<T>(L.C), c->at<cpx<T>>(L.A), g.nf_out, R));   // FP64, Chebyshev cut
   // 5. S = div T, and the wall-normal derivatives the right-hand sides need
   cpx<double>* D3 = C64(L.D3);
   cb.n = 3;   // D T_xz, D T_yz, D T_zz

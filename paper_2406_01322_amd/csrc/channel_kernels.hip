@@ -43,10 +43,14 @@ struct CTile {
 //   a_n = G_n / (nc cbar_n),  G = FFT of the even extension of f;
 // dir = -1: coefficients -> values, f_j = FFT of the even extension of b with
 //   b_0 = a_0, b_nc = a_nc, b_n = a_n / 2.
+// out64 (forward only, if not NULL): the coefficients are written in FP64
+// instead, those with n > kz as zero (the products' Chebyshev truncation),
+// so the step needs no separate promotion pass.
 template <typename T, int N>
 __global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                              long long nlines, int dir, long long fstride,
-                                             const cpx<T>* __restrict__ tw_g) {
+                                             const cpx<T>* __restrict__ tw_g, cpx<double>* __restrict__ out64,
+                                             int kz) {
   using P = Plan<N>;
   using G = CTile<P>;
   constexpr int E = G::E, L = G::L, LP = L + 1, NC = N / 2;
@@ -57,6 +61,7 @@ __global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx
   const int line = tid % L, t = tid / L;
   in += (long long)blockIdx.y * fstride;   // field blockIdx.y
   out += (long long)blockIdx.y * fstride;
+  if (out64) out64 += (long long)blockIdx.y * fstride;
   if (tw_g) {
     for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
   } else {
@@ -101,7 +106,10 @@ __global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx
             x.re *= sc;
             x.im *= sc;
           }
-          out[(long long)p * nlines + l] = x;
+          if (out64)
+            out64[(long long)p * nlines + l] = (p > kz) ? cpx<double>{0.0, 0.0} : cpx<double>{double(x.re), double(x.im)};
+          else
+            out[(long long)p * nlines + l] = x;
         }
       }
   }
@@ -617,10 +625,10 @@ bool supported_nc(int nc) {
 namespace {
 template <typename T, int N>
 hipError_t dct_n(const cpx<T>* in, cpx<T>* out, long long nlines, int dir, long long fstride, int nfield,
-                 const cpx<T>* tw, hipStream_t st) {
+                 const cpx<T>* tw, cpx<double>* out64, int kz, hipStream_t st) {
   using G = CTile<Plan<N>>;
   const dim3 grid(unsigned((nlines + G::L - 1) / G::L), unsigned(nfield));
-  k_dct<T, N><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw);
+  k_dct<T, N><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw, out64, kz);
   return hipGetLastError();
 }
 unsigned blocks(long long n, int bs) {
@@ -636,10 +644,11 @@ hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, i
 
 template <typename T>
 hipError_t launch_dct_fields(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, long long fstride, int nfield,
-                             const cpx<T>* tw, int dir, hipStream_t st) {
+                             const cpx<T>* tw, int dir, hipStream_t st, cpx<double>* out64, int kz) {
   if (nfield < 1 || nlines == 0) return hipSuccess;
+  if (out64 && dir < 0) return hipErrorInvalidValue;
   switch (2 * nc) {
-#define PSMS_CASE(NN) case NN: return dct_n<T, NN>(in, out, nlines, dir, fstride, nfield, tw, st);
+#define PSMS_CASE(NN) case NN: return dct_n<T, NN>(in, out, nlines, dir, fstride, nfield, tw, out64, kz, st);
     PSMS_FOR_EACH_2NC(PSMS_CASE)
 #undef PSMS_CASE
   }
@@ -724,9 +733,9 @@ hipError_t launch_uv(const cpx<double>* om, const cpx<double>* dw, cpx<double>* 
 
 template hipError_t launch_dct<double>(int, const cpx<double>*, cpx<double>*, long long, int, hipStream_t);
 template hipError_t launch_dct_fields<double>(int, const cpx<double>*, cpx<double>*, long long, long long, int,
-                                              const cpx<double>*, int, hipStream_t);
+                                              const cpx<double>*, int, hipStream_t, cpx<double>*, int);
 template hipError_t launch_dct_fields<float>(int, const cpx<float>*, cpx<float>*, long long, long long, int,
-                                             const cpx<float>*, int, hipStream_t);
+                                             const cpx<float>*, int, hipStream_t, cpx<double>*, int);
 template hipError_t launch_dct<float>(int, const cpx<float>*, cpx<float>*, long long, int, hipStream_t);
 
 }  // namespace psms

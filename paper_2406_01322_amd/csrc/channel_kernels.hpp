@@ -13,10 +13,11 @@ bool supported_nc(int nc);
 template <typename T>
 hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st);
 // nfield fields fstride elements apart in one launch; tw: exp(-2 pi i m / (2 nc)),
-// m < 2 nc, or NULL (computed in the kernel)
+// m < 2 nc, or NULL (computed in the kernel).  out64 (forward only): write the
+// coefficients to it in FP64 instead of to out, those with n > kz as zero.
 template <typename T>
 hipError_t launch_dct_fields(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, long long fstride, int nfield,
-                             const cpx<T>* tw, int dir, hipStream_t st);
+                             const cpx<T>* tw, int dir, hipStream_t st, cpx<double>* out64 = nullptr, int kz = 0);
 hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st);
 // up to kChebBatchMax arrays of the same lines per launch: out[j] = D in[j]
 // (lap = 0) or D^2 in[j] - k^2 in[j] (lap = 1)

@@ -87,15 +87,6 @@ __global__ void k_ch_products(ChanGeom g, T* __restrict__ f, T cs) {
   }
 }
 
-template <typename T>
-__global__ void k_ch_promote(ChanGeom g, const cpx<T>* __restrict__ in, cpx<double>* __restrict__ out) {
-  PSMS_GRID_LOOP(id, g.nf_out * g.NZL) {
-    const long long n = (id % g.NZL) / g.NL;
-    const cpx<T> x = in[id];
-    out[id] = (n > g.Kz) ? cpx<double>{0.0, 0.0} : cpx<double>{double(x.re), double(x.im)};
-  }
-}
-
 __global__ void k_ch_s(ChanGeom g, const cpx<double>* __restrict__ R, const cpx<double>* __restrict__ dxz,
                        const cpx<double>* __restrict__ dyz, const cpx<double>* __restrict__ dzz,
                        const double* __restrict__ kxl, const double* __restrict__ kyl, cpx<double>* __restrict__ s3,
@@ -197,11 +188,6 @@ hipError_t launch_ch_products(const ChanGeom& g, T* f, double csig, hipStream_t 
   k_ch_products<T><<<blocks_for(g.P), kThreads, 0, st>>>(g, f, T(csig));
   return hipGetLastError();
 }
-template <typename T>
-hipError_t launch_ch_promote(const ChanGeom& g, const cpx<T>* in, cpx<double>* out, hipStream_t st) {
-  k_ch_promote<T><<<blocks_for(g.nf_out * g.NZL), kThreads, 0, st>>>(g, in, out);
-  return hipGetLastError();
-}
 hipError_t launch_ch_s(const ChanGeom& g, const cpx<double>* R, const cpx<double>* dxz, const cpx<double>* dyz,
                        const cpx<double>* dzz, const double* kx, const double* ky, cpx<double>* s3, cpx<double>* q,
                        hipStream_t st) {
@@ -232,7 +218,5 @@ template hipError_t launch_ch_fields<double>(const ChanGeom&, const cpx<double>*
                                              hipStream_t);
 template hipError_t launch_ch_products<float>(const ChanGeom&, float*, double, hipStream_t);
 template hipError_t launch_ch_products<double>(const ChanGeom&, double*, double, hipStream_t);
-template hipError_t launch_ch_promote<float>(const ChanGeom&, const cpx<float>*, cpx<double>*, hipStream_t);
-template hipError_t launch_ch_promote<double>(const ChanGeom&, const cpx<double>*, cpx<double>*, hipStream_t);
 
 }  // namespace psms

@@ -38,9 +38,6 @@ hipError_t launch_ch_fields(const ChanGeom& g, const cpx<double>* om, const cpx<
 // phase 3 in, the 6 components of -u_i u_j out
 template <typename T>
 hipError_t launch_ch_products(const ChanGeom& g, T* f, double csig, hipStream_t st);
-// g.nf_out transformed products (precision T) -> FP64 with Chebyshev modes n > Kz zeroed
-template <typename T>
-hipError_t launch_ch_promote(const ChanGeom& g, const cpx<T>* in, cpx<double>* out, hipStream_t st);
 // S_x, S_y, S_z and Q = i kx S_x + i ky S_y from the products and D T_xz, D T_yz, D T_zz
 hipError_t launch_ch_s(const ChanGeom& g, const cpx<double>* R, const cpx<double>* dxz, const cpx<double>* dyz,
                        const cpx<double>* dzz, const double* kx, const double* ky, cpx<double>* s3, cpx<double>* q,
