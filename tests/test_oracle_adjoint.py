@@ -90,3 +90,60 @@ def test_gradient_matches_central_differences():
         fd = (Jat(+1) - Jat(-1)) / (2 * eps)
         ad = float(np.sum(dphi0 * d)) + dwe * dw
         assert abs(fd - ad) < 1e-6 * max(abs(fd), 1e-8 * abs(J)), (fd, ad)
+
+
+def _objective_closed_form():
+    """The trigonometric fields of the box diagnostics pin: J = (2 pi)^3 (<|grad phi|^2>
+    + 1/2 <|u|^2>) with both averages in closed form."""
+    import math
+    n = 16
+    x = 2.0 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    A, B, C = 0.7, -0.4, 0.9
+    u = np.stack([A * np.sin(2 * Y + Z), B * np.cos(X - 3 * Z), C * np.sin(2 * X + Y)])
+    modes = [((1, 2, 0), 0.3, 0.4), ((0, -1, 3), 0.2, -1.1), ((2, 0, 0), 0.1, 0.0)]
+    phi = np.full((n, n, n), 0.1)
+    for (kx, ky, kz), a, t in modes:
+        phi += a * np.cos(kx * X + ky * Y + kz * Z + t)
+    g2 = sum(a * a * (kx * kx + ky * ky + kz * kz) / 2.0 for (kx, ky, kz), a, _ in modes)
+    u2 = (A * A + B * B + C * C) / 2.0
+    J = (2.0 * math.pi) ** 3 * (g2 + 0.5 * u2)
+    prm = box.Params(n=n, re=100.0, we=1.0, ch=0.05, pe=20.0, dt=1e-3)
+    return box.init_state(u, phi, prm), J
+
+
+def test_objective_closed_form():
+    """J of the terminal state equals int |grad phi|^2 + 1/2 int |u|^2 over the
+    (2 pi)^3 box, in closed form for trigonometric fields (pins the Parseval
+    weights, the factor 1/2 and the volume)."""
+    st, J = _objective_closed_form()
+    assert abs(adj.objective(st, 16) - J) < 1e-13 * J
+
+
+@pytest.mark.parametrize("plant", ["weight2_at_kx0", "unit_volume"])
+def test_objective_pin_catches_planted_mistakes(monkeypatch, plant):
+    if plant == "weight2_at_kx0":
+        monkeypatch.setattr(box, "half_weights", lambda n: np.full(n // 2 + 1, 2.0))
+    else:
+        monkeypatch.setattr(adj, "VOLUME", 1.0)
+    st, J = _objective_closed_form()
+    assert abs(adj.objective(st, 16) - J) > 1e-3 * J
+
+
+def test_objective_gradient_is_the_derivative_of_j():
+    """objective_grad is the Riesz representative of dJ under the half-spectrum inner
+    product: <grad, d> equals the central difference of J along d (J is quadratic, so
+    the difference is exact up to rounding)."""
+    st, _ = _objective_closed_form()
+    n = 16
+    D = box.dealias_mask(n)
+    rng = np.random.default_rng(4)
+    du = box.fwd(rng.standard_normal((3, n, n, n))) * D
+    dp = box.fwd(rng.standard_normal((n, n, n))) * D
+    gu, gp = adj.objective_grad(st, n)
+    eps = 1e-3
+    sp = dict(st, uh=st["uh"] + eps * du, ph=st["ph"] + eps * dp)
+    sm = dict(st, uh=st["uh"] - eps * du, ph=st["ph"] - eps * dp)
+    fd = (adj.objective(sp, n) - adj.objective(sm, n)) / (2 * eps)
+    an = adj.inner(gu, du) + adj.inner(gp, dp)
+    assert abs(fd - an) < 1e-10 * abs(an)

@@ -399,3 +399,57 @@ def test_band_limited_step_is_independent_of_n():
     assert np.max(np.abs(u48 - u32)) < 1e-15 * 100 * np.max(np.abs(u32))
     assert np.max(np.abs(p48 - p32)) < 1e-15 * 100 * np.max(np.abs(p32))
     assert ru < 1e-15 and rp < 1e-15
+
+
+# ---------------------------------------------------------------- diagnostics by quadrature
+
+def _trig_state(n=16):
+    """A solenoidal trigonometric velocity and a trigonometric phase field with their
+    volume averages in closed form.  u = (A sin(2y + z), B cos(x - 3z), C sin(2x + y))
+    (each component independent of its own coordinate, so div u = 0) has
+    <|u|^2> = (A^2 + B^2 + C^2)/2; phi = c0 + sum_m a_m cos(k_m.x + t_m) over distinct
+    wavevectors has <|grad phi|^2> = sum_m a_m^2 |k_m|^2 / 2.  One phi mode and one
+    velocity component have kx = 0, the others kx > 0, so the half-spectrum weights of
+    both kinds enter."""
+    X, Y, Z = _grid(n)
+    A, B, C = 0.7, -0.4, 0.9
+    u = np.stack([A * np.sin(2 * Y + Z), B * np.cos(X - 3 * Z), C * np.sin(2 * X + Y)])
+    modes = [((1, 2, 0), 0.3, 0.4), ((0, -1, 3), 0.2, -1.1), ((2, 0, 0), 0.1, 0.0), ((3, 1, -2), 0.05, 2.0)]
+    phi = np.full((n, n, n), -0.3)
+    for (kx, ky, kz), a, t in modes:
+        phi += a * np.cos(kx * X + ky * Y + kz * Z + t)
+    ke = 0.5 * (A * A + B * B + C * C) / 2.0
+    grad2 = sum(a * a * (kx * kx + ky * ky + kz * kz) / 2.0 for (kx, ky, kz), a, _ in modes)
+    prm = box.Params(n=n, re=100.0, we=1.0, ch=0.05, pe=20.0, dt=1e-3)
+    return box.init_state(u, phi, prm), ke, grad2, u, phi
+
+
+def _diag_errors():
+    st, ke, grad2, u, phi = _trig_state()
+    d = box.diagnostics(st, 16)
+    return abs(d["ke"] - ke) / ke, abs(d["grad2"] - grad2) / grad2, d
+
+
+def test_kinetic_energy_and_gradient_norm_closed_form():
+    """The spectral diagnostics (Parseval over the half spectrum) equal the volume
+    averages 1/2 <|u|^2> and <|grad phi|^2> of the trigonometric fields in closed form,
+    and the plain grid averages of the same fields (exact quadrature: every product of
+    two band-limited fields stays below the grid's Nyquist)."""
+    eke, eg2, d = _diag_errors()
+    assert eke < 1e-14 and eg2 < 1e-14
+    st, ke, grad2, u, phi = _trig_state()
+    assert abs(0.5 * np.mean(np.sum(u * u, axis=0)) - ke) < 1e-14
+    assert abs(d["mean_phi"] + 0.3) < 1e-15
+
+
+@pytest.mark.parametrize("plant", ["weight2_at_kx0", "no_half", "weight1_everywhere"])
+def test_diagnostics_pin_catches_planted_mistakes(monkeypatch, plant):
+    """A wrong Parseval weight or a dropped factor 1/2 fails the closed-form pin."""
+    if plant == "weight2_at_kx0":
+        monkeypatch.setattr(box, "half_weights", lambda n: np.full(n // 2 + 1, 2.0))
+    elif plant == "weight1_everywhere":
+        monkeypatch.setattr(box, "half_weights", lambda n: np.ones(n // 2 + 1))
+    eke, eg2, d = _diag_errors()
+    if plant == "no_half":
+        eke = abs(2.0 * d["ke"] - _trig_state()[1]) / _trig_state()[1]
+    assert max(eke, eg2) > 1e-3
