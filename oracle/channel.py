@@ -23,6 +23,8 @@ phisplit; Sec. 3.2.2).  This module writes those operations out densely:
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 from numpy.polynomial import chebyshev as npcheb
 
@@ -79,6 +81,14 @@ def d2_matrix(nc: int) -> np.ndarray:
     return D2
 
 
+@functools.lru_cache(maxsize=None)
+def _d2_fixed(nc: int) -> np.ndarray:
+    """d2_matrix(nc), built once per nc and kept read-only."""
+    m = d2_matrix(nc)
+    m.setflags(write=False)
+    return m
+
+
 def _wall_row(nc: int, kind: str, wall: int) -> np.ndarray:
     """Row evaluating f (Dirichlet) or f' (Neumann) at z = wall (+1 or -1):
     T_n(+-1) = (+-1)^n, T_n'(+-1) = (+-1)^(n+1) n^2."""
@@ -105,7 +115,7 @@ def helmholtz(g: np.ndarray, beta: float, kind="dirichlet", top=0.0, bottom=0.0)
     does).  Dense LU."""
     g = np.asarray(g)
     nc = g.shape[0] - 1
-    A = d2_matrix(nc) - beta * np.eye(nc + 1)
+    A = _d2_fixed(nc) - beta * np.eye(nc + 1)
     rt, rb = bc_rows(nc, kind)
     A[nc - 1] = rt
     A[nc] = rb
@@ -113,6 +123,37 @@ def helmholtz(g: np.ndarray, beta: float, kind="dirichlet", top=0.0, bottom=0.0)
     rhs[nc - 1] = top
     rhs[nc] = bottom
     return np.linalg.solve(A, rhs)
+
+
+def helmholtz_lines(g: np.ndarray, beta, kind="dirichlet", top=0.0, bottom=0.0, chunk: int = 512) -> np.ndarray:
+    """`helmholtz` for many independent lines at once: g [nc+1][L] (one line per
+    column), beta [L] (or a scalar), the same kind for every line, top and
+    bottom scalars or [L].  Each line gets exactly the matrix `helmholtz` builds
+    for it; the L dense systems are solved as one stacked LU call, `chunk`
+    lines at a time (only to bound memory).  The matrices are real, so the real
+    and imaginary parts of each right-hand side share one real factorisation."""
+    g = np.asarray(g)
+    nc = g.shape[0] - 1
+    L = g.shape[1]
+    beta = np.broadcast_to(np.asarray(beta, dtype=float), (L,))
+    top = np.broadcast_to(np.asarray(top), (L,))
+    bottom = np.broadcast_to(np.asarray(bottom), (L,))
+    rt, rb = bc_rows(nc, kind)
+    eye = np.eye(nc + 1)
+    out = np.empty((nc + 1, L), dtype=complex)
+    for s in range(0, L, chunk):
+        e = min(L, s + chunk)
+        A = _d2_fixed(nc)[None] - beta[s:e, None, None] * eye[None]
+        A[:, nc - 1] = rt
+        A[:, nc] = rb
+        rhs = np.array(g[:, s:e].T, dtype=complex)
+        rhs[:, nc - 1] = top[s:e]
+        rhs[:, nc] = bottom[s:e]
+        # the matrix is real: one real LU per line, the real and imaginary parts of
+        # the right-hand side as its two columns
+        x = np.linalg.solve(A, np.stack([rhs.real, rhs.imag], axis=-1))
+        out[:, s:e] = (x[..., 0] + 1j * x[..., 1]).T
+    return out
 
 
 def wall_values(a: np.ndarray):
@@ -181,4 +222,55 @@ def wall_normal_solve(g_om, g_w, g_phi, kx, ky, beta_ns, beta_a, beta_b, walls=(
         dw = deriv(w)
         u = 1j * (kx * dw + ky * om) / k2
         v = 1j * (ky * dw - kx * om) / k2
+    return dict(omega=om, w=w, phi=phi, u=u, v=v)
+
+
+def wall_normal_solve_lines(g_om, g_w, g_phi, kx, ky, beta_ns, beta_a, beta_b, walls=("noslip", "noslip")):
+    """`wall_normal_solve` for L pairs at once: g_* [nc+1][L], kx, ky, beta_* [L].
+    The same problems, the same matrices and the same influence-matrix
+    combination per line; every Helmholtz problem of the set is one stacked
+    dense solve (`helmholtz_lines`).  Returns dict(omega, w, phi, u, v) of
+    [nc+1][L] arrays."""
+    g_om, g_w, g_phi = (np.asarray(g) for g in (g_om, g_w, g_phi))
+    nc, L = g_om.shape[0] - 1, g_om.shape[1]
+    kx = np.asarray(kx, dtype=float)
+    ky = np.asarray(ky, dtype=float)
+    beta_ns = np.broadcast_to(np.asarray(beta_ns, dtype=float), (L,))
+    k2 = kx * kx + ky * ky
+    om = helmholtz_lines(g_om, beta_ns, wall_kinds(walls))
+    w = np.zeros((nc + 1, L), complex)
+    nz = np.nonzero(k2 != 0.0)[0]
+    if len(nz):
+        bn, kn = beta_ns[nz], k2[nz]
+        psi_p = helmholtz_lines(g_w[:, nz], bn, "dirichlet")
+        w_p = helmholtz_lines(psi_p, kn, "dirichlet")
+        clamped = [j for j in range(2) if walls[j] == "noslip"]
+        n = np.arange(nc + 1, dtype=float)
+        dwall = (n * n, (-1.0) ** (n + 1) * n * n)          # rows of w'(+1), w'(-1)
+        if clamped:
+            zero = np.zeros((nc + 1, len(nz)))
+            w_h = []
+            for j in clamped:
+                psi_j = helmholtz_lines(zero, bn, "dirichlet", 1.0 if j == 0 else 0.0, 1.0 if j == 1 else 0.0)
+                w_h.append(helmholtz_lines(psi_j, kn, "dirichlet"))
+            M = np.empty((len(nz), len(clamped), len(clamped)), complex)
+            for a, i in enumerate(clamped):
+                for b, wh in enumerate(w_h):
+                    M[:, a, b] = dwall[i] @ wh
+            r = -np.stack([dwall[i] @ w_p for i in clamped], axis=1)
+            c = np.linalg.solve(M, r[..., None])[..., 0]
+            acc = 0
+            for b, wh in enumerate(w_h):
+                acc = acc + c[:, b][None, :] * wh
+            w[:, nz] = w_p + acc
+        else:
+            w[:, nz] = w_p
+    xi = helmholtz_lines(g_phi, beta_a, "neumann")
+    phi = helmholtz_lines(xi, beta_b, "neumann")
+    u = np.zeros((nc + 1, L), complex)
+    v = np.zeros((nc + 1, L), complex)
+    if len(nz):
+        dw = deriv(w[:, nz])
+        u[:, nz] = 1j * (kx[nz] * dw + ky[nz] * om[:, nz]) / k2[nz]
+        v[:, nz] = 1j * (ky[nz] * dw - kx[nz] * om[:, nz]) / k2[nz]
     return dict(omega=om, w=w, phi=phi, u=u, v=v)

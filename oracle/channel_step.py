@@ -256,13 +256,15 @@ def step(st: dict, p: ChannelParams, lines=None) -> dict:
         om = np.full(shp, np.nan + 0j)
         w = np.full(shp, np.nan + 0j)
         ph = np.full(shp, np.nan + 0j)
-    for iy, ix in lines:
-        kk = kx[ix] ** 2 + ky[iy] ** 2
-        r = ch.wall_normal_solve(g_om[:, iy, ix], g_w[:, iy, ix], g_phi[:, iy, ix], kx[ix], ky[iy],
-                                 kk + beta, kk + a, kk + b, p.walls)
-        om[:, iy, ix] = r["omega"]
-        w[:, iy, ix] = r["w"]
-        ph[:, iy, ix] = r["phi"]
+    iy = np.array([l[0] for l in lines], dtype=int)
+    ix = np.array([l[1] for l in lines], dtype=int)
+    kk = kx[ix] ** 2 + ky[iy] ** 2
+    # every (kx, ky) pair's problems, solved together (each line its own dense systems)
+    r = ch.wall_normal_solve_lines(g_om[:, iy, ix], g_w[:, iy, ix], g_phi[:, iy, ix], kx[ix], ky[iy],
+                                   kk + beta, kk + a, kk + b, p.walls)
+    om[:, iy, ix] = r["omega"]
+    w[:, iy, ix] = r["w"]
+    ph[:, iy, ix] = r["phi"]
     d2 = dz(dz(st["mean"].T)).T
     mean = np.zeros((2, p.nc + 1), complex)
     drive = np.zeros(p.nc + 1)

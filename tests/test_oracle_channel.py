@@ -202,3 +202,23 @@ def test_mean_mode_has_no_wall_normal_velocity():
     g = np.ones(nc + 1, complex)
     r = ch.wall_normal_solve(g, g, g, 0.0, 0.0, 100.0, 30.0, 50.0)
     assert np.all(r["w"] == 0) and np.all(r["u"] == 0) and np.all(r["v"] == 0)
+
+
+@pytest.mark.parametrize("walls", [("noslip", "noslip"), ("freeslip", "noslip"), ("freeslip", "freeslip")])
+def test_stacked_line_solves_equal_the_per_line_solves(walls):
+    """The stacked solve of many (kx, ky) pairs builds, per line, the matrices of the
+    one-line solve: their results agree to rounding (the w combination cancels to
+    about 1e-13 of its terms at large k), including the mean pair k = 0."""
+    nc, L = 32, 9
+    rng = np.random.default_rng(11)
+    g = [rng.standard_normal((nc + 1, L)) + 1j * rng.standard_normal((nc + 1, L)) for _ in range(3)]
+    kx = np.array([0.0, 0.5, 0.0, 1.0, 2.5, 3.0, 0.5, 7.0, 10.5])
+    ky = np.array([0.0, 0.0, 1.0, -1.0, 2.0, -3.0, 4.0, 0.0, -6.0])
+    k2 = kx * kx + ky * ky
+    b_ns, b_a, b_b = k2 + 2e5, k2 + 900.0, k2 + 2500.0
+    got = ch.wall_normal_solve_lines(*g, kx, ky, b_ns, b_a, b_b, walls)
+    for l in range(L):
+        want = ch.wall_normal_solve(g[0][:, l], g[1][:, l], g[2][:, l], kx[l], ky[l], b_ns[l], b_a[l], b_b[l], walls)
+        for k in ("omega", "w", "phi", "u", "v"):
+            scale = max(np.max(np.abs(want[k])), 1e-300)
+            assert np.max(np.abs(got[k][:, l] - want[k])) <= 1e-12 * scale, (k, l)
