@@ -280,3 +280,71 @@ def run(st: dict, p: ChannelParams, nsteps: int) -> dict:
     for _ in range(nsteps):
         st = step(st, p)
     return st
+
+
+# ---------------------------------------------------------------------------
+# diagnostics (volume averages over [0, Lx) x [0, Ly) x [-1, 1])
+# ---------------------------------------------------------------------------
+
+def cheb_integrals(nc: int) -> np.ndarray:
+    """int_{-1}^{1} T_n(z) dz = 2 / (1 - n^2) for even n, 0 for odd n."""
+    n = np.arange(nc + 1)
+    out = np.zeros(nc + 1)
+    ev = n % 2 == 0
+    out[ev] = 2.0 / (1.0 - n[ev].astype(float) ** 2)
+    return out
+
+
+def cheb_gram(nc: int) -> np.ndarray:
+    """G[m, n] = int_{-1}^{1} T_m T_n dz = (I(m + n) + I(|m - n|)) / 2 with
+    I(k) = int T_k (the product rule T_m T_n = (T_{m+n} + T_{|m-n|}) / 2)."""
+    I = cheb_integrals(2 * nc)
+    m = np.arange(nc + 1)
+    return 0.5 * (I[m[:, None] + m[None, :]] + I[np.abs(m[:, None] - m[None, :])])
+
+
+def local_spacing(nc: int) -> np.ndarray:
+    """Grid spacing at each CGL point: (z_{j-1} - z_{j+1}) / 2 inside, the one-sided
+    spacing at the two walls."""
+    z = ch.cgl(nc)
+    dz_ = np.empty(nc + 1)
+    dz_[1:-1] = 0.5 * (z[:-2] - z[2:])
+    dz_[0] = z[0] - z[1]
+    dz_[-1] = z[-2] - z[-1]
+    return dz_
+
+
+def diagnostics(st: dict, p: ChannelParams) -> dict:
+    """Volume averages of the state (eqs. cont and CHE):
+      mean_phi = <phi> = (1/2) int phi_00(z) dz (the mean line, kx = ky = 0);
+      ke    = 1/2 <|u|^2>, grad2 = <|grad phi|^2>: Parseval in x and y (half-spectrum
+              weights 1 at kx = 0, 2 otherwise) and the exact Chebyshev integral
+              (1/2) int conj(f) g dz = (1/2) a^H G b in z (cheb_gram);
+      max_div = max |i kx u + i ky v + D w| over the band (continuity);
+      nonfinite = number of non-finite entries of the state and mean lines;
+      cfl   = dt max (|u| / dx + |v| / dy + |w| / dz_j) over the collocation grid,
+              dx = Lx / nx, dy = Ly / ny, dz_j the local spacing (local_spacing)."""
+    kx, ky = band_wavenumbers(p)
+    KX = kx[None, None, :]
+    KY = ky[None, :, None]
+    u, v = velocities(st, p)
+    w, ph = st["w"], st["phi"]
+    G = cheb_gram(p.nc)
+    wx = np.where(kx == 0.0, 1.0, 2.0)[None, :]
+
+    def avg_sq(a):
+        """<|f|^2> of a band field a [n][ky][kx]."""
+        per_line = np.einsum("mij,mn,nij->ij", np.conj(a), G, a).real
+        return 0.5 * float(np.sum(wx * per_line))
+
+    ke = 0.5 * (avg_sq(u) + avg_sq(v) + avg_sq(w))
+    grad2 = avg_sq(1j * KX * ph) + avg_sq(1j * KY * ph) + avg_sq(dz(ph))
+    mean_phi = 0.5 * float(np.dot(cheb_integrals(p.nc), ph[:, 0, 0].real))
+    div = 1j * KX * u + 1j * KY * v + dz(w)
+    arrays = [st["om"], st["w"], st["phi"], st["mean"]]
+    nonfinite = int(sum(np.count_nonzero(~np.isfinite(a)) for a in arrays))
+    U, V, W = (to_physical(x, p) for x in (u, v, w))
+    dzl = local_spacing(p.nc)[:, None, None]
+    speed = np.abs(U) / (p.lx / p.nx) + np.abs(V) / (p.ly / p.ny) + np.abs(W) / dzl
+    return dict(mean_phi=mean_phi, ke=ke, grad2=grad2, max_div=float(np.max(np.abs(div))),
+                nonfinite=nonfinite, cfl=float(p.dt * np.max(speed)))

@@ -243,3 +243,72 @@ def test_small_step_response_to_capillary_forcing():
     lw = cs.to_physical(cs.lap(st1["w"], p), p)[inner] / p.dt
     ref = cs.to_physical(want["h_w"], p)[inner]
     assert np.max(np.abs(lw - ref)) < 1e-3 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# diagnostics: volume averages of fields whose averages are known in closed form
+# ---------------------------------------------------------------------------
+
+def _diag_fields(p, A=3.0, B=0.7, c0=0.25):
+    """A solenoidal velocity and a phase field with closed-form volume averages:
+    U(z) = A (1 - z^2) (mean flow); u' = f'(z) sin(kx x), w = -kx f(z) cos(kx x) from
+    the stream function f(z) sin(kx x), f = (1 - z^2)^2; v = B (1 - z^2) cos(kx x)
+    (divergence free on its own); phi = c0 + z^2 / 2 + h(z) cos(kx x + ky y),
+    h = z (1 - z^2)."""
+    import sympy as sp
+    zs = sp.symbols("z")
+    f = (1 - zs ** 2) ** 2
+    h = zs * (1 - zs ** 2)
+    kx, ky = 2 * math.pi / p.lx, 2 * math.pi / p.ly
+    z, Z, Y, X = _grid(p)
+    lam = lambda e: sp.lambdify(zs, e, "numpy")
+    fz, dfz, hz = lam(f)(Z), lam(sp.diff(f, zs))(Z), lam(h)(Z)
+    u = A * (1 - Z ** 2) + dfz * np.sin(kx * X)
+    w = -kx * fz * np.cos(kx * X)
+    v = B * (1 - Z ** 2) * np.cos(kx * X)
+    phi = c0 + 0.5 * Z ** 2 + hz * np.cos(kx * X + ky * Y)
+    half = lambda e: float(sp.integrate(e, (zs, -1, 1))) / 2.0     # (1/2) int dz
+    # <u^2> = <U^2> + <u'^2> (cross term averages to zero in x), <sin^2> = <cos^2> = 1/2
+    ke = 0.5 * (A * A * half((1 - zs ** 2) ** 2) + 0.5 * half(sp.diff(f, zs) ** 2)
+                + 0.5 * kx * kx * half(f ** 2) + 0.5 * B * B * half((1 - zs ** 2) ** 2))
+    # grad phi = (-kx h sin, -ky h sin, z + h' cos): <|grad phi|^2>
+    grad2 = (0.5 * (kx * kx + ky * ky) * half(h ** 2) + half(zs ** 2) + 0.5 * half(sp.diff(h, zs) ** 2))
+    mean_phi = c0 + half(zs ** 2 / 2)
+    # CFL on the grid, from the closed-form fields
+    dzl = cs.local_spacing(p.nc)[:, None, None]
+    cfl = p.dt * np.max(np.abs(u) / (p.lx / p.nx) + np.abs(v) / (p.ly / p.ny) + np.abs(w) / dzl)
+    return (u, v, w, phi), dict(ke=ke, grad2=grad2, mean_phi=mean_phi, cfl=cfl)
+
+
+def test_diagnostics_closed_form_volume_averages():
+    """Pins the half-spectrum weights, the Chebyshev integrals (cheb_gram, cheb_integrals),
+    the 1/2 of the z-average, the local spacing of the CFL number and the continuity
+    check on fields whose averages sympy integrates exactly."""
+    p = _params(nx=12, ny=8, nc=16, lx=4 * math.pi, ly=2 * math.pi, dt=1e-3)
+    f, want = _diag_fields(p)
+    st = cs.init_state(*f, p)
+    d = cs.diagnostics(st, p)
+    for k in ("ke", "grad2", "mean_phi", "cfl"):
+        assert abs(d[k] - want[k]) <= 1e-13 * abs(want[k]), (k, d[k], want[k])
+    assert d["max_div"] < 1e-13 and d["nonfinite"] == 0
+
+
+def test_diagnostics_gram_matrix_and_nonfinite_count():
+    """cheb_gram against numpy's Chebyshev product and integral, and the non-finite count."""
+    from numpy.polynomial import chebyshev as npcheb
+    nc = 9
+    G = cs.cheb_gram(nc)
+    for m in range(nc + 1):
+        for n in range(nc + 1):
+            em = np.zeros(m + 1)
+            em[m] = 1.0
+            en = np.zeros(n + 1)
+            en[n] = 1.0
+            integ = npcheb.chebint(npcheb.chebmul(em, en), lbnd=-1)
+            assert abs(G[m, n] - npcheb.chebval(1.0, integ)) < 1e-14
+    p = _params(nc=8)
+    f, _ = _diag_fields(p)
+    st = cs.init_state(*f, p)
+    st["om"][3, 1, 1] = np.nan
+    st["mean"][0, 2] = np.inf
+    assert cs.diagnostics(st, p)["nonfinite"] == 2
