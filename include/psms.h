@@ -70,7 +70,7 @@ enum {
 /* Problem parameters (Sec. 2.1 dimensionless numbers and the time step). */
 typedef struct psms_params {
   int32_t geometry;  /* PSMS_BOX (PSMS_CHANNEL returns PSMS_E_NOTSUP) */
-  int32_t n;         /* grid points per axis: 8,12,16,24,32,48,64,96,128,192,256,384,512 */
+  int32_t n;         /* grid points per axis: 8,12,16,24,32,48,64,96,128,192,256 */
   int32_t precision; /* PSMS_FP64, or PSMS_MIXED: FP32 transforms and products,
                         FP64 state, RHS assembly, projection and update */
   int32_t reserved;  /* must be 0 */
@@ -172,7 +172,7 @@ int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms);
  * Data are nlines complex lines (one per Fourier pair (kx, ky)), stored
  * position-major: entry n of line l at [n][l] (nc+1 entries per line),
  * complex interleaved.  nc must make 2 nc a supported FFT length
- * (nc in {4,6,8,12,16,24,32,48,64,96,128}).  These calls are stateless:
+ * (nc in {4,6,8,12,16,24,32,48,64,96,128,256}).  These calls are stateless:
  * they run on `stream` (a hipStream_t, NULL for the default stream) and
  * allocate nothing.
  * ------------------------------------------------------------------------- */
@@ -191,9 +191,8 @@ int psms_cheb_transform(int32_t nc, int64_t nlines, int32_t dir, int32_t precisi
  * b_nc = 0 (c_0 = 2).  d_in and d_out must not overlap. */
 int psms_cheb_deriv(int32_t nc, int64_t nlines, const double* d_in, double* d_out, void* stream);
 
-/* The wall-normal Helmholtz problems of Sec. 2.2 ("a system of Helmholtz
- * problems along the wall-normal direction for each (x, y) location"):
- * (D^2 - beta_l) f = g on each line by the Chebyshev-tau method in FP64,
+/* The wall-normal Helmholtz problems of Sec. 2.2 (one independent 1-D problem
+ * per Fourier pair (kx, ky)): (D^2 - beta_l) f = g on each line by the Chebyshev-tau method in FP64,
  * rows n = 0..nc-2 of the equation (g entries n > nc-2 are ignored) and two
  * boundary rows: bc = PSMS_DIRICHLET: f(+1), f(-1); PSMS_NEUMANN: f'(+1),
  * f'(-1), given by d_bcval [nlines][2] complex (top, bottom), or zero if

@@ -12,7 +12,7 @@
 //    the integration recurrence turns each parity (even / odd n) into a
 //    tridiagonal system plus one boundary row; it is solved by one downward
 //    elimination sweep and two upward sweeps, one thread per (line, parity)
-//    (Sec. 3.2.2: "tridiagonal systems ... Gauss elimination along z").
+//    (the banded wall-normal solves of Sec. 3.2.2).
 //  * k_influence, k_uv: the influence-matrix combination that enforces
 //    w' = 0 at the walls, and u, v from continuity and eq. omegadef.
 #include <hip/hip_runtime.h>
@@ -662,7 +662,8 @@ hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long 
 
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
                              int lap, hipStream_t st) {
-  if (b.n < 1 || b.n > kChebBatchMax || nlines == 0) return hipSuccess;
+  if (b.n < 0 || b.n > kChebBatchMax || nlines < 0) return hipErrorInvalidValue;
+  if (b.n == 0 || nlines == 0) return hipSuccess;
   k_cheb_batch<<<dim3(blocks(2 * nlines, 64), unsigned(b.n)), 64, 0, st>>>(b, nc, nlines, kx, ky, lap);
   return hipGetLastError();
 }
@@ -682,13 +683,15 @@ hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc,
 }
 
 hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st) {
+  if (b.np < 0 || b.np > kHelmBatchMax) return hipErrorInvalidValue;
   long long most = 0;
   bool same_walls = true;
   for (int i = 0; i < b.np; ++i) {
+    if (b.p[i].nlines < 0) return hipErrorInvalidValue;
     most = most > b.p[i].nlines ? most : b.p[i].nlines;
     same_walls = same_walls && (b.p[i].bc == 0 || b.p[i].bc == 3);
   }
-  if (b.np < 1 || b.np > kHelmBatchMax || most == 0) return hipSuccess;
+  if (b.np == 0 || most == 0) return hipSuccess;
   if (same_walls) {
     const dim3 grid(blocks(most, 64), unsigned(b.np), 2);
     switch (nc) {

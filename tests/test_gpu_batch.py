@@ -93,3 +93,45 @@ def test_autotune_and_variants_do_not_change_results(tmp_path):
     # a second batch of the same shape reuses the cached choice
     b3 = Batch([c[0] for c in cases], precision="mixed")
     assert b3.autotune(reps=2, cache_path=str(tmp_path / "tune.json"))["source"] == "cache"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_64_96_groups_match_single_boxes_under_every_variant(precision):
+    """Groups of 64^3 and 96^3 boxes (most of the batched workload's points): the
+    default, autotuned and each forced workgroup-size variant give, after an AB1 step
+    and two graph replays, bitwise the single-box result of every box."""
+    from paper_2406_01322_amd.psms import Batch
+    cases = [c for c in synth.batch_cases(nbox=12, seed=4) if c[0]["n"] in (64, 96)][:4]
+    assert sorted(set(c[0]["n"] for c in cases)) == [64, 96]
+    refs = [_single(*c, 3, precision) for c in cases]
+    runs = {"default": None, "v0": [0] * 8, "v1": [1] * 8, "v2": [2] * 8, "tuned": "tune"}
+    for name, variants in runs.items():
+        b = Batch([c[0] for c in cases], precision=precision)
+        if variants == "tune":
+            b.autotune(reps=1, cache_path=None)
+        elif variants is not None:
+            b.set_variants(variants)
+        for i, (p, u, phi) in enumerate(cases):
+            b.init_state(i, torch.from_numpy(u), torch.from_numpy(phi))
+        b.step(1, use_graph=True)
+        b.step(2, use_graph=True)
+        for i in range(len(cases)):
+            got = b.get_state(i)
+            assert np.array_equal(got[0].cpu().numpy(), refs[i][0]), (name, i)
+            assert np.array_equal(got[1].cpu().numpy(), refs[i][1]), (name, i)
+        b.close()
+
+
+def test_batch_96_box_matches_oracle():
+    """A 96^3 box of a batch with a 64^3 box (FP64), two steps, against the oracle."""
+    cases = [c for c in synth.batch_cases(nbox=12, seed=4) if c[0]["n"] in (64, 96)]
+    cases = [next(c for c in cases if c[0]["n"] == 64), next(c for c in cases if c[0]["n"] == 96)]
+    b = _batch(cases, "fp64")
+    b.step(2)
+    for i, (p, u, phi) in enumerate(cases):
+        prm = obox.Params(**p)
+        ref = obox.run(obox.init_state(u, phi, prm), prm, 2)
+        uh, ph = b.get_state(i)
+        uh, ph = uh.cpu().numpy(), ph.cpu().numpy()
+        assert np.linalg.norm(uh - ref["uh"]) <= 1e-12 * np.linalg.norm(ref["uh"])
+        assert np.linalg.norm(ph - ref["ph"]) <= 1e-12 * np.linalg.norm(ref["ph"])

@@ -184,7 +184,7 @@ def _load(s, st):
     s.set_state(_dev(st["uh"]), _dev(st["ph"]), _dev(hist), st["nstep"])
 
 
-@pytest.mark.parametrize("case", ["single_drop_32", "drops4_48", "drops2_64"])
+@pytest.mark.parametrize("case", ["single_drop_32", "drops4_48", "drops2_64", "drops3_96"])
 @pytest.mark.parametrize("nprev", [0, 1])
 def test_one_step_parity_fp64(case, nprev):
     p, prm, st = _prepare(case, nprev)
@@ -203,9 +203,10 @@ def test_one_step_parity_fp64(case, nprev):
     assert ph[0, 0, 0] == st["ph"][0, 0, 0]
 
 
-@pytest.mark.parametrize("case", ["single_drop_32", "drops4_48", "drops2_64"])
-def test_one_step_parity_mixed(case):
-    p, prm, st = _prepare(case, 1)
+@pytest.mark.parametrize("case", ["single_drop_32", "drops4_48", "drops2_64", "drops3_96"])
+@pytest.mark.parametrize("nprev", [0, 1])
+def test_one_step_parity_mixed(case, nprev):
+    p, prm, st = _prepare(case, nprev)
     ref = box.step(st, prm)
     s = _solver(p, precision="mixed")
     _load(s, st)
@@ -288,6 +289,33 @@ def test_large_n_band_limited_steps_match_the_oracle_at_32(n, precision, tol):
         assert rel_l2(sp, wp) < tol, rel_l2(sp, wp)
         if i == 0:
             assert ru < tol * np.max(np.abs(wu)) and rp < tol * np.max(np.abs(wp))
+
+
+@pytest.fixture(scope="module")
+def drops256():
+    """The 256^3 two-drop case (full state, every mode of the band populated): the
+    oracle's state after init and one step, and its second (Adams-Bashforth 2) step."""
+    p, u, phi, prm = _oracle_state("drops2_256")
+    st = box.step(box.init_state(u, phi, prm), prm)
+    ref = box.step(st, prm)
+    return p, st, ref
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_full_state_256_one_step(drops256, precision, tol, record_error):
+    """N = 256 on a full state (the band edge K = 85, the radix-2 plans and the x
+    stage's direct-to-LDS staging on real data): one AB2 step against the oracle."""
+    p, st, ref = drops256
+    s = _solver(p, precision=precision)
+    _load(s, st)
+    s.step(1)
+    uh, ph, hist = (_host(t) for t in s.get_state(with_history=True))
+    for i in range(3):
+        assert record_error("u%d" % i, rel_l2(uh[i], ref["uh"][i]), tol) < tol, i
+        assert record_error("hS%d" % i, rel_l2(hist[i], ref["hS"][i]), tol) < tol, i
+    assert record_error("phi", rel_l2(ph, ref["ph"]), tol) < tol
+    assert record_error("hphi", rel_l2(hist[3], ref["hphi"]), tol) < tol
+    assert ph[0, 0, 0] == st["ph"][0, 0, 0]
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])

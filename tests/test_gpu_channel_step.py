@@ -1,13 +1,25 @@
 """GPU parity of the channel step (psms_channel_*) with the FP64 oracle
 (oracle/channel_step.py), through the C ABI.
 
-Per step from the same state: FP64 max error <= 1e-9 of each field's maximum
-(omega_z, w, phi, U, V: the wall-normal solves of the tau systems at
-beta = 2 Re / dt differ from the oracle's dense LU by rounding amplified by the
-conditioning, as in the wall-solve tests, and the explicit terms carry fourth
-Chebyshev derivatives); MIXED (FP32 transforms and products) rel-L2 <= 1e-5.
-The full channel workload (256 x 128 x 129) is checked on sampled (kx, ky) lines,
-whose wall-normal solves the oracle performs one by one, and on the mean flow.
+Bars, per step from the same state (FP64):
+* the state a step produces (omega_z, w, phi and the mean flow U, V): max error
+  <= 1e-12 of each field's maximum (measured: <= 8e-15 at every size here);
+* the history (the explicit right-hand sides H_omega, H_w, S_phi of the step): its
+  terms carry up to two Chebyshev derivatives of the FP64 products (H_w holds
+  D of the divergence of T, S_phi holds D^2 of phi^3), whose norms grow as nc^2,
+  so the rounding of the products reaches it amplified by nc^2:
+  4e-9 (nc / 256)^2 of the field's maximum (measured: 1.3e-9 at nc = 256,
+  2.6e-11 at nc = 128, 7e-13 at nc = 32);
+* MIXED (FP32 transforms and products): state rel-L2 <= 1e-5; its history is
+  checked against 1e-2 only: the rounding model of the FP64 history scaled from
+  FP64 to FP32 unit roundoff (x 2^29) allows far more, and the FP32 rounding of
+  products dominated by the mean flow (|U|^2 ~ 5.6e3 at Re_tau = 150) is not
+  removed by the derivatives that form H_omega and H_w: 1.7e-4 and 9.6e-4 measured
+  on the channel workload.
+The full channel workload (256 x 128 x 129) is checked on every (kx, ky) line and
+on the mean flow; the single-phase 256 x 256 x 257 grid on lines that use every
+kx and every ky index.  Multi-step runs (10 steps) are held to 1e-11: the
+trajectories stay close over so few steps (measured below 1e-13).
 """
 import numpy as np
 import pytest
@@ -51,6 +63,14 @@ def _rel_l2(a, b):
     return np.linalg.norm((a - b).ravel()) / s if s > 0 else np.linalg.norm(a.ravel())
 
 
+STATE_BAR = 1e-12
+
+
+def hist_bar(nc):
+    """Bar of the explicit right-hand sides: rounding amplified as nc^2 (module docstring)."""
+    return 4e-9 * (nc / 256.0) ** 2
+
+
 def _case(name):
     p, u, v, w, phi = synth.channel_case(name)
     return p, cs.ChannelParams(**{k: x for k, x in p.items() if k != "single_phase"}), (u, v, w, phi)
@@ -70,7 +90,7 @@ def test_channel_init_state_parity(name):
 
 @pytest.mark.parametrize("name", ["chan_small", "chan_mid"])
 @pytest.mark.parametrize("nprev", [0, 1])
-def test_channel_one_step_parity_fp64(name, nprev):
+def test_channel_one_step_parity_fp64(name, nprev, record_error):
     p, prm, f = _case(name)
     st = cs.run(cs.init_state(*f, prm), prm, nprev)
     ref = cs.step(st, prm)
@@ -78,12 +98,13 @@ def test_channel_one_step_parity_fp64(name, nprev):
     _load(c, st)
     c.step(1)
     state, mean, hist, hmean = (_host(t) for t in c.get_state(with_history=True))
+    hb = hist_bar(p["nc"])
     for i, k in enumerate(("om", "w", "phi")):
-        assert _rel_max(state[i], ref[k]) < 1e-9, (k, _rel_max(state[i], ref[k]))
+        assert record_error(k, _rel_max(state[i], ref[k]), STATE_BAR) < STATE_BAR, (k, _rel_max(state[i], ref[k]))
     for i, k in enumerate(("h_om", "h_w", "h_phi")):
-        assert _rel_max(hist[i], ref[k]) < 1e-9, (k, _rel_max(hist[i], ref[k]))
-    assert _rel_max(mean, ref["mean"]) < 1e-9
-    assert _rel_max(hmean, ref["h_mean"]) < 1e-9
+        assert record_error(k, _rel_max(hist[i], ref[k]), hb) < hb, (k, _rel_max(hist[i], ref[k]))
+    assert record_error("mean", _rel_max(mean, ref["mean"]), STATE_BAR) < STATE_BAR
+    assert record_error("h_mean", _rel_max(hmean, ref["h_mean"]), hb) < hb
 
 
 @pytest.mark.parametrize("name", ["chan_small", "chan_mid"])
@@ -100,7 +121,7 @@ def test_channel_one_step_parity_mixed(name):
     assert _rel_l2(mean, ref["mean"]) < 1e-5
 
 
-def test_channel_ten_steps_fp64():
+def test_channel_ten_steps_fp64(record_error):
     p, prm, f = _case("chan_small")
     ref = cs.run(cs.init_state(*f, prm), prm, 10)
     c = _gpu(p, "fp64")
@@ -108,32 +129,51 @@ def test_channel_ten_steps_fp64():
     c.step(10)
     state, mean = (_host(t) for t in c.get_state())
     for i, k in enumerate(("om", "w", "phi")):
-        assert _rel_max(state[i], ref[k]) < 1e-8, (k, _rel_max(state[i], ref[k]))
-    assert _rel_max(mean, ref["mean"]) < 1e-8
+        assert record_error(k, _rel_max(state[i], ref[k]), 1e-11) < 1e-11, (k, _rel_max(state[i], ref[k]))
+    assert record_error("mean", _rel_max(mean, ref["mean"]), 1e-11) < 1e-11
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
-def test_channel_workload_256_sampled_lines(precision, tol):
-    """256 x 128 x 129 (the channel workload), one step after one oracle step;
-    sampled lines (the mean line, low and band-edge wavenumbers) and the mean flow."""
+@pytest.fixture(scope="module")
+def chan256():
+    """256 x 128 x 129 (the channel workload): the oracle's state after one step from
+    the initial fields, and its second (Adams-Bashforth 2) step on every (kx, ky) line."""
     p, prm, f = _case("chan_256")
     st = cs.step(cs.init_state(*f, prm), prm)
-    lines = [(0, 0), (1, 0), (0, 1), (1, 1), (42, 85), (43, 85), (84, 3), (20, 40)]
-    ref = cs.step(st, prm, lines=lines)
+    ref = cs.step(st, prm)
+    return p, st, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_channel_workload_256_every_line(chan256, precision, record_error):
+    """256 x 128 x 129, one AB2 step from the oracle's state, all 7310 (kx, ky) lines and
+    the mean flow.  FP64: each field to the bars of the module docstring, and every line
+    also to its own scale (1e-9 of the line's largest coefficient, with a floor of 1e-14
+    of the field's largest line), so that an indexing error on a weak line shows."""
+    p, st, ref = chan256
     c = _gpu(p, precision)
     _load(c, st)
     c.step(1)
-    state, mean = (_host(t) for t in c.get_state())
+    state, mean, hist, hmean = (_host(t) for t in c.get_state(with_history=True))
+    hb = hist_bar(p["nc"])
     for i, k in enumerate(("om", "w", "phi")):
-        a = np.stack([state[i][:, iy, ix] for iy, ix in lines])
-        b = np.stack([ref[k][:, iy, ix] for iy, ix in lines])
-        if precision == "fp64":   # every sampled line to its own scale
-            for j, (iy, ix) in enumerate(lines):
-                scale = np.max(np.abs(b[j]))
-                assert np.max(np.abs(a[j] - b[j])) <= tol * scale or scale == 0.0, (k, iy, ix)
-        else:                     # FP32 transforms: errors scale with the field, not the line
-            assert _rel_l2(a, b) < tol, (k, _rel_l2(a, b))
-    assert _rel_max(mean, ref["mean"]) < tol
+        for got, want, name, bar in ((state[i], ref[k], k, STATE_BAR), (hist[i], ref["h_" + k], "h_" + k, hb)):
+            if precision == "fp64":
+                a = got.reshape(got.shape[0], -1)
+                b = want.reshape(want.shape[0], -1)
+                scale = np.max(np.abs(b), axis=0)
+                floor = 1e-14 * np.max(scale)
+                err = np.max(np.abs(a - b), axis=0)
+                ratio = err / (1e-9 * scale + floor)
+                record_error(name + " (per line / line bar)", np.max(ratio), 1.0)
+                assert record_error(name, _rel_max(got, want), bar) < bar, name
+                assert np.max(ratio) <= 1.0, (name, np.unravel_index(np.argmax(ratio), got.shape[1:]))
+            else:
+                bar = 1e-5 if name == k else 1e-2
+                e = _rel_l2(got, want)
+                assert record_error(name, e, bar) < bar, (name, e)
+    mbar, hmbar = (STATE_BAR, hb) if precision == "fp64" else (1e-5, 1e-2)
+    assert record_error("mean", _rel_max(mean, ref["mean"]), mbar) < mbar
+    assert record_error("h_mean", _rel_max(hmean, ref["h_mean"]), hmbar) < hmbar
 
 
 def test_channel_step_before_init_is_rejected():
@@ -168,11 +208,9 @@ def test_single_phase_equals_two_phase_with_zero_phi():
 
 
 @pytest.mark.parametrize("nprev", [0, 1])
-def test_single_phase_nc256_parity_fp64(nprev):
-    """16 x 12 x 257 (the 512-point Chebyshev extension), Re_tau 150, dt 1e-4.
-    The history holds H_w = lap_h S_z - D div_h S: the norm of D grows as nc^2, so the
-    rounding of the transformed products reaches it 4 times amplified from nc = 128,
-    where the bound is 1e-9: 4e-9 here."""
+def test_single_phase_nc256_parity_fp64(nprev, record_error):
+    """16 x 12 x 257 (the 512-point Chebyshev extension), Re_tau 150, dt 1e-4, against
+    the bars of the module docstring (the history's nc^2 bar is 4e-9 here)."""
     p, prm, f = _case("chan_sp_small")
     st = cs.run(cs.init_state(*f, prm), prm, nprev)
     ref = cs.step(st, prm)
@@ -180,13 +218,13 @@ def test_single_phase_nc256_parity_fp64(nprev):
     _load(c, st)
     c.step(1)
     state, mean, hist, hmean = (_host(t) for t in c.get_state(with_history=True))
-    tol = 1e-9 * (p["nc"] / 128) ** 2
+    hb = hist_bar(p["nc"])
     for i, k in enumerate(("om", "w")):
-        assert _rel_max(state[i], ref[k]) < tol, (k, _rel_max(state[i], ref[k]))
-        assert _rel_max(hist[i], ref["h_" + k]) < tol, (k, _rel_max(hist[i], ref["h_" + k]))
+        assert record_error(k, _rel_max(state[i], ref[k]), STATE_BAR) < STATE_BAR, (k, _rel_max(state[i], ref[k]))
+        assert record_error("h_" + k, _rel_max(hist[i], ref["h_" + k]), hb) < hb, k
     assert np.all(state[2] == 0.0)
-    assert _rel_max(mean, ref["mean"]) < tol
-    assert _rel_max(hmean, ref["h_mean"]) < tol
+    assert record_error("mean", _rel_max(mean, ref["mean"]), STATE_BAR) < STATE_BAR
+    assert record_error("h_mean", _rel_max(hmean, ref["h_mean"]), hb) < hb
 
 
 def test_single_phase_nc256_parity_mixed():
@@ -205,19 +243,24 @@ def test_single_phase_nc256_parity_mixed():
 @pytest.fixture(scope="module")
 def sp256():
     """256 x 256 x 257 single phase: the oracle's first (Adams-Bashforth 1) step from
-    the initial state, on sampled lines."""
+    the initial state, on 349 lines (two diagonals through the band, so that every kx
+    and every ky index is used, and the corners)."""
     p, prm, f = _case("chan_sp_256")
     st = cs.init_state(*f, prm)
-    lines = [(0, 0), (1, 0), (0, 1), (1, 1), (85, 85), (84, 85), (3, 84), (40, 20)]
+    cy, hx = cs.band_shape(prm)[1:]
+    # two diagonals through the band: every kx and every ky occurs on each
+    lines = sorted(set([(i % cy, i % hx) for i in range(cy)] + [(i % cy, (7 * i + 3) % hx) for i in range(cy)]
+                       + [(0, 0), (1, 0), (0, 1), (1, 1), (85, 85), (86, 85), (3, 84)]))
     ref = cs.step(st, prm, lines=lines)
     return p, f, lines, ref
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 4e-9), ("mixed", 1e-5)])
-def test_single_phase_256_sampled_lines(sp256, precision, tol):
-    """FP64: each sampled line to its own scale (the nc = 256 bound above); the
-    band-edge lines, which the first step from modes |k| <= 4 leaves at zero up to
-    rounding, to the rounding level of the field (1e-14 of its largest line)."""
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
+def test_single_phase_256_sampled_lines(sp256, precision, tol, record_error):
+    """FP64: the state on the sampled lines to 1e-12 of the field's largest sampled
+    line, and each line also to its own scale (1e-9); the band-edge lines, which the
+    first step from modes |k| <= 4 leaves at zero up to rounding, to the rounding level
+    of the field (1e-14 of its largest line)."""
     p, f, lines, ref = sp256
     c = _gpu(p, precision)
     c.init_state(*[_dev(x) for x in f[:3]])
@@ -228,12 +271,17 @@ def test_single_phase_256_sampled_lines(sp256, precision, tol):
         b = np.stack([ref[k][:, iy, ix] for iy, ix in lines])
         if precision == "fp64":
             floor = 1e-14 * np.max(np.abs(b))
+            worst = 0.0
             for j, (iy, ix) in enumerate(lines):
                 scale = np.max(np.abs(b[j]))
+                worst = max(worst, np.max(np.abs(a[j] - b[j])) / (tol * scale + floor))
                 assert np.max(np.abs(a[j] - b[j])) <= tol * scale + floor, (k, iy, ix)
+            record_error(k + " (per line / line bar)", worst, 1.0)
+            assert record_error(k, _rel_max(a, b), STATE_BAR) < STATE_BAR, k
         else:
-            assert _rel_l2(a, b) < tol, (k, _rel_l2(a, b))
-    assert _rel_max(mean, ref["mean"]) < tol
+            assert record_error(k, _rel_l2(a, b), tol) < tol, (k, _rel_l2(a, b))
+    mbar = STATE_BAR if precision == "fp64" else tol
+    assert record_error("mean", _rel_max(mean, ref["mean"]), mbar) < mbar
 
 
 # ---------------------------------------------------------------------------
@@ -247,7 +295,7 @@ WALLS = [("freeslip", "noslip"), ("noslip", "freeslip"), ("freeslip", "freeslip"
 
 @pytest.mark.parametrize("walls", WALLS)
 @pytest.mark.parametrize("nprev", [0, 1])
-def test_free_slip_walls_one_step_parity_fp64(walls, nprev):
+def test_free_slip_walls_one_step_parity_fp64(walls, nprev, record_error):
     import dataclasses
     p, prm, f = _case("chan_mid")
     prm = dataclasses.replace(prm, walls=walls)
@@ -258,9 +306,11 @@ def test_free_slip_walls_one_step_parity_fp64(walls, nprev):
     c.step(1)
     state, mean, hist, hmean = (_host(t) for t in c.get_state(with_history=True))
     for i, k in enumerate(("om", "w", "phi")):
-        assert _rel_max(state[i], ref[k]) < 1e-9, (k, _rel_max(state[i], ref[k]))
-    assert _rel_max(mean, ref["mean"]) < 1e-9
-    assert _rel_max(hmean, ref["h_mean"]) < 1e-9
+        assert record_error(k, _rel_max(state[i], ref[k]), STATE_BAR) < STATE_BAR, (k, _rel_max(state[i], ref[k]))
+    for i, k in enumerate(("h_om", "h_w", "h_phi")):
+        assert record_error(k, _rel_max(hist[i], ref[k]), hist_bar(p["nc"])) < hist_bar(p["nc"]), k
+    assert record_error("mean", _rel_max(mean, ref["mean"]), STATE_BAR) < STATE_BAR
+    assert record_error("h_mean", _rel_max(hmean, ref["h_mean"]), hist_bar(p["nc"])) < hist_bar(p["nc"])
 
 
 @pytest.mark.parametrize("walls", WALLS)
@@ -279,7 +329,7 @@ def test_free_slip_walls_one_step_parity_mixed(walls):
     assert _rel_l2(mean, ref["mean"]) < 1e-5
 
 
-def test_free_slip_ten_steps_fp64():
+def test_free_slip_ten_steps_fp64(record_error):
     import dataclasses
     p, prm, f = _case("chan_small")
     walls = ("freeslip", "noslip")
@@ -290,8 +340,8 @@ def test_free_slip_ten_steps_fp64():
     c.step(10)
     state, mean = (_host(t) for t in c.get_state())
     for i, k in enumerate(("om", "w", "phi")):
-        assert _rel_max(state[i], ref[k]) < 1e-8, (k, _rel_max(state[i], ref[k]))
-    assert _rel_max(mean, ref["mean"]) < 1e-8
+        assert record_error(k, _rel_max(state[i], ref[k]), 1e-11) < 1e-11, (k, _rel_max(state[i], ref[k]))
+    assert record_error("mean", _rel_max(mean, ref["mean"]), 1e-11) < 1e-11
 
 
 def test_bad_wall_flags_are_rejected():
@@ -317,6 +367,6 @@ def test_single_phase_open_channel_parity_fp64():
     c.step(1)
     state, mean = (_host(t) for t in c.get_state())
     for i, k in enumerate(("om", "w")):
-        assert _rel_max(state[i], ref[k]) < 1e-9, (k, _rel_max(state[i], ref[k]))
+        assert _rel_max(state[i], ref[k]) < STATE_BAR, (k, _rel_max(state[i], ref[k]))
     assert np.all(state[2] == 0.0)
-    assert _rel_max(mean, ref["mean"]) < 1e-9
+    assert _rel_max(mean, ref["mean"]) < STATE_BAR
