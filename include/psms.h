@@ -201,6 +201,20 @@ int psms_cheb_deriv(int32_t nc, int64_t nlines, const double* d_in, double* d_ou
 int psms_cheb_helmholtz(int32_t nc, int64_t nlines, const double* d_beta, int32_t bc, const double* d_bcval,
                         const double* d_rhs, double* d_out, double* d_work, void* stream);
 
+/* For callers that cannot allocate device memory or hand over a workspace
+ * (work recorded under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): psms_cheb_helmholtz without d_work.  The elimination
+ * scratch is a device array owned by the library, PSMS_NOALLOC_SCRATCH_DOUBLES
+ * doubles (8 MiB) on each GPU the call runs on, held until the process ends;
+ * (nc+1) * nlines larger than that returns PSMS_E_WORKSPACE.  Nothing is
+ * allocated and nothing needs clearing between calls.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other streams or
+ * threads) race: the caller must order them.  Other arguments, results and
+ * errors as psms_cheb_helmholtz. */
+#define PSMS_NOALLOC_SCRATCH_DOUBLES ((size_t)1 << 20)
+int psms_cheb_helmholtz_noalloc(int32_t nc, int64_t nlines, const double* d_beta, int32_t bc, const double* d_bcval,
+                                const double* d_rhs, double* d_out, void* stream);
+
 /* The implicit wall-normal solves of one channel time step for every
  * (kx, ky) line (Sec. 2.2, items iv and v; eqs. omegaz, ww, omegadef,
  * phisplit), k^2 = kx^2 + ky^2:

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -636,6 +637,64 @@ int psms_cheb_helmholtz(int32_t nc, int64_t nlines, const double* d_beta, int32_
                                    reinterpret_cast<const cpx<double>*>(d_bcval), cpx<double>{0.0, 0.0},
                                    cpx<double>{0.0, 0.0}, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "cheb_helmholtz");
+  return PSMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// psms_cheb_helmholtz_noalloc: the elimination scratch in a library-owned
+// device array instead of a caller workspace.  The array exists once per GPU
+// (each device holds its own copy at its own address); host code never passes
+// its name to a kernel, only the address hipGetSymbolAddress returns for the
+// device that is current.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) double scratch[PSMS_NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch`, looked up (once per
+// device, with that device current) on the first call.
+hipError_t device_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+int psms_cheb_helmholtz_noalloc(int32_t nc, int64_t nlines, const double* d_beta, int32_t bc, const double* d_bcval,
+                                const double* d_rhs, double* d_out, void* stream) {
+  if (nc < 4 || nlines < 0) return fail(PSMS_E_INVAL, "bad nc or nlines");
+  if (bc != PSMS_DIRICHLET && bc != PSMS_NEUMANN) return fail(PSMS_E_INVAL, "bc must be DIRICHLET or NEUMANN");
+  if (nlines == 0) return PSMS_OK;
+  if (!d_beta || !d_rhs || !d_out) return fail(PSMS_E_INVAL, "NULL argument");
+  if (d_rhs == d_out) return fail(PSMS_E_INVAL, "d_rhs and d_out must not overlap");
+  if (nlines > (long long)(PSMS_NOALLOC_SCRATCH_DOUBLES / size_t(nc + 1)))
+    return fail(PSMS_E_WORKSPACE, "(nc + 1) * nlines exceeds the " + std::to_string(PSMS_NOALLOC_SCRATCH_DOUBLES) +
+                                      " doubles of the library's scratch; use psms_cheb_helmholtz");
+  double* work = nullptr;
+  hipError_t e = device_scratch(&work);
+  if (e != hipSuccess) return hip_fail(e, "cheb_helmholtz_noalloc: scratch address");
+  // the same kernel as psms_cheb_helmholtz; the scratch needs no clearing (every
+  // entry a line reads was written earlier by the same thread)
+  e = psms::launch_helm(reinterpret_cast<const cpx<double>*>(d_rhs), reinterpret_cast<cpx<double>*>(d_out), work, nc,
+                        nlines, d_beta, 0.0, nullptr, nullptr, bc == PSMS_NEUMANN ? 1 : 0,
+                        reinterpret_cast<const cpx<double>*>(d_bcval), cpx<double>{0.0, 0.0}, cpx<double>{0.0, 0.0},
+                        static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "cheb_helmholtz_noalloc");
   return PSMS_OK;
 }
 

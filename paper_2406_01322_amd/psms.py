@@ -94,6 +94,9 @@ _SIGS = {
     "psms_cheb_helmholtz": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),
+    "psms_cheb_helmholtz_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p]),
     "psms_wall_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "psms_wall_solve": (ctypes.c_int, [ctypes.POINTER(WallArgs), ctypes.c_void_p, ctypes.c_size_t,
                                        ctypes.c_void_p]),
@@ -344,6 +347,29 @@ def cheb_helmholtz(g, beta, bc="dirichlet", bcval=None):
         bv = _ptr(bcval)
     kind = {"dirichlet": DIRICHLET, "neumann": NEUMANN}[bc]
     _check(lib().psms_cheb_helmholtz(nc, nl, _ptr(beta), kind, bv, _ptr(g), _ptr(out), _ptr(work), _stream()))
+    return out
+
+
+def cheb_helmholtz_noalloc(g, beta, bc="dirichlet", bcval=None, out=None):
+    """cheb_helmholtz with the library's own device scratch (no workspace): for
+    callers that cannot allocate.  `out` (same shape and dtype as g) may be given
+    so that the call itself allocates nothing."""
+    import torch
+    if g.dtype != torch.complex128 or beta.dtype != torch.float64:
+        raise ValueError("complex128 g and float64 beta required")
+    if not (g.is_contiguous() and beta.is_contiguous()):
+        raise ValueError("contiguous g and beta required")
+    nc = g.shape[0] - 1
+    nl = g.numel() // (nc + 1)
+    if out is None:
+        out = torch.empty_like(g)
+    bv = None
+    if bcval is not None:
+        if bcval.dtype != torch.complex128 or not bcval.is_contiguous():
+            raise ValueError("contiguous complex128 bcval required")
+        bv = _ptr(bcval)
+    kind = {"dirichlet": DIRICHLET, "neumann": NEUMANN}[bc]
+    _check(lib().psms_cheb_helmholtz_noalloc(nc, nl, _ptr(beta), kind, bv, _ptr(g), _ptr(out), _stream()))
     return out
 
 
