@@ -301,7 +301,8 @@ int psms_channel_workspace_bytes(const psms_channel_params* p, size_t* bytes);
 int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* d_workspace, size_t bytes,
                         void* stream);
 /* State from physical u, v, w, phi ([nc+1][ny][nx] each, on the collocation
- * grid); the next step is Adams-Bashforth 1.  Synchronises. */
+ * grid); the next step is Adams-Bashforth 1.  Synchronises; PSMS_E_NONFINITE if
+ * an input value is not finite. */
 int psms_channel_init_state(psms_channel* c, const double* d_u, const double* d_v, const double* d_w,
                             const double* d_phi);
 /* State, mean lines and (for nstep > 0) history in the layouts above (in
@@ -309,6 +310,17 @@ int psms_channel_init_state(psms_channel* c, const double* d_u, const double* d_
 int psms_channel_set_state(psms_channel* c, const double* d_state, const double* d_mean, const double* d_hist,
                            const double* d_hmean, int32_t nstep);
 int psms_channel_step(psms_channel* c, int32_t nsteps);
+/* Diagnostics of the channel state into *h_out (synchronises the stream),
+ * volume averages over [0, lx) x [0, ly) x [-1, 1] (eqs. cont and CHE):
+ * mean_phi = <phi>; ke = 1/2 <|u|^2>; grad2 = <|grad phi|^2> (Parseval in x and
+ * y, the exact Chebyshev integral in z); max_div = max |i kx u + i ky v + D w|
+ * over the band (continuity); nonfinite = number of non-finite entries of the
+ * state and mean lines; cfl = dt max (|u| / dx + |v| / dy + |w| / dz_j) over the
+ * collocation grid, dx = lx / nx, dy = ly / ny, dz_j the local spacing of the
+ * points ((z_{j-1} - z_{j+1}) / 2, one-sided at the walls).  Uses the step's
+ * scratch (the next step rebuilds it).  psms_channel_init_state runs it and
+ * returns PSMS_E_NONFINITE if an input value is not finite. */
+int psms_channel_diagnostics(psms_channel* c, psms_diag* h_out);
 /* d_hist and d_hmean may be NULL. */
 int psms_channel_get_state(psms_channel* c, double* d_state, double* d_mean, double* d_hist, double* d_hmean);
 int psms_channel_destroy(psms_channel* c);

@@ -1318,8 +1318,10 @@ struct ChanLayout {
   size_t kx, ky, twx64, twx32, twy64, twy32, twz64, twz32;
   size_t state, mean, hist, hmean;
   size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, lapc, lapphi, lapom, psi, lappsi, G;
-  size_t d2mean, gmean, wt, wb, M, psip, xi, xw, total;
+  size_t d2mean, gmean, wt, wb, M, psip, xi, xw, diag, total;
 };
+
+constexpr int kChanDiagBlocks = 1024;   // partial sums of the diagnostics
 
 psms::ChanGeom chan_geom(const psms_channel_params& p) {
   psms::ChanGeom g{};
@@ -1390,6 +1392,7 @@ ChanLayout chan_layout(const psms_channel_params& p) {
   take(L.psip, arr);
   take(L.xi, arr);
   take(L.xw, 4 * nz * size_t(g.NL) * sizeof(double));   // one elimination scratch per batched problem
+  take(L.diag, (8 * size_t(kChanDiagBlocks) + 8) * sizeof(double));
   L.total = off;
   return L;
 }
@@ -1754,6 +1757,65 @@ int psms_channel_init_state(psms_channel* c, const double* d_u, const double* d_
   if (e != hipSuccess) return hip_fail(e, "channel_init_state");
   c->nstep = 0;
   c->have_state = 1;
+  // a non-finite input value reaches every coefficient of its line through the
+  // transforms: the diagnostics' count finds it
+  psms_diag d;
+  const int r = psms_channel_diagnostics(c, &d);
+  if (r) return r;
+  if (d.nonfinite) {
+    c->have_state = 0;
+    return fail(PSMS_E_NONFINITE, "non-finite value in the initial fields");
+  }
+  return PSMS_OK;
+}
+
+int psms_channel_diagnostics(psms_channel* c, psms_diag* h_out) {
+  if (!c || !h_out) return fail(PSMS_E_INVAL, "NULL argument");
+  if (!c->have_state) return fail(PSMS_E_STATE, "channel_diagnostics before init_state / set_state");
+  const psms::ChanGeom& g = c->g;
+  const ChanLayout& L = c->lay;
+  hipStream_t st = c->stream;
+  auto C64 = [&](size_t off) { return c->at<cpx<double>>(off); };
+  cpx<double>* om = C64(L.state);
+  cpx<double>* w = om + g.NZL;
+  cpx<double>* phi = w + g.NZL;
+  const double* kx = c->at<double>(L.kx);
+  const double* ky = c->at<double>(L.ky);
+  double* part = c->at<double>(L.diag);
+  double* part2 = part + 4 * kChanDiagBlocks;
+  double* out = part2 + 4 * kChanDiagBlocks;
+  const int nb1 = int(std::min<long long>(kChanDiagBlocks, (g.NL + 255) / 256));
+  const int nb2 = int(std::min<long long>(kChanDiagBlocks, (g.P + 255) / 256));
+  // D w and D phi (the step's scratch: the next step recomputes them), the
+  // per-line sums, then u, v, w in FP64 on the collocation grid for the CFL
+  // number (through the step's transform buffers, which hold 4 FP64 fields in
+  // MIXED)
+  psms::ChebBatch cb{};
+  cb.n = g.sp ? 1 : 2;
+  cb.in[0] = w;
+  cb.out[0] = C64(L.dw);
+  cb.in[1] = phi;
+  cb.out[1] = C64(L.dphi);
+  hipError_t e = psms::launch_cheb_batch(cb, g.nc, g.NL, kx, ky, 0, st);
+  if (e == hipSuccess)
+    e = psms::launch_ch_diag_lines(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky, part, nb1, st);
+  if (e == hipSuccess)
+    e = psms::launch_ch_fields<double>(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky, C64(L.R), st);
+  if (e == hipSuccess) e = chan_inverse<double>(c, C64(L.R), c->at<double>(L.C), 3);
+  if (e == hipSuccess)
+    e = psms::launch_ch_cfl(g, c->at<double>(L.C), g.nx / c->p.lx, g.ny / c->p.ly, c->p.dt, part2, nb2, st);
+  if (e == hipSuccess) e = psms::launch_ch_diag_final(g, part, nb1, part2, nb2, phi, out, st);
+  double h[6];
+  if (e == hipSuccess) e = hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "channel_diagnostics");
+  h_out->mean_phi = h[0];
+  h_out->ke = h[1];
+  h_out->grad2 = h[2];
+  h_out->max_div = h[3];
+  h_out->nonfinite = int32_t(h[4]);
+  h_out->nstep = c->nstep;
+  h_out->cfl = h[5];
   return PSMS_OK;
 }
 

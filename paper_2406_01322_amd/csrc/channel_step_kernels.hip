@@ -174,7 +174,191 @@ __global__ void k_ch_mean_io(int nz, const cpx<double>* __restrict__ in, cpx<dou
   }
 }
 
+// ---------------------------------------------------------------------------
+// diagnostics: volume averages over the channel (x, y by Parseval with
+// half-spectrum weights, z exactly: int T_m T_n dz = (I(m+n) + I(|m-n|)) / 2,
+// I(k) = int T_k dz = 2 / (1 - k^2) for even k, 0 for odd k)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double cheb_int(int k) { return (k & 1) ? 0.0 : 2.0 / (1.0 - double(k) * double(k)); }
+
+// u, v of coefficient n on line l: continuity and eq. omegadef (the mean line: U, V)
+__device__ __forceinline__ void diag_uv(const ChanGeom& g, long long l, long long n, double kx, double ky,
+                                        const cpx<double>* om, const cpx<double>* dw, const cpx<double>* mean,
+                                        cpx<double>& u, cpx<double>& v) {
+  if (l == 0) {
+    u = mean[2 * n];
+    v = mean[2 * n + 1];
+    return;
+  }
+  const long long id = n * g.NL + l;
+  const double ik2 = 1.0 / (kx * kx + ky * ky);
+  const cpx<double> o = om[id], d = dw[id];
+  u = scl(ik2, ti(1.0, add(scl(kx, d), scl(ky, o))));
+  v = scl(ik2, ti(1.0, sub(scl(ky, d), scl(kx, o))));
+}
+
+__device__ __forceinline__ double rdot(cpx<double> a, cpx<double> b) { return a.re * b.re + a.im * b.im; }
+__device__ __forceinline__ bool bad(cpx<double> a) { return !isfinite(a.re) || !isfinite(a.im); }
+
+// One thread per (kx, ky) line; part[4 b + (0..3)] = block sums of the kinetic
+// energy and <|grad phi|^2>, the block max of |i kx u + i ky v + D w|, and the
+// number of non-finite state entries.
+__global__ void k_ch_diag_lines(ChanGeom g, const cpx<double>* __restrict__ om, const cpx<double>* __restrict__ w,
+                                const cpx<double>* __restrict__ phi, const cpx<double>* __restrict__ dw,
+                                const cpx<double>* __restrict__ dphi, const cpx<double>* __restrict__ mean,
+                                const double* __restrict__ kxl, const double* __restrict__ kyl,
+                                double* __restrict__ part) {
+  __shared__ double sh[4][kThreads];
+  double ke = 0.0, gr = 0.0, md = 0.0, nf = 0.0;
+  const int nc = g.nc;
+  PSMS_GRID_LOOP(l, g.NL) {
+    const double kx = kxl[l], ky = kyl[l];
+    // the quadratic forms sum_{m,n} G_mn Re(conj f_m f_n) of u, v, w, phi, D phi
+    double qu = 0.0, qv = 0.0, qw = 0.0, qp = 0.0, qd = 0.0;
+    for (int m = 0; m <= nc; ++m) {
+      const long long im = (long long)m * g.NL + l;
+      cpx<double> um, vm;
+      diag_uv(g, l, m, kx, ky, om, dw, mean, um, vm);
+      const cpx<double> wm = w[im], pm = g.sp ? cpx<double>{0.0, 0.0} : phi[im];
+      const cpx<double> dm = g.sp ? cpx<double>{0.0, 0.0} : dphi[im];
+      const double gmm = 0.5 * (cheb_int(2 * m) + 2.0);
+      qu += gmm * rdot(um, um);
+      qv += gmm * rdot(vm, vm);
+      qw += gmm * rdot(wm, wm);
+      qp += gmm * rdot(pm, pm);
+      qd += gmm * rdot(dm, dm);
+      for (int n = m & 1; n < m; n += 2) {   // pairs of one parity, each counted twice
+        const long long in = (long long)n * g.NL + l;
+        cpx<double> un, vn;
+        diag_uv(g, l, n, kx, ky, om, dw, mean, un, vn);
+        const double gmn = cheb_int(m + n) + cheb_int(m - n);   // 2 G_mn
+        qu += gmn * rdot(um, un);
+        qv += gmn * rdot(vm, vn);
+        qw += gmn * rdot(wm, w[in]);
+        if (!g.sp) {
+          qp += gmn * rdot(pm, phi[in]);
+          qd += gmn * rdot(dm, dphi[in]);
+        }
+      }
+      // continuity of coefficient m, and the non-finite entries of the state
+      const cpx<double> dv = add(add(ti(kx, um), ti(ky, vm)), dw[im]);
+      md = fmax(md, sqrt(dv.re * dv.re + dv.im * dv.im));
+      nf += (bad(om[im]) ? 1.0 : 0.0) + (bad(w[im]) ? 1.0 : 0.0) + ((!g.sp && bad(phi[im])) ? 1.0 : 0.0);
+      if (l == 0) nf += (bad(mean[2 * m]) ? 1.0 : 0.0) + (bad(mean[2 * m + 1]) ? 1.0 : 0.0);
+    }
+    const double wx = (kx == 0.0) ? 1.0 : 2.0;   // half spectrum: kx > 0 stands for +-kx
+    ke += 0.25 * wx * (qu + qv + qw);            // 1/2 <|u|^2>, <.> in z = (1/2) int dz
+    gr += 0.5 * wx * ((kx * kx + ky * ky) * qp + qd);
+  }
+  const int t = threadIdx.x;
+  sh[0][t] = ke; sh[1][t] = gr; sh[2][t] = md; sh[3][t] = nf;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sh[0][t] += sh[0][t + s];
+      sh[1][t] += sh[1][t + s];
+      sh[2][t] = fmax(sh[2][t], sh[2][t + s]);
+      sh[3][t] += sh[3][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = sh[k][0];
+  }
+}
+
+// Block maxima of dt (|u| / dx + |v| / dy + |w| / dz_j) over the collocation
+// grid (u, v, w physical FP64 [3][P]; dz_j the local spacing of the CGL points,
+// (z_{j-1} - z_{j+1}) / 2 inside, one-sided at the walls) into part[4 b + 2].
+__global__ void k_ch_cfl(ChanGeom g, const double* __restrict__ f, double inv_dx, double inv_dy, double dt,
+                         double* __restrict__ part) {
+  __shared__ double sh[kThreads];
+  double mx = 0.0;
+  const long long plane = (long long)g.ny * g.nx;
+  PSMS_GRID_LOOP(id, g.P) {
+    const int j = int(id / plane);
+    const double h = M_PI / double(g.nc);
+    double dz;
+    if (j == 0) dz = cos(0.0) - cos(h);
+    else if (j == g.nc) dz = cos(h * double(g.nc - 1)) - cos(h * double(g.nc));
+    else dz = 0.5 * (cos(h * double(j - 1)) - cos(h * double(j + 1)));
+    const double s = fabs(f[id]) * inv_dx + fabs(f[g.P + id]) * inv_dy + fabs(f[2 * g.P + id]) / dz;
+    mx = fmax(mx, dt * s);
+  }
+  const int t = threadIdx.x;
+  sh[t] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) part[4 * blockIdx.x + 2] = sh[0];
+}
+
+// out[0..5] = mean phi, ke, grad2, max div, non-finite count, CFL from the
+// partials of k_ch_diag_lines (nb1 blocks, part) and k_ch_cfl (nb2 blocks, part2)
+__global__ void k_ch_diag_final(ChanGeom g, const double* __restrict__ part, int nb1, const double* __restrict__ part2,
+                                int nb2, const cpx<double>* __restrict__ phi, double* __restrict__ out) {
+  __shared__ double sh[5][kThreads];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0, e = 0.0;
+  for (int i = t; i < nb1; i += blockDim.x) {
+    a += part[4 * i];
+    b += part[4 * i + 1];
+    c = fmax(c, part[4 * i + 2]);
+    d += part[4 * i + 3];
+  }
+  for (int i = t; i < nb2; i += blockDim.x) e = fmax(e, part2[4 * i + 2]);
+  sh[0][t] = a; sh[1][t] = b; sh[2][t] = c; sh[3][t] = d; sh[4][t] = e;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sh[0][t] += sh[0][t + s];
+      sh[1][t] += sh[1][t + s];
+      sh[2][t] = fmax(sh[2][t], sh[2][t + s]);
+      sh[3][t] += sh[3][t + s];
+      sh[4][t] = fmax(sh[4][t], sh[4][t + s]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double mp = 0.0;   // <phi> = (1/2) int phi_00 dz, the mean line (l = 0)
+    if (!g.sp)
+      for (int n = 0; n <= g.nc; n += 2) mp += 0.5 * cheb_int(n) * phi[(long long)n * g.NL].re;
+    out[0] = mp;
+    out[1] = sh[0][0];
+    out[2] = sh[1][0];
+    out[3] = sh[2][0];
+    out[4] = sh[3][0];
+    out[5] = sh[4][0];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_ch_diag_lines(const ChanGeom& g, const cpx<double>* om, const cpx<double>* w, const cpx<double>* phi,
+                                const cpx<double>* dw, const cpx<double>* dphi, const cpx<double>* mean,
+                                const double* kx, const double* ky, double* part, int max_blocks, hipStream_t st) {
+  long long b = (g.NL + kThreads - 1) / kThreads;
+  if (b > max_blocks) b = max_blocks;
+  k_ch_diag_lines<<<unsigned(b < 1 ? 1 : b), kThreads, 0, st>>>(g, om, w, phi, dw, dphi, mean, kx, ky, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_ch_cfl(const ChanGeom& g, const double* f, double inv_dx, double inv_dy, double dt, double* part,
+                         int max_blocks, hipStream_t st) {
+  long long b = (g.P + kThreads - 1) / kThreads;
+  if (b > max_blocks) b = max_blocks;
+  k_ch_cfl<<<unsigned(b < 1 ? 1 : b), kThreads, 0, st>>>(g, f, inv_dx, inv_dy, dt, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_ch_diag_final(const ChanGeom& g, const double* part, int nb1, const double* part2, int nb2,
+                                const cpx<double>* phi, double* out, hipStream_t st) {
+  k_ch_diag_final<<<1, kThreads, 0, st>>>(g, part, nb1, part2, nb2, phi, out);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_ch_fields(const ChanGeom& g, const cpx<double>* om, const cpx<double>* w, const cpx<double>* phi,

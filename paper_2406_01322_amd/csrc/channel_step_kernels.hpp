@@ -70,6 +70,18 @@ hipError_t launch_ch_assemble(const ChanGeom& g, const ChanCoef& c, const ChanAs
 // 3 in single phase, phi set to zero)
 hipError_t launch_ch_init(const ChanGeom& g, const cpx<double>* U4, const double* kx, const double* ky,
                           cpx<double>* om, cpx<double>* w, cpx<double>* phi, cpx<double>* mean, hipStream_t st);
+// diagnostics of the state (volume averages; eqs. cont and CHE): per-line partial
+// sums (at most max_blocks blocks of 256 lines' worth of work, part[4 * block]),
+// the CFL maxima of physical FP64 u, v, w [3][P] (part[4 * block + 2]), and the
+// final reduction out[0..5] = mean phi, kinetic energy, <|grad phi|^2>,
+// max |i kx u + i ky v + D w|, non-finite entries, CFL
+hipError_t launch_ch_diag_lines(const ChanGeom& g, const cpx<double>* om, const cpx<double>* w, const cpx<double>* phi,
+                                const cpx<double>* dw, const cpx<double>* dphi, const cpx<double>* mean,
+                                const double* kx, const double* ky, double* part, int max_blocks, hipStream_t st);
+hipError_t launch_ch_cfl(const ChanGeom& g, const double* f, double inv_dx, double inv_dy, double dt, double* part,
+                         int max_blocks, hipStream_t st);
+hipError_t launch_ch_diag_final(const ChanGeom& g, const double* part, int nb1, const double* part2, int nb2,
+                                const cpx<double>* phi, double* out, hipStream_t st);
 // mean lines: [2][nc+1] (caller) <-> [nc+1][2] (internal); dir > 0 copies into internal
 hipError_t launch_ch_mean_io(const ChanGeom& g, const cpx<double>* in, cpx<double>* out, int dir, hipStream_t st);
 

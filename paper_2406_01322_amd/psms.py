@@ -71,6 +71,7 @@ _SIGS = {
     "psms_channel_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "psms_channel_get_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
     "psms_channel_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "psms_channel_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diag)]),
     "psms_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
     "psms_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Params), ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p]),
@@ -678,3 +679,9 @@ class Channel:
         _check(lib().psms_channel_get_state(self.h, _ptr(st), _ptr(mn), _ptr(hs) if hs is not None else None,
                                             _ptr(hm) if hm is not None else None))
         return (st, mn, hs, hm) if with_history else (st, mn)
+
+    def diagnostics(self):
+        d = Diag()
+        _check(lib().psms_channel_diagnostics(self.h, ctypes.byref(d)))
+        return dict(mean_phi=d.mean_phi, ke=d.ke, grad2=d.grad2, max_div=d.max_div,
+                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl)
