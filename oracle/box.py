@@ -139,6 +139,8 @@ class Params:
     pe: float
     dt: float
     s: float | None = None
+    cube: str = "grid"   # phi^3: "grid" = pointwise cube on the N grid, then truncated;
+                         # "exact" = the truncation of the exact cube (cube_exact)
 
     def split_s(self) -> float:
         if self.s is not None and self.s > 0.0:
@@ -218,11 +220,53 @@ def nonlinear_terms(uh: np.ndarray, ph: np.ndarray, prm: Params):
     S[:, 0, 0, 0] = 0.0
 
     adv = fwd(u[0] * g[0] + u[1] * g[1] + u[2] * g[2]) * D      # u.grad(phi)
-    cube = fwd(phi * phi * phi) * D                              # phi^3
+    if prm.cube == "exact":
+        cube = cube_exact(ph, n)                                 # phi^3 without aliasing
+    else:
+        cube = fwd(phi * phi * phi) * D                          # phi^3 on the N grid
     Sphi = -adv - (k2 / prm.pe) * cube + ((1.0 + s * prm.ch ** 2) / prm.pe) * k2 * ph
     Sphi0 = complex(Sphi[0, 0, 0])
     Sphi[0, 0, 0] = 0.0
     return S, Sphi, Sphi0
+
+
+def cube_exact(ph: np.ndarray, n: int, m: int | None = None) -> np.ndarray:
+    """The retained band of the exact cube of the band-limited phi (chemical
+    potential mu = phi^3 - phi - Ch^2 lap phi, Sec. 2.1.1): phi is evaluated on
+    an m^3 grid (default 2n), cubed there and transformed back, and the modes
+    |k_i| <= K of the n grid kept.  The cube of modes |k| <= K reaches 3K; on
+    the m grid its aliases land at |k| >= m - 3K > K once m > 4K, so the kept
+    modes are those of the exact product (for any such m)."""
+    K = cutoff(n)
+    m = 2 * n if m is None else m
+    if m <= 4 * K:
+        raise ValueError("m must exceed 4K")
+    kz, ky, _ = wavenumbers(n)
+    kzm, kym, _ = wavenumbers(m)
+    band = np.abs(kz) <= K
+    pos_n = np.nonzero(band)[0]                      # rows / planes of the band on the n grid
+    pos_m = np.array([np.nonzero(kzm == kz[p])[0][0] for p in pos_n])   # the same k on the m grid
+    big = np.zeros((m, m, m // 2 + 1), dtype=complex)
+    big[np.ix_(pos_m, pos_m, np.arange(K + 1))] = ph[np.ix_(pos_n, pos_n, np.arange(K + 1))]
+    f = inv(big, m)
+    cm = fwd(f * f * f)
+    out = np.zeros_like(ph)
+    out[np.ix_(pos_n, pos_n, np.arange(K + 1))] = cm[np.ix_(pos_m, pos_m, np.arange(K + 1))]
+    return out
+
+
+def pressure(state: dict, prm: Params) -> np.ndarray:
+    """The pressure that the projection removes (eq. cont): lap p = div S, i.e.
+    p_hat = -i k.S_hat / k^2 with S the unprojected nonlinear term of the state
+    (convective and Korteweg parts, ``nonlinear_terms``); p_hat(0) = 0."""
+    n = prm.n
+    S, _, _ = nonlinear_terms(state["uh"], state["ph"], prm)
+    KX, KY, KZ = kgrid(n)
+    k2 = KX * KX + KY * KY + KZ * KZ
+    k2[0, 0, 0] = 1.0
+    p = -1j * (KX * S[0] + KY * S[1] + KZ * S[2]) / k2
+    p[0, 0, 0] = 0.0
+    return p
 
 
 def step(state: dict, prm: Params) -> dict:

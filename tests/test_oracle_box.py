@@ -214,19 +214,14 @@ def test_planar_interface_is_ch_equilibrium():
 def test_laplace_pressure_jump_of_spherical_drop():
     """The Korteweg force with coefficient 3/sqrt(8) Ch/We gives surface tension 1/We:
     a resting spherical drop has the Laplace jump p_in - p_out = 2 sigma / R = 2 / (We R).
-    The pressure solves lap p = div S with S the oracle's nonlinear term at u = 0."""
+    The pressure (box.pressure) solves lap p = div S with S the oracle's nonlinear term at u = 0."""
     n = 64
     ch, we, R = 0.12, 2.0, 1.5
     prm = box.Params(n=n, re=100.0, we=we, ch=ch, pe=10.0, dt=1e-3)
     c = np.array([[np.pi, np.pi, np.pi]])
     phi = synth.drops_phi(n, c, R, ch)
     st = box.init_state(np.zeros((3, n, n, n)), phi, prm)
-    S, _, _ = box.nonlinear_terms(st["uh"], st["ph"], prm)
-    KX, KY, KZ = box.kgrid(n)
-    k2 = KX ** 2 + KY ** 2 + KZ ** 2
-    k2[0, 0, 0] = 1.0
-    divS = 1j * (KX * S[0] + KY * S[1] + KZ * S[2])
-    p = box.inv(-divS / k2, n)
+    p = box.inv(box.pressure(st, prm), n)
     jump = p[n // 2, n // 2, n // 2] - p[0, 0, 0]
     assert abs(jump - 2.0 / (we * R)) < 0.01 * 2.0 / (we * R)
 
@@ -453,3 +448,84 @@ def test_diagnostics_pin_catches_planted_mistakes(monkeypatch, plant):
     if plant == "no_half":
         eke = abs(2.0 * d["ke"] - _trig_state()[1]) / _trig_state()[1]
     assert max(eke, eg2) > 1e-3
+
+
+# ---------------------------------------------------------------- exact dealiasing of phi^3, pressure
+
+def _band_limited_phi(n, seed):
+    rng = np.random.default_rng(seed)
+    return box.fwd(rng.standard_normal((n, n, n))) * box.dealias_mask(n)
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_exact_cube_equals_brute_force_triple_convolution(n):
+    """(phi^3)_k = sum_{p + q + r = k} phi_p phi_q phi_r over the band (full spectrum,
+    phi_{-k} = conj phi_k), kept for |k_i| <= K: no product of the grid involved."""
+    K = box.cutoff(n)
+    ph = _band_limited_phi(n, n)
+    ks = range(-K, K + 1)
+    full = {}
+    for a in ks:
+        for b in ks:
+            for c in ks:
+                if c >= 0:
+                    full[(a, b, c)] = ph[a % n, b % n, c]
+                else:
+                    full[(a, b, c)] = np.conj(ph[(-a) % n, (-b) % n, -c])
+    kk = np.array(list(full))                        # every band wavevector (kz, ky, kx)
+    vals = np.array([full[tuple(k)] for k in kk])
+    qr = (kk[:, None, :] + kk[None, :, :]).reshape(-1, 3)          # q + r over all pairs
+    vqr = (vals[:, None] * vals[None, :]).reshape(-1)
+    want = np.zeros_like(ph)
+    for p, vp in zip(kk, vals):
+        k = qr + p                                   # p + q + r
+        ok = np.all(np.abs(k) <= K, axis=1) & (k[:, 2] >= 0)
+        np.add.at(want, (k[ok, 0] % n, k[ok, 1] % n, k[ok, 2]), vp * vqr[ok])
+    got = box.cube_exact(ph, n)
+    assert np.max(np.abs(got - want)) < 1e-13 * np.max(np.abs(want))
+
+
+def test_exact_cube_removes_the_alias_of_cos_2x_at_n8():
+    """phi = cos 2x on N = 8 (K = 2): phi^3 = (3/4) cos 2x + (1/4) cos 6x.  The pointwise
+    cube on the grid folds cos 6x onto cos 2x (coefficient 1/2); the exact one keeps 3/8."""
+    n = 8
+    X, Y, Z = _grid(n)
+    ph = box.fwd(np.cos(2 * X)) * box.dealias_mask(n)
+    exact = box.cube_exact(ph, n)
+    grid = box.fwd(np.cos(2 * X) ** 3) * box.dealias_mask(n)
+    assert abs(exact[0, 0, 2] - 3.0 / 8.0) < 1e-15 and abs(grid[0, 0, 2] - 0.5) < 1e-15
+    exact[0, 0, 2] = 0.0
+    assert np.max(np.abs(exact)) < 1e-15
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_exact_cube_does_not_depend_on_the_padded_grid(n):
+    K = box.cutoff(n)
+    ph = _band_limited_phi(n, 3 * n)
+    a = box.cube_exact(ph, n, m=2 * n)
+    for m in (4 * K + 1, 4 * K + 2, 3 * n):
+        assert np.max(np.abs(box.cube_exact(ph, n, m=m) - a)) < 1e-14 * np.max(np.abs(a))
+    with pytest.raises(ValueError):
+        box.cube_exact(ph, n, m=4 * K)
+
+
+def test_exact_cube_step_keeps_mean_phi_and_differs_from_the_grid_cube():
+    p, u, phi = synth.box_case("single_drop_32")
+    prm = box.Params(**p, cube="exact")
+    st = box.step(box.init_state(u, phi, prm), prm)
+    ref = box.step(box.init_state(u, phi, box.Params(**p)), box.Params(**p))
+    assert st["ph"][0, 0, 0] == ref["ph"][0, 0, 0]
+    d = np.linalg.norm(st["ph"] - ref["ph"]) / np.linalg.norm(ref["ph"])
+    assert 1e-12 < d < 1e-2
+
+
+def test_pressure_of_the_taylor_green_vortex():
+    """u = (sin x cos y, -cos x sin y, 0) with phi = -1 (no capillary force): -u.grad u =
+    grad p with p = (cos 2x + cos 2y) / 4, so the pressure is that field exactly."""
+    n = 16
+    X, Y, Z = _grid(n)
+    u = np.stack([np.sin(X) * np.cos(Y), -np.cos(X) * np.sin(Y), 0 * X])
+    prm = box.Params(n=n, re=100.0, we=1.0, ch=0.1, pe=10.0, dt=1e-3)
+    st = box.init_state(u, -np.ones((n, n, n)), prm)
+    p = box.inv(box.pressure(st, prm), n)
+    assert np.max(np.abs(p - 0.25 * (np.cos(2 * X) + np.cos(2 * Y)))) < 1e-14
