@@ -271,17 +271,20 @@ def bench_channel(steps=20, warmup=2, case="chan_256"):
     out = {"grid": [p["nx"], p["ny"], p["nc"] + 1], "points": npts, "steps": steps, "single_phase": sp}
     f = [torch.from_numpy(x).cuda() for x in ((u, v, w) if sp else (u, v, w, phi))]
     del u, v, w, phi
+    stream = torch.cuda.Stream()       # a capturable stream: steps after the first replay a hipGraph
+    torch.cuda.synchronize()
     for prec in ("mixed", "fp64"):
-        c = psms.Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=prec,
-                         lx=p["lx"], ly=p["ly"], single_phase=sp)
-        c.init_state(*f)
-        c.step(warmup)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        c.step(steps)
-        e1.record()
-        e1.synchronize()
+        with torch.cuda.stream(stream):
+            c = psms.Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=prec,
+                             lx=p["lx"], ly=p["ly"], single_phase=sp, stream=stream)
+            c.init_state(*f)
+            c.step(warmup)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            c.step(steps)
+            e1.record(stream)
+            e1.synchronize()
         ms = e0.elapsed_time(e1) / steps
         out[prec] = {"ms_per_step": ms, "value": npts / (ms * 1e-3)}
         c.close()

@@ -73,7 +73,11 @@ typedef struct psms_params {
   int32_t n;         /* grid points per axis: 8,12,16,24,32,48,64,96,128,192,256 */
   int32_t precision; /* PSMS_FP64, or PSMS_MIXED: FP32 transforms and products,
                         FP64 state, RHS assembly, projection and update */
-  int32_t reserved;  /* must be 0 */
+  int32_t cube;      /* phi^3 in the chemical potential (Sec. 2.1.1): 0 = the pointwise
+                        cube on the n grid, then truncated to the 2/3 band (it aliases:
+                        a cube is not dealiased by the 2/3 rule); 1 = the band of the
+                        exact cube, formed on a padded grid m > 4K (the smallest
+                        supported size; n <= 192; not for batches or the adjoint) */
   double re;         /* Reynolds number Re (eq. Re) > 0 */
   double we;         /* Weber number We (eq. We) > 0 */
   double ch;         /* Cahn number Ch > 0 */
@@ -150,6 +154,16 @@ int psms_solve_helmholtz(psms_ctx* c, int32_t nfield, const double* h_lambda, co
 
 /* Diagnostics of the current state into *h_out (synchronises the stream). */
 int psms_diagnostics(psms_ctx* c, psms_diag* h_out);
+
+/* The pressure of the current state (eq. cont): the field that the projection
+ * of Sec. 2.2 removes from the nonlinear term S = div T of eqs. NSE and kort,
+ * lap p = div S, i.e. p_hat = k_i k_j T_ij_hat / k^2 with p_hat(0) = 0, into
+ * d_p [n][n][n/2+1] complex double (zero outside the band).  Products and
+ * transforms in the context's precision, the division in FP64.  Asynchronous;
+ * uses the step's scratch (the next step rebuilds its input).  For a resting
+ * drop of radius R the jump between inside and outside is the Laplace
+ * pressure 2 / (We R) (surface tension 1/We of the Korteweg force). */
+int psms_pressure(psms_ctx* c, double* d_p);
 
 /* The device-side index maps of the retained band, as the kernels use them:
  * for each band mode m (ordered [kz slot][ky slot][kx]), d_out[4m..4m+3] =
@@ -309,7 +323,12 @@ int psms_channel_init_state(psms_channel* c, const double* d_u, const double* d_
  * single phase the phi parts are ignored and set to zero). */
 int psms_channel_set_state(psms_channel* c, const double* d_state, const double* d_mean, const double* d_hist,
                            const double* d_hmean, int32_t nstep);
+/* Advance nsteps steps (asynchronous).  On a non-NULL stream every step after
+ * the first (Adams-Bashforth 1) one replays a captured hipGraph of the step's
+ * launches. */
 int psms_channel_step(psms_channel* c, int32_t nsteps);
+/* Enable (default) or disable the graph replay of psms_channel_step. */
+int psms_channel_set_graphs(psms_channel* c, int32_t enable);
 /* Diagnostics of the channel state into *h_out (synchronises the stream),
  * volume averages over [0, lx) x [0, ly) x [-1, 1] (eqs. cont and CHE):
  * mean_phi = <phi>; ke = 1/2 <|u|^2>; grad2 = <|grad phi|^2> (Parseval in x and

@@ -37,6 +37,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
   size_t state, hist, bufa, bufb, tw64, tw32, diag, diag_out, box, phys, acc, total;
   size_t bufa_bytes, bufb_bytes;
+  // exact cube of phi (cube = 1): the padded grid m, two spectral buffers of
+  // [m][m][K+1], the m^3 physical field, the m-point twiddles
+  int m;
+  size_t pad_s1, pad_s2, pad_phys, pad_tw64, pad_tw32;
 };
 
 constexpr int kDiagBlocks = 1024;
@@ -50,6 +54,17 @@ BoxGeom make_geom(int n) {
   g.Q = (long long)g.C * g.H;
   g.M = g.Q * g.C;
   return g;
+}
+
+// Smallest supported grid m > 4K: the cube of modes |k| <= K reaches 3K, and
+// on an m grid its aliases miss the band |k| <= K exactly when m > 4K.  0 if
+// none is supported.
+int pad_size(int n) {
+  const int K = (n - 1) / 3;
+  const int sizes[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+  for (int m : sizes)
+    if (m > 4 * K) return m;
+  return 0;
 }
 
 Layout make_layout(const psms_params& p) {
@@ -74,6 +89,16 @@ Layout make_layout(const psms_params& p) {
   L.box = off; off = align256(off + sizeof(psms::BoxDev));
   L.phys = off; off = align256(off + n * n * n * sizeof(double));   // CFL: one physical component
   L.acc = off; off = align256(off + n * n * n * sizeof(double));    // CFL: sum_i |u_i| / dx
+  L.m = 0;
+  if (p.cube == 1) {
+    const size_t m = size_t(pad_size(p.n));
+    L.m = int(m);
+    L.pad_s1 = off; off = align256(off + m * m * size_t(g.H) * tp);
+    L.pad_s2 = off; off = align256(off + m * m * size_t(g.H) * tp);
+    L.pad_phys = off; off = align256(off + m * m * m * tp / 2);
+    L.pad_tw64 = off; off = align256(off + m * sizeof(cpx<double>));
+    L.pad_tw32 = off; off = align256(off + m * sizeof(cpx<float>));
+  }
   L.total = off;
   return L;
 }
@@ -85,7 +110,9 @@ int validate(const psms_params* p) {
   if (!psms::supported_n(p->n))
     return fail(PSMS_E_INVAL, "n must be one of 8,12,16,24,32,48,64,96,128,192,256");
   if (p->precision != PSMS_FP64 && p->precision != PSMS_MIXED) return fail(PSMS_E_INVAL, "precision must be FP64 or MIXED");
-  if (p->reserved != 0) return fail(PSMS_E_INVAL, "reserved must be 0");
+  if (p->cube != 0 && p->cube != 1) return fail(PSMS_E_INVAL, "cube must be 0 (grid) or 1 (exact)");
+  if (p->cube == 1 && pad_size(p->n) == 0)
+    return fail(PSMS_E_NOTSUP, "the exact cube needs a supported grid larger than 4K (n <= 192)");
   const double v[5] = {p->re, p->we, p->ch, p->pe, p->dt};
   const char* nm[5] = {"re", "we", "ch", "pe", "dt"};
   for (int i = 0; i < 5; ++i)
@@ -111,6 +138,7 @@ struct psms_ctx {
   cpx<float>* tw32;
   double* diag;
   double* diag_out;
+  int m;                 // padded grid of the exact cube (0: the grid cube)
   psms::BoxDev* d_box;   // one-entry device descriptor table
   psms::BoxDev h_box;    // its host copy
   int box_ab1;           // ab1 value last written to d_box (-1: never)
@@ -164,6 +192,77 @@ hipError_t prologue(psms_ctx* c) {
   return psms::launch_step_stage<T>(c->g.n, 3, c->variant[3], c->d_box, 0, 1, twiddles<T>(c), 0, c->stream);
 }
 
+// The exact cube of phi (cube = 1), replacing the grid cube among the y-forward
+// products: phi's band on the padded m^3 grid (z, y inverse from the band, x
+// rows), cubed there, back to the band (x rows to K+1 entries, y and z to the
+// 2K+1 band slots, 1/m^3), then z-inverse on the n grid times n^2 into product
+// field 7 of the y-forward output, where the z stage's forward transform (with
+// its 1/n^3) recovers the band.  Every buffer is written before it is read.
+template <typename T>
+hipError_t exact_cube(psms_ctx* c) {
+  const BoxGeom& g = c->g;
+  const int n = g.n, m = c->m;
+  hipStream_t st = c->stream;
+  const Layout& L = c->lay;
+  cpx<T>* S1 = reinterpret_cast<cpx<T>*>(c->ws + L.pad_s1);
+  cpx<T>* S2 = reinterpret_cast<cpx<T>*>(c->ws + L.pad_s2);
+  T* Pm = reinterpret_cast<T*>(c->ws + L.pad_phys);
+  const cpx<T>* twm = reinterpret_cast<const cpx<T>*>(c->ws + (std::is_same<T, double>::value ? L.pad_tw64
+                                                                                             : L.pad_tw32));
+  const cpx<double>* phi = c->state + 3 * g.M;
+  const cpx<T>* band;
+  hipError_t e = hipSuccess;
+  if (std::is_same<T, double>::value) {
+    band = reinterpret_cast<const cpx<T>*>(phi);
+  } else {
+    e = psms::launch_band_to<T>(phi, S2, g.M, st);
+    band = S2;
+  }
+  psms::LineArgs lz{};
+  lz.n_in = g.C;
+  lz.n_out = m;
+  lz.inner = g.Q;
+  lz.nlines = g.Q;
+  lz.fmap = 0;
+  lz.scale = 1.0;
+  if (e == hipSuccess) e = psms::launch_lines<T>(m, +1, band, S1, twm, lz, 1, st);   // [m][C][H]
+  psms::LineArgs ly{};
+  ly.n_in = g.C;
+  ly.n_out = m;
+  ly.inner = g.H;
+  ly.nlines = (long long)m * g.H;
+  ly.fmap = 0;
+  ly.scale = 1.0;
+  if (e == hipSuccess) e = psms::launch_lines<T>(m, +1, S1, S2, twm, ly, 1, st);     // [m][m][H]
+  psms::RowArgs ra{};
+  ra.nrows = (long long)m * m;
+  ra.n_in = g.H;
+  ra.n_out = m;
+  ra.scale = 1.0;
+  if (e == hipSuccess) e = psms::launch_rows<T>(m, +1, S2, Pm, twm, ra, 1, st);        // [m][m][m]
+  if (e == hipSuccess) e = psms::launch_cube<T>(Pm, (long long)m * m * m, st);
+  ra.n_in = m;
+  ra.n_out = g.H;
+  if (e == hipSuccess) e = psms::launch_rows<T>(m, -1, Pm, S1, twm, ra, 1, st);        // [m][m][H]
+  ly.n_in = m;
+  ly.n_out = g.C;
+  if (e == hipSuccess) e = psms::launch_lines<T>(m, -1, S1, S2, twm, ly, 1, st);     // [m][C][H]
+  lz.n_in = m;
+  lz.n_out = g.C;
+  lz.scale = 1.0 / (double(m) * m * m);
+  if (e == hipSuccess) e = psms::launch_lines<T>(m, -1, S2, S1, twm, lz, 1, st);     // [C][C][H] band
+  psms::LineArgs li{};
+  li.n_in = g.C;
+  li.n_out = n;
+  li.inner = g.Q;
+  li.nlines = g.Q;
+  li.fmap = 0;
+  li.scale = double(n) * n;
+  cpx<T>* w7 = static_cast<cpx<T>*>(c->bufa) + 7LL * n * g.Q;                      // [n][C][H]
+  if (e == hipSuccess) e = psms::launch_lines<T>(n, +1, S1, w7, twiddles<T>(c), li, 1, st);
+  return e;
+}
+
 // One time step: y-inverse, x stage with products, y-forward, z stage with the
 // update.  `ev` (optional) receives an event before each stage and after the last.
 template <typename T>
@@ -172,6 +271,7 @@ hipError_t one_step(psms_ctx* c, hipEvent_t* ev = nullptr) {
   if (e != hipSuccess) return e;
   for (int stage = 0; stage < 4; ++stage) {
     if (ev && (e = hipEventRecord(ev[stage], c->stream)) != hipSuccess) return e;
+    if (stage == 3 && c->m && (e = exact_cube<T>(c)) != hipSuccess) return e;
     e = psms::launch_step_stage<T>(c->g.n, stage, c->variant[stage], c->d_box, 0, 1, twiddles<T>(c), 1, c->stream);
     if (e != hipSuccess) return e;
   }
@@ -344,6 +444,18 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
   }
   hipError_t e = hipMemcpyAsync(c->tw64, t64.data(), n * sizeof(cpx<double>), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->tw32, t32.data(), n * sizeof(cpx<float>), hipMemcpyHostToDevice, c->stream);
+  c->m = lay.m;
+  std::vector<cpx<double>> m64(lay.m);
+  std::vector<cpx<float>> m32(lay.m);
+  for (int k = 0; k < lay.m; ++k) {
+    const double a = -2.0 * M_PI * double(k) / double(lay.m);
+    m64[k] = cpx<double>{std::cos(a), std::sin(a)};
+    m32[k] = cpx<float>{float(m64[k].re), float(m64[k].im)};
+  }
+  if (e == hipSuccess && lay.m)
+    e = hipMemcpyAsync(c->ws + lay.pad_tw64, m64.data(), lay.m * sizeof(cpx<double>), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && lay.m)
+    e = hipMemcpyAsync(c->ws + lay.pad_tw32, m32.data(), lay.m * sizeof(cpx<float>), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = sync_box(c);  // the device descriptor is valid from creation on
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -586,6 +698,52 @@ int psms_diagnostics(psms_ctx* c, psms_diag* h_out) {
   return PSMS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The pressure of the current state: the step's y-inverse, x (products) and
+// y-forward stages, the z-forward of the six T_ij into the compact band, then
+// p_hat = k_i k_j T_ij / k^2 and its full half spectrum.  The stages overwrite
+// the z-inverse of the state that the next step starts from.
+template <typename T>
+hipError_t pressure_impl(psms_ctx* c, double* d_p) {
+  const BoxGeom& g = c->g;
+  const int n = g.n;
+  hipError_t e = hipSuccess;
+  if (!c->g_valid) e = prologue<T>(c);
+  if (e == hipSuccess) e = sync_box(c);
+  for (int stage = 0; stage < 3 && e == hipSuccess; ++stage)
+    e = psms::launch_step_stage<T>(n, stage, c->variant[stage], c->d_box, 0, 1, twiddles<T>(c), 1, c->stream);
+  c->g_valid = 0;
+  psms::LineArgs lz{};
+  lz.n_in = n;
+  lz.n_out = g.C;
+  lz.inner = g.Q;
+  lz.nlines = g.Q;
+  lz.in_fstride = (long long)n * g.Q;
+  lz.out_fstride = g.M;
+  lz.fmap = 0x543210u;
+  lz.scale = 1.0 / (double(n) * n * n);
+  cpx<T>* t6 = static_cast<cpx<T>*>(c->bufb);
+  if (e == hipSuccess)
+    e = psms::launch_lines<T>(n, -1, static_cast<const cpx<T>*>(c->bufa), t6, twiddles<T>(c), lz, 6, c->stream);
+  cpx<double>* pb = reinterpret_cast<cpx<double>*>(c->ws + c->lay.phys);
+  if (e == hipSuccess) e = psms::launch_pressure_band<T>(t6, g, pb, c->stream);
+  if (e == hipSuccess) e = psms::launch_expand<double>(pb, reinterpret_cast<cpx<double>*>(d_p), g, 1, c->stream);
+  return e;
+}
+}  // namespace
+
+extern "C" {
+
+int psms_pressure(psms_ctx* c, double* d_p) {
+  if (!c || !d_p) return fail(PSMS_E_INVAL, "NULL argument");
+  if (!c->have_state) return fail(PSMS_E_STATE, "no state");
+  const hipError_t e = (c->p.precision == PSMS_MIXED) ? pressure_impl<float>(c, d_p) : pressure_impl<double>(c, d_p);
+  if (e != hipSuccess) return hip_fail(e, "pressure");
+  return PSMS_OK;
+}
+
 int psms_index_maps(psms_ctx* c, int32_t* d_out) {
   if (!c || !d_out) return fail(PSMS_E_INVAL, "NULL argument");
   hipError_t e = psms::launch_index_maps(d_out, c->g, c->stream);
@@ -820,6 +978,7 @@ int batch_layout(int32_t nbox, const psms_params* p, BatchLayout* L) {
     int r = validate(&p[i]);
     if (r) return r;
     if (p[i].precision != p[0].precision) return fail(PSMS_E_INVAL, "all boxes of a batch share one precision");
+    if (p[i].cube != 0) return fail(PSMS_E_NOTSUP, "batched boxes take the grid cube (cube = 0)");
     L->box_off[i] = off;
     L->box_bytes[i] = make_layout(p[i]).total;
     off = align256(off + L->box_bytes[i]);
@@ -1115,6 +1274,7 @@ struct AdjLayout {
 int adjoint_layout(const psms_params* p, int32_t max_steps, int32_t seg_len, AdjLayout* L) {
   int r = validate(p);
   if (r) return r;
+  if (p->cube != 0) return fail(PSMS_E_NOTSUP, "the adjoint differentiates the grid cube (cube = 0)");
   if (max_steps < 1 || seg_len < 1) return fail(PSMS_E_INVAL, "max_steps and seg_len must be >= 1");
   psms_params p64 = *p;
   p64.precision = PSMS_FP64;
@@ -1318,7 +1478,7 @@ struct ChanLayout {
   size_t kx, ky, twx64, twx32, twy64, twy32, twz64, twz32;
   size_t state, mean, hist, hmean;
   size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, lapc, lapphi, lapom, psi, lappsi, G;
-  size_t d2mean, gmean, wt, wb, M, psip, xi, xw, diag, total;
+  size_t d2mean, gmean, wt, wb, M, whp, mhp, psip, xi, xw, diag, xdev, total;
 };
 
 constexpr int kChanDiagBlocks = 1024;   // partial sums of the diagnostics
@@ -1389,10 +1549,13 @@ ChanLayout chan_layout(const psms_channel_params& p) {
   take(L.wt, arr);
   take(L.wb, arr);
   take(L.M, 4 * size_t(g.NL) * sizeof(double));
+  take(L.whp, nz * size_t(g.NL) * sizeof(double));
+  take(L.mhp, 2 * size_t(g.NL) * sizeof(double));
   take(L.psip, arr);
   take(L.xi, arr);
   take(L.xw, 4 * nz * size_t(g.NL) * sizeof(double));   // one elimination scratch per batched problem
   take(L.diag, (8 * size_t(kChanDiagBlocks) + 8) * sizeof(double));
+  take(L.xdev, sizeof(psms::BoxDev));   // descriptor of the fused x stage
   L.total = off;
   return L;
 }
@@ -1422,6 +1585,11 @@ struct psms_channel {
   psms::ChanGeom g;
   psms::ChanCoef coef;
   ChanLayout lay;
+  psms::BoxDev h_xdev;   // host copy of the x-stage descriptor (source of its upload)
+  int use_graph = 1;     // replay a captured step after the first (needs a non-NULL stream)
+  int graph_ok = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   char* ws;
   hipStream_t stream;
   double a_fac, b_fac;
@@ -1446,23 +1614,14 @@ const cpx<T>* chan_twz(const psms_channel* c) {
   return reinterpret_cast<const cpx<T>*>(c->ws + (std::is_same<T, double>::value ? c->lay.twz64 : c->lay.twz32));
 }
 
-// physical [nf][z][y][x] (T) -> band [nf][n][line] (T): x rows, y lines (1/(nx ny)), DCT-I;
-// with band64, the DCT-I writes FP64 coefficients there instead, n > Kz zeroed
+// x-spectral [nf][z][y][kx band] (T) -> band [nf][n][line] (T): y lines (1/(nx ny)),
+// DCT-I; with band64, the DCT-I writes FP64 coefficients there instead, n > Kz zeroed
 template <typename T>
-hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf, cpx<double>* band64 = nullptr) {
+hipError_t chan_forward_yz(psms_channel* c, const cpx<T>* xs, cpx<T>* band, int nf, cpx<double>* band64) {
   const psms::ChanGeom& g = c->g;
   const long long nz = g.nc + 1;
-  cpx<T>* B = c->at<cpx<T>>(c->lay.B);
   cpx<T>* A2 = c->at<cpx<T>>(c->lay.A2);
-  psms::RowArgs ra{};
-  ra.nrows = nz * g.ny;
-  ra.n_in = g.nx;
-  ra.n_out = g.Hx;
-  ra.in_fstride = g.P;
-  ra.out_fstride = nz * g.ny * g.Hx;
-  ra.scale = 1.0;
-  hipError_t e = psms::launch_rows<T>(g.nx, -1, phys, B, chan_tw<T>(c, true), ra, nf, c->stream);
-  if (e != hipSuccess) return e;
+  hipError_t e;
   psms::LineArgs la{};
   la.n_in = g.ny;
   la.n_out = g.Cy;
@@ -1473,15 +1632,34 @@ hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf, cp
   la.fmap = 0x76543210u;
   la.dmask = 0;
   la.scale = 1.0 / (double(g.nx) * double(g.ny));
-  e = psms::launch_lines<T>(g.ny, -1, B, A2, chan_tw<T>(c, false), la, nf, c->stream);
+  e = psms::launch_lines<T>(g.ny, -1, xs, A2, chan_tw<T>(c, false), la, nf, c->stream);
   if (e == hipSuccess)
     e = psms::launch_dct_fields<T>(g.nc, A2, band, g.NL, g.NZL, nf, chan_twz<T>(c), +1, c->stream, band64, g.Kz);
   return e;
 }
 
-// band [nf][n][line] (T) -> physical [nf][z][y][x] (T)
+// physical [nf][z][y][x] (T) -> band [nf][n][line] (T): x rows, then chan_forward_yz
 template <typename T>
-hipError_t chan_inverse(psms_channel* c, const cpx<T>* band, T* phys, int nf) {
+hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf, cpx<double>* band64 = nullptr) {
+  const psms::ChanGeom& g = c->g;
+  const long long nz = g.nc + 1;
+  cpx<T>* B = c->at<cpx<T>>(c->lay.B);
+  psms::RowArgs ra{};
+  ra.nrows = nz * g.ny;
+  ra.n_in = g.nx;
+  ra.n_out = g.Hx;
+  ra.in_fstride = g.P;
+  ra.out_fstride = nz * g.ny * g.Hx;
+  ra.scale = 1.0;
+  hipError_t e = psms::launch_rows<T>(g.nx, -1, phys, B, chan_tw<T>(c, true), ra, nf, c->stream);
+  if (e != hipSuccess) return e;
+  return chan_forward_yz<T>(c, B, band, nf, band64);
+}
+
+// band [nf][n][line] (T) -> x-spectral [nf][z][y][kx band] (T) in the buffer B:
+// DCT-I, y lines
+template <typename T>
+hipError_t chan_inverse_yz(psms_channel* c, const cpx<T>* band, int nf) {
   const psms::ChanGeom& g = c->g;
   const long long nz = g.nc + 1;
   cpx<T>* B = c->at<cpx<T>>(c->lay.B);
@@ -1498,7 +1676,16 @@ hipError_t chan_inverse(psms_channel* c, const cpx<T>* band, T* phys, int nf) {
   la.fmap = 0x76543210u;
   la.dmask = 0;
   la.scale = 1.0;
-  e = psms::launch_lines<T>(g.ny, +1, A2, B, chan_tw<T>(c, false), la, nf, c->stream);
+  return psms::launch_lines<T>(g.ny, +1, A2, B, chan_tw<T>(c, false), la, nf, c->stream);
+}
+
+// band [nf][n][line] (T) -> physical [nf][z][y][x] (T)
+template <typename T>
+hipError_t chan_inverse(psms_channel* c, const cpx<T>* band, T* phys, int nf) {
+  const psms::ChanGeom& g = c->g;
+  const long long nz = g.nc + 1;
+  cpx<T>* B = c->at<cpx<T>>(c->lay.B);
+  hipError_t e = chan_inverse_yz<T>(c, band, nf);
   if (e != hipSuccess) return e;
   psms::RowArgs ra{};
   ra.nrows = nz * g.ny;
@@ -1535,12 +1722,25 @@ hipError_t chan_step_once(psms_channel* c) {
   cb.in[1] = phi;
   cb.out[1] = C64(L.dphi);
   PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0, st));
-  PSMS_TRY(psms::launch_ch_fields<T>(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky,
-                                     c->at<cpx<T>>(L.A), st));
-  PSMS_TRY(chan_inverse<T>(c, c->at<cpx<T>>(L.A), c->at<T>(L.C), g.nf_in));
-  // 3-4. products and the forward transforms, 2/3 rule in x, y and z
-  PSMS_TRY(psms::launch_ch_products<T>(g, c->at<T>(L.C), c->coef.csig, st));
-  PSMS_TRY(chan_forward<T>(c, c->at<T>(L.C), c->at<cpx<T>>(L.A), g.nf_out, R));   // FP64, Chebyshev cut
+  if (g.sp) {
+    PSMS_TRY(psms::launch_ch_fields<T>(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky,
+                                       c->at<cpx<T>>(L.A), st));
+    PSMS_TRY(chan_inverse<T>(c, c->at<cpx<T>>(L.A), c->at<T>(L.C), g.nf_in));
+    // 3-4. products and the forward transforms, 2/3 rule in x, y and z
+    PSMS_TRY(psms::launch_ch_products<T>(g, c->at<T>(L.C), c->coef.csig, st));
+    PSMS_TRY(chan_forward<T>(c, c->at<T>(L.C), c->at<cpx<T>>(L.A), g.nf_out, R));   // FP64, Chebyshev cut
+  } else {
+    // two-phase: u, v, w, phi, dy phi, dz phi through the DCT-I and y lines; the
+    // x-inverse, the 8 products and the x-forward in one pass (the box's x stage on
+    // (nc + 1) ny rows; dx phi formed on load), so that no physical field is
+    // stored; then y lines and the DCT-I with the Chebyshev cut (FP64)
+    PSMS_TRY(psms::launch_ch_fields<T>(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky,
+                                       c->at<cpx<T>>(L.A), st, 1));
+    PSMS_TRY(chan_inverse_yz<T>(c, c->at<cpx<T>>(L.A), 6));
+    PSMS_TRY(psms::launch_xstage_rows<T>(g.nx, c->at<psms::BoxDev>(L.xdev), chan_tw<T>(c, true),
+                                         (long long)(nc + 1) * g.ny, 2.0 * M_PI / c->p.lx, st));
+    PSMS_TRY(chan_forward_yz<T>(c, c->at<cpx<T>>(L.C), c->at<cpx<T>>(L.A), 8, R));
+  }
   // 5. S = div T, and the wall-normal derivatives the right-hand sides need
   cpx<double>* D3 = C64(L.D3);
   cb.n = 3;   // D T_xz, D T_yz, D T_zz
@@ -1606,8 +1806,16 @@ hipError_t chan_step_once(psms_channel* c) {
   b2.np = g.sp ? 1 : 2;
   b2.p[0] = psms::HelmProblem{C64(L.psip), w, xw, nl, 0.0, kx, ky, 0, z0, z0};             // w_p
   b2.p[1] = psms::HelmProblem{C64(L.xi), phi, xw + xws, nl, c->b_fac, kx, ky, 3, z0, z0};  // phi
+  // between two no-slip walls the influence correction is applied by the w
+  // chains themselves (the two wall conditions split by parity)
+  const bool fused = (fs == 0) && psms::helm_fuses_influence(nc);
+  if (fused) {
+    b2.p[0].wh = c->at<double>(L.whp);
+    b2.p[0].mh = c->at<double>(L.mhp);
+  }
   PSMS_TRY(psms::launch_helm_batch(b2, nc, st));
-  PSMS_TRY(psms::launch_influence_apply(w, C64(L.wt), C64(L.wb), c->at<double>(L.M), nc, nl, kx, ky, fs, st));
+  if (!fused)
+    PSMS_TRY(psms::launch_influence_apply(w, C64(L.wt), C64(L.wb), c->at<double>(L.M), nc, nl, kx, ky, fs, st));
 #undef PSMS_TRY
   return hipSuccess;
 }
@@ -1688,7 +1896,16 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
   tws(p->ny, y64, y32);
   tws(2 * p->nc, z64, z32);
   hipStream_t st = c->stream;
-  hipError_t e = hipMemcpyAsync(c->ws + lay.kx, hkx.data(), g.NL * sizeof(double), hipMemcpyHostToDevice, st);
+  // descriptor of the fused x stage: y-inverse output B in, the products'
+  // x-spectra into C (8 fields of (nc + 1) ny rows of Hx entries fit there)
+  psms::BoxDev xd{};
+  xd.bufa = c->ws + lay.B;
+  xd.bufb = c->ws + lay.C;
+  xd.csig = c->coef.csig;
+  c->h_xdev = xd;
+  hipError_t e = hipMemcpyAsync(c->ws + lay.xdev, &c->h_xdev, sizeof(psms::BoxDev), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + lay.kx, hkx.data(), g.NL * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.ky, hky.data(), g.NL * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twx64, x64.data(), x64.size() * sizeof(cpx<double>), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->ws + lay.twx32, x32.data(), x32.size() * sizeof(cpx<float>), hipMemcpyHostToDevice, st);
@@ -1719,6 +1936,9 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
     if (e == hipSuccess)
       e = psms::launch_influence_pre(c->at<cpx<double>>(lay.wt), c->at<cpx<double>>(lay.wb), p->nc, g.NL,
                                      c->at<double>(lay.M), p->free_slip & 3, st);
+    if (e == hipSuccess)
+      e = psms::launch_influence_parity_pre(c->at<cpx<double>>(lay.wt), c->at<cpx<double>>(lay.wb), p->nc, g.NL,
+                                            c->at<double>(lay.whp), c->at<double>(lay.mhp), st);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
@@ -1859,11 +2079,36 @@ int psms_channel_step(psms_channel* c, int32_t nsteps) {
   if (!c) return fail(PSMS_E_INVAL, "NULL context");
   if (nsteps < 0) return fail(PSMS_E_INVAL, "nsteps must be >= 0");
   if (!c->have_state) return fail(PSMS_E_STATE, "step before init_state / set_state");
+  const bool mixed = c->p.precision == PSMS_MIXED;
   for (int i = 0; i < nsteps; ++i) {
-    const hipError_t e = (c->p.precision == PSMS_MIXED) ? chan_step_once<float>(c) : chan_step_once<double>(c);
+    // after the Adams-Bashforth 1 step every step is the same launch sequence
+    // with the same arguments: capture it once and replay it
+    const bool graph = c->use_graph && c->stream != nullptr && c->nstep > 0;
+    hipError_t e = hipSuccess;
+    if (graph) {
+      if (!c->graph_ok) {
+        e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          const hipError_t e2 = mixed ? chan_step_once<float>(c) : chan_step_once<double>(c);
+          e = hipStreamEndCapture(c->stream, &c->graph);
+          if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) c->graph_ok = 1;
+      }
+      if (e == hipSuccess) e = hipGraphLaunch(c->gexec, c->stream);
+    } else {
+      e = mixed ? chan_step_once<float>(c) : chan_step_once<double>(c);
+    }
     if (e != hipSuccess) return hip_fail(e, "channel_step");
     ++c->nstep;
   }
+  return PSMS_OK;
+}
+
+int psms_channel_set_graphs(psms_channel* c, int32_t enable) {
+  if (!c) return fail(PSMS_E_INVAL, "NULL context");
+  c->use_graph = enable ? 1 : 0;
   return PSMS_OK;
 }
 
@@ -1886,6 +2131,10 @@ int psms_channel_get_state(psms_channel* c, double* d_state, double* d_mean, dou
 }
 
 int psms_channel_destroy(psms_channel* c) {
+  if (c && c->graph_ok) {
+    hipGraphExecDestroy(c->gexec);
+    hipGraphDestroy(c->graph);
+  }
   delete c;
   return PSMS_OK;
 }

@@ -321,9 +321,12 @@ __device__ __forceinline__ T xproduct(const cpx<T> (&ph)[7][E], int e, int c, T 
   else return p3 * p3 * p3;                                               // phi^3
 }
 
-template <typename T, int N, int V>
+// CH: the same stage on rows of any count (the plane channel's x stage:
+// xrows = (nc + 1) ny rows of the y-inverse, kx = kxs k for x periods other
+// than 2 pi); the box passes xrows = N^2 and kxs = 1 implicitly.
+template <typename T, int N, int V, bool CH = false>
 __global__ void __launch_bounds__(64 << V) __attribute__((amdgpu_waves_per_eu(kXstepWaves<T, N>)))
-k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ tw_g) {
+k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ tw_g, long long xrows, double kxs) {
   using P = Plan<N>;
   using G = Tile<P, V>;
   const BoxDev& bx = boxes[box0 + blockIdx.z];
@@ -334,7 +337,7 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
   constexpr int RI = first_radix<P, 1>();   // inverse starts with R[NST-1]
   constexpr int RP = last_radix<P, 1>();    // inverse ends / forward starts with R[0]
   constexpr int RO = last_radix<P, -1>();   // forward ends with R[NST-1]
-  constexpr long long ROWS = (long long)N * N;
+  const long long ROWS = CH ? xrows : (long long)N * N;
   constexpr bool XDMA = kXstepDma<T, N>;
   __shared__ cpx<T> twf[tw_size<P, -1>()];
   __shared__ cpx<T> twi[tw_size<P, 1>()];
@@ -375,7 +378,7 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
     const int p = slot_pos<P, RI>(t, e / RI, e % RI);
     const int k = (p <= N / 2) ? p : N - p;
     if (vf == 4) {
-      const T kx = T(k);
+      const T kx = CH ? T(double(k) * kxs) : T(k);
       A = cpx<T>{-kx * A.im, kx * A.re};
       B = cpx<T>{-kx * B.im, kx * B.re};
     }
@@ -768,6 +771,50 @@ __global__ void k_compact(const cpx<T>* __restrict__ full, cpx<T>* __restrict__ 
   }
 }
 
+// a compact FP64 band converted to precision T (n entries)
+template <typename T>
+__global__ void k_band_to(const cpx<double>* __restrict__ a, cpx<T>* __restrict__ out, long long n) {
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
+       id += (long long)gridDim.x * blockDim.x) {
+    const cpx<double> v = a[id];
+    out[id] = cpx<T>{T(v.re), T(v.im)};
+  }
+}
+
+// f <- f^3 over n values
+template <typename T>
+__global__ void k_cube(T* __restrict__ f, long long n) {
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
+       id += (long long)gridDim.x * blockDim.x) {
+    const T a = f[id];
+    f[id] = a * a * a;
+  }
+}
+
+// The pressure that the projection removes, from the compact spectra of the six
+// products T_ij (order xx, yy, zz, xy, xz, yz; [6][M], precision T): with
+// S_i = i k_j T_ij and lap p = div S, p_hat = k_i k_j T_ij / k^2 (FP64; k = 0 -> 0).
+template <typename T>
+__global__ void k_pressure_band(const cpx<T>* __restrict__ t6, BoxGeom g, cpx<double>* __restrict__ p) {
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < g.M;
+       id += (long long)gridDim.x * blockDim.x) {
+    const int ix = int(id % g.H);
+    const int iy = int((id / g.H) % g.C);
+    const int iz = int(id / ((long long)g.H * g.C));
+    const double kx = ix, ky = (iy <= g.K) ? iy : iy - g.C, kz = (iz <= g.K) ? iz : iz - g.C;
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double w[6] = {kx * kx, ky * ky, kz * kz, 2.0 * kx * ky, 2.0 * kx * kz, 2.0 * ky * kz};
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const cpx<T> a = t6[f * g.M + id];
+      re += w[f] * double(a.re);
+      im += w[f] * double(a.im);
+    }
+    p[id] = (k2 == 0.0) ? cpx<double>{0.0, 0.0} : cpx<double>{re / k2, im / k2};
+  }
+}
+
 // Leray projection of the compact velocity [3][M] in place (k = 0 -> 0).
 __global__ void k_project(cpx<double>* __restrict__ u, BoxGeom g) {
   for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < g.M;
@@ -1029,7 +1076,7 @@ hipError_t step_nv(int stage, const BoxDev* boxes, int box0, int nbox, const cpx
     case 1: {  // x stage with products
       const long long pairs = (long long)N * N / 2;
       const dim3 grid(unsigned((pairs + G::L - 1) / G::L), 1, unsigned(nbox));
-      k_xstep<T, N, V><<<grid, threads, 0, st>>>(boxes, box0, tw);
+      k_xstep<T, N, V><<<grid, threads, 0, st>>>(boxes, box0, tw, 0, 1.0);
       break;
     }
     case 2: {  // y-forward, 8 fields
@@ -1059,6 +1106,31 @@ hipError_t step_n(int stage, int variant, const BoxDev* boxes, int box0, int nbo
 }
 
 }  // namespace
+
+template <typename T, int N>
+hipError_t xstage_rows_n(const BoxDev* dev, const cpx<T>* tw, long long rows, double kxs, hipStream_t st) {
+  using G = Tile<Plan<N>, 2>;
+  const long long pairs = rows / 2;
+  const dim3 grid(unsigned((pairs + G::L - 1) / G::L), 1, 1);
+  k_xstep<T, N, 2, true><<<grid, unsigned(G::L * G::TT), 0, st>>>(dev, 0, tw, rows, kxs);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xstage_rows(int n, const BoxDev* dev, const cpx<T>* tw, long long rows, double kxs,
+                              hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  if (rows % 2) return hipErrorInvalidValue;   // rows are transformed in pairs
+  switch (n) {
+#define PSMS_CASE(NN) case NN: return xstage_rows_n<T, NN>(dev, tw, rows, kxs, st);
+    PSMS_FOR_EACH_N(PSMS_CASE)
+#undef PSMS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_xstage_rows<float>(int, const BoxDev*, const cpx<float>*, long long, double, hipStream_t);
+template hipError_t launch_xstage_rows<double>(int, const BoxDev*, const cpx<double>*, long long, double,
+                                               hipStream_t);
 
 template <typename T>
 hipError_t launch_lines(int n, int dir, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, const LineArgs& a,
@@ -1116,6 +1188,26 @@ hipError_t launch_project(cpx<double>* u, const BoxGeom& g, hipStream_t st) {
   k_project<<<grid_for(g.M), 256, 0, st>>>(u, g);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_band_to(const cpx<double>* a, cpx<T>* out, long long n, hipStream_t st) {
+  k_band_to<T><<<grid_for(n), 256, 0, st>>>(a, out, n);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_cube(T* f, long long n, hipStream_t st) {
+  k_cube<T><<<grid_for(n), 256, 0, st>>>(f, n);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_pressure_band(const cpx<T>* t6, const BoxGeom& g, cpx<double>* p, hipStream_t st) {
+  k_pressure_band<T><<<grid_for(g.M), 256, 0, st>>>(t6, g, p);
+  return hipGetLastError();
+}
+template hipError_t launch_band_to<float>(const cpx<double>*, cpx<float>*, long long, hipStream_t);
+template hipError_t launch_cube<float>(float*, long long, hipStream_t);
+template hipError_t launch_cube<double>(double*, long long, hipStream_t);
+template hipError_t launch_pressure_band<float>(const cpx<float>*, const BoxGeom&, cpx<double>*, hipStream_t);
+template hipError_t launch_pressure_band<double>(const cpx<double>*, const BoxGeom&, cpx<double>*, hipStream_t);
 template <typename T>
 hipError_t launch_spec_finish(const cpx<T>* in, cpx<T>* out, const BoxGeom& g, int nf, int dealias, int axis,
                               double scale, hipStream_t st) {

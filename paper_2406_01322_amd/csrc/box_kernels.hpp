@@ -75,11 +75,29 @@ constexpr int kStepVariants = 3;
 template <typename T>
 hipError_t launch_step_stage(int n, int stage, int variant, const BoxDev* table, int box0, int nbox,
                              const cpx<T>* tw, int do_update, hipStream_t st);
+// The x stage of the step (x-inverse of u, v, w, phi, i kx phi (formed on
+// load from phi), dy phi, dz phi; the 8 products; x-forward) on `rows` rows
+// of length n (rows even): dev->bufa holds the 6 input fields [6][rows][n/2+1
+// band entries K+1], dev->bufb receives the 8 products [8][rows][K+1]; kx =
+// kxs k; dev->csig the capillary coefficient.  One descriptor (box0 = 0).
+template <typename T>
+hipError_t launch_xstage_rows(int n, const BoxDev* dev, const cpx<T>* tw, long long rows, double kxs,
+                              hipStream_t st);
 template <typename T>
 hipError_t launch_expand(const cpx<T>* cmp, cpx<T>* full, const BoxGeom& g, int nf, hipStream_t st);
 template <typename T>
 hipError_t launch_compact(const cpx<T>* full, cpx<T>* cmp, const BoxGeom& g, int nf, hipStream_t st);
 hipError_t launch_project(cpx<double>* u, const BoxGeom& g, hipStream_t st);
+// exact cube of phi: a compact FP64 band converted to T (n entries); the
+// pointwise cube of n values in place
+template <typename T>
+hipError_t launch_band_to(const cpx<double>* a, cpx<T>* out, long long n, hipStream_t st);
+template <typename T>
+hipError_t launch_cube(T* f, long long n, hipStream_t st);
+// p_hat = k_i k_j T_ij / k^2 from the compact spectra [6][M] of the products
+// (xx, yy, zz, xy, xz, yz), into p [M] (FP64)
+template <typename T>
+hipError_t launch_pressure_band(const cpx<T>* t6, const BoxGeom& g, cpx<double>* p, hipStream_t st);
 template <typename T>
 hipError_t launch_spec_finish(const cpx<T>* in, cpx<T>* out, const BoxGeom& g, int nf, int dealias, int axis,
                               double scale, hipStream_t st);

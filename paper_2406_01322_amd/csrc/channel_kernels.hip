@@ -368,9 +368,14 @@ __global__ void k_helm_batch(HelmBatch b, int nc) {
 // workgroup), X_i of each chain in registers (the loops over i are unrolled
 // for the compile-time NC, and i > m is skipped uniformly) and Y_i in LDS, so
 // that HBM sees only the right-hand side read and the solution written (32
-// bytes per coefficient instead of 104 through the scratch chains).  Same
+// bytes per coefficient instead of 104 through the scratch chains).  The
+// chain's right-hand side entries are first copied into the same LDS rows by
+// 16-byte global_load_lds copies, all in flight at once: each chain is one
+// thread's sequential recurrence and a workgroup is one wavefront, so loads
+// issued inside the recurrence would leave their latency exposed.  Same
 // condition at both walls only (bc 0 or 3); the arithmetic is that of
-// helm_line, in the same order.
+// helm_line, in the same order.  With P.wh the w problem's influence
+// correction follows in the second upward sweep (HelmProblem).
 template <int NC>
 __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
   constexpr int MM = NC / 2;                 // longest chain: parity 0, i = 0..MM
@@ -379,9 +384,27 @@ __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
   const int p = blockIdx.z;
   const int tid = threadIdx.x;
   const long long l = (long long)blockIdx.x * 64 + tid;
-  if (l >= P.nlines) return;                 // no barrier below: each chain is one thread's
   const long long nl = P.nlines;
   const int m = (NC - p) / 2;
+  const cpx<double>* __restrict__ g = P.g;
+  if (g) {
+    // entries n = p + 2 i <= NC - 2 of this parity into row i (lane tid's
+    // 16 bytes at &Ys[i][tid]); lanes past the last line copy nothing
+    if (l < nl) {
+#pragma unroll
+      for (int i = 0; i <= MM; ++i) {
+        if (i <= m && p + 2 * i <= NC - 2)
+          __builtin_amdgcn_global_load_lds(
+              (const __attribute__((address_space(1))) void*)(g + (long long)(p + 2 * i) * nl + l),
+              (__attribute__((address_space(3))) void*)(&Ys[i][0]), 16, 0, 0);
+      }
+    }
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0): the copies have landed in LDS
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+  }
+  if (l >= nl) return;                       // no barrier below: each chain is one thread's
   const bool neu = P.bc == 3;
   double be = P.beta_add;
   if (P.kx) be += P.kx[l] * P.kx[l] + P.ky[l] * P.ky[l];
@@ -389,10 +412,12 @@ __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
   const bool plus = (p == 0) != neu;
   const cpx<double> s = plus ? cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)}
                              : cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)};
-  const cpx<double>* __restrict__ g = P.g;
+  // entry n of g (zero outside the tau rows); row (n - p) / 2 of Ys until the
+  // downward sweep overwrites it with Y (after its last use: the sweep keeps
+  // the three entries it needs in registers)
   auto G = [&](int n) -> cpx<double> {
     if (!g || n > NC - 2 || n < 0) return cpx<double>{0.0, 0.0};
-    return g[(long long)n * nl + l];
+    return Ys[(n - p) >> 1][tid];
   };
   // downward sweep: a_i = X_i a_{i-1} + Y_i
   double X[MM + 1];
@@ -418,18 +443,20 @@ __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
       const double den = 1.0 / (B + C * Xn);
       const double Xv = -A * den;
       const cpx<double> Y = {(R.re - C * Yn.re) * den, (R.im - C * Yn.im) * den};
+      g2 = g0;
+      g0 = gm;
+      gm = G(n - 4);
       X[i] = Xv;
       Ys[i][tid] = Y;
       Xn = Xv;
       Yn = Y;
-      g2 = g0;
-      g0 = gm;
-      gm = G(n - 4);
     }
   }
-  // upward sweep 1: a_i = P_i a_0 + Q_i and the boundary row of this parity
-  double Pc = 1.0, SP = 0.0;
-  cpx<double> Qv = {0.0, 0.0}, SQ = {0.0, 0.0};
+  // upward sweep 1: a_i = P_i a_0 + Q_i and the boundary row of this parity;
+  // with the influence correction also sum n^2 P_i and sum n^2 Q_i
+  const bool infl = P.wh != nullptr;
+  double Pc = 1.0, SP = 0.0, SPn = 0.0;
+  cpx<double> Qv = {0.0, 0.0}, SQ = {0.0, 0.0}, SQn = {0.0, 0.0};
 #pragma unroll
   for (int i = 0; i <= MM; ++i) {
     if (i <= m) {
@@ -439,24 +466,68 @@ __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
         Pc = X[i] * Pc;
         Qv = cpx<double>{X[i] * Qv.re + Y.re, X[i] * Qv.im + Y.im};
       }
-      const double w = neu ? double(n) * double(n) : 1.0;
+      const double n2 = double(n) * double(n);
+      const double w = neu ? n2 : 1.0;
       SP += w * Pc;
       SQ.re += w * Qv.re;
       SQ.im += w * Qv.im;
+      if (infl) {
+        SPn += n2 * Pc;
+        SQn.re += n2 * Qv.re;
+        SQn.im += n2 * Qv.im;
+      }
     }
   }
-  // a_0, then upward sweep 2
+  // a_0, the influence coefficient, then upward sweep 2
   cpx<double> a = {(s.re - SQ.re) / SP, (s.im - SQ.im) / SP};
   cpx<double>* __restrict__ f = P.f;
-  f[(long long)p * nl + l] = a;
+  cpx<double> c = {0.0, 0.0};
+  if (infl) {
+    if (P.kx[l] == 0.0 && P.ky[l] == 0.0) {  // no wall-normal velocity on the mean line
+#pragma unroll
+      for (int i = 0; i <= MM; ++i)
+        if (i <= m) f[(long long)(p + 2 * i) * nl + l] = cpx<double>{0.0, 0.0};
+      return;
+    }
+    // sum n^2 (a_n + c wh_n) = 0 with sum n^2 a_n = a_0 SPn + SQn
+    const double r = -1.0 / P.mh[(long long)p * nl + l];
+    c = cpx<double>{r * (a.re * SPn + SQn.re), r * (a.im * SPn + SQn.im)};
+  }
+  const double* __restrict__ wh = P.wh;
+  auto put = [&](int n, cpx<double> v) {
+    if (infl) {
+      const double h = wh[(long long)n * nl + l];
+      v = cpx<double>{v.re + c.re * h, v.im + c.im * h};
+    }
+    f[(long long)n * nl + l] = v;
+  };
+  put(p, a);
 #pragma unroll
   for (int i = 1; i <= MM; ++i) {
     if (i <= m) {
       const cpx<double> Y = Ys[i][tid];
       a = cpx<double>{X[i] * a.re + Y.re, X[i] * a.im + Y.im};
-      f[(long long)(p + 2 * i) * nl + l] = a;
+      put(p + 2 * i, a);
     }
   }
+}
+
+// wh_n = (w_t + w_b)_n (even n) or (w_t - w_b)_n (odd n): the homogeneous
+// solutions with psi = 1 at both walls (even) and psi = +-1 (odd); mh[p][l] =
+// sum over the parity of n^2 wh_n (w'(+1) = +-w'(-1) splits by parity)
+__global__ void k_influence_parity_pre(const cpx<double>* __restrict__ wt, const cpx<double>* __restrict__ wb, int nc,
+                                       long long nlines, double* __restrict__ wh, double* __restrict__ mh) {
+  const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlines) return;
+  double s[2] = {0.0, 0.0};
+  for (int n = 0; n <= nc; ++n) {
+    const long long o = (long long)n * nlines + l;
+    const double h = (n & 1) ? wt[o].re - wb[o].re : wt[o].re + wb[o].re;
+    wh[o] = h;
+    s[n & 1] += double(n) * double(n) * h;
+  }
+  mh[l] = s[0];
+  mh[nlines + l] = s[1];
 }
 
 // w = w_p + c_t w_t + c_b w_b with (c_t, c_b) making w'(+1) = w'(-1) = 0;
@@ -692,6 +763,9 @@ hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st) {
     same_walls = same_walls && (b.p[i].bc == 0 || b.p[i].bc == 3);
   }
   if (b.np == 0 || most == 0) return hipSuccess;
+  const bool reg = same_walls && helm_fuses_influence(nc);
+  for (int i = 0; i < b.np; ++i)
+    if (b.p[i].wh && (!reg || !b.p[i].kx || !b.p[i].mh)) return hipErrorInvalidValue;
   if (same_walls) {
     const dim3 grid(blocks(most, 64), unsigned(b.np), 2);
     switch (nc) {
@@ -704,6 +778,20 @@ hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st) {
     }
   }
   k_helm_batch<<<dim3(blocks(2 * most, 64), unsigned(b.np)), 64, 0, st>>>(b, nc);
+  return hipGetLastError();
+}
+
+bool helm_fuses_influence(int nc) {
+  switch (nc) {
+    case 4: case 6: case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96: case 128: return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_influence_parity_pre(const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
+                                       double* wh, double* mh, hipStream_t st) {
+  if (nlines <= 0) return hipSuccess;
+  k_influence_parity_pre<<<blocks(nlines, 64), 64, 0, st>>>(wt, wb, nc, nlines, wh, mh);
   return hipGetLastError();
 }
 

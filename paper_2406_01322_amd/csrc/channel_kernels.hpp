@@ -49,12 +49,27 @@ struct HelmProblem {
   const double* ky;
   int bc;   // bit 0: Neumann at the top wall (z = +1), bit 1: at the bottom wall; else Dirichlet
   cpx<double> top_c, bot_c;
+  // optional (on-chip path only, see helm_fuses_influence): the clamped-wall
+  // influence correction of the w problem between two no-slip walls, f + c_p wh
+  // per parity p with c_p making sum_{n = p mod 2} n^2 f_n = 0 (f' = 0 at both
+  // walls); wh [nc+1][nlines] the parity-split homogeneous solutions, mh [2][nlines]
+  // their sums sum n^2 wh_n; f = 0 on the line kx = ky = 0
+  const double* wh = nullptr;
+  const double* mh = nullptr;
 };
 struct HelmBatch {
   HelmProblem p[kHelmBatchMax];
   int np;
 };
 hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st);
+// whether launch_helm_batch keeps the chains on chip for this nc (same condition
+// at both walls), the only path that applies HelmProblem::wh
+bool helm_fuses_influence(int nc);
+// the parity-split homogeneous solutions of the clamped w problem between two
+// no-slip walls: wh_n = (w_t + w_b)_n for even n, (w_t - w_b)_n for odd n (real),
+// and mh[p][l] = sum_{n = p mod 2} n^2 wh_n
+hipError_t launch_influence_parity_pre(const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
+                                       double* wh, double* mh, hipStream_t st);
 hipError_t launch_influence(cpx<double>* wp, const cpx<double>* wt, const cpx<double>* wb, int nc, long long nlines,
                             const double* kx, const double* ky, hipStream_t st);
 // influence matrix with fixed homogeneous solutions: M [4][nlines] once, then

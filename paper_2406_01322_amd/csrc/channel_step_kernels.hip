@@ -32,7 +32,8 @@ template <typename T>
 __global__ void k_ch_fields(ChanGeom g, const cpx<double>* __restrict__ om, const cpx<double>* __restrict__ w,
                             const cpx<double>* __restrict__ phi, const cpx<double>* __restrict__ dw,
                             const cpx<double>* __restrict__ dphi, const cpx<double>* __restrict__ mean,
-                            const double* __restrict__ kxl, const double* __restrict__ kyl, cpx<T>* __restrict__ out) {
+                            const double* __restrict__ kxl, const double* __restrict__ kyl, cpx<T>* __restrict__ out,
+                            int six) {
   PSMS_GRID_LOOP(id, g.NZL) {
     const long long l = id % g.NL, n = id / g.NL;
     const double kx = kxl[l], ky = kyl[l];
@@ -52,9 +53,15 @@ __global__ void k_ch_fields(ChanGeom g, const cpx<double>* __restrict__ om, cons
     out[2 * g.NZL + id] = cpx<T>{T(ww.re), T(ww.im)};
     if (!g.sp) {
       const cpx<double> p = phi[id];
-      const cpx<double> f[4] = {p, ti(kx, p), ti(ky, p), dphi[id]};
+      if (six) {   // dx phi is formed by the x stage
+        const cpx<double> f[3] = {p, ti(ky, p), dphi[id]};
 #pragma unroll
-      for (int k = 0; k < 4; ++k) out[(k + 3) * g.NZL + id] = cpx<T>{T(f[k].re), T(f[k].im)};
+        for (int k = 0; k < 3; ++k) out[(k + 3) * g.NZL + id] = cpx<T>{T(f[k].re), T(f[k].im)};
+      } else {
+        const cpx<double> f[4] = {p, ti(kx, p), ti(ky, p), dphi[id]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[(k + 3) * g.NZL + id] = cpx<T>{T(f[k].re), T(f[k].im)};
+      }
     }
   }
 }
@@ -363,8 +370,8 @@ hipError_t launch_ch_diag_final(const ChanGeom& g, const double* part, int nb1, 
 template <typename T>
 hipError_t launch_ch_fields(const ChanGeom& g, const cpx<double>* om, const cpx<double>* w, const cpx<double>* phi,
                             const cpx<double>* dw, const cpx<double>* dphi, const cpx<double>* mean, const double* kx,
-                            const double* ky, cpx<T>* out, hipStream_t st) {
-  k_ch_fields<T><<<blocks_for(g.NZL), kThreads, 0, st>>>(g, om, w, phi, dw, dphi, mean, kx, ky, out);
+                            const double* ky, cpx<T>* out, hipStream_t st, int six) {
+  k_ch_fields<T><<<blocks_for(g.NZL), kThreads, 0, st>>>(g, om, w, phi, dw, dphi, mean, kx, ky, out, six);
   return hipGetLastError();
 }
 template <typename T>
@@ -395,11 +402,11 @@ hipError_t launch_ch_mean_io(const ChanGeom& g, const cpx<double>* in, cpx<doubl
 template hipError_t launch_ch_fields<float>(const ChanGeom&, const cpx<double>*, const cpx<double>*,
                                             const cpx<double>*, const cpx<double>*, const cpx<double>*,
                                             const cpx<double>*, const double*, const double*, cpx<float>*,
-                                            hipStream_t);
+                                            hipStream_t, int);
 template hipError_t launch_ch_fields<double>(const ChanGeom&, const cpx<double>*, const cpx<double>*,
                                              const cpx<double>*, const cpx<double>*, const cpx<double>*,
                                              const cpx<double>*, const double*, const double*, cpx<double>*,
-                                             hipStream_t);
+                                             hipStream_t, int);
 template hipError_t launch_ch_products<float>(const ChanGeom&, float*, double, hipStream_t);
 template hipError_t launch_ch_products<double>(const ChanGeom&, double*, double, hipStream_t);
 

@@ -29,11 +29,12 @@ struct ChanCoef {
 };
 
 // the 7 spectral fields u, v, w, phi, i kx phi, i ky phi, D phi (precision T);
-// u, v, w only in single phase
+// with six, the 6 fields u, v, w, phi, i ky phi, D phi (the fused x stage
+// forms i kx phi itself); u, v, w only in single phase
 template <typename T>
 hipError_t launch_ch_fields(const ChanGeom& g, const cpx<double>* om, const cpx<double>* w, const cpx<double>* phi,
                             const cpx<double>* dw, const cpx<double>* dphi, const cpx<double>* mean, const double* kx,
-                            const double* ky, cpx<T>* out, hipStream_t st);
+                            const double* ky, cpx<T>* out, hipStream_t st, int six = 0);
 // pointwise products, 7 physical fields in, 8 out (in place, [8][P]); single
 // phase 3 in, the 6 components of -u_i u_j out
 template <typename T>

@@ -31,7 +31,7 @@ class PsmsError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("geometry", ctypes.c_int32), ("n", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("re", ctypes.c_double), ("we", ctypes.c_double),
+                ("cube", ctypes.c_int32), ("re", ctypes.c_double), ("we", ctypes.c_double),
                 ("ch", ctypes.c_double), ("pe", ctypes.c_double), ("dt", ctypes.c_double),
                 ("s", ctypes.c_double)]
 
@@ -72,6 +72,7 @@ _SIGS = {
     "psms_channel_get_state": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
     "psms_channel_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "psms_channel_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diag)]),
+    "psms_channel_set_graphs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "psms_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
     "psms_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Params), ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p]),
@@ -85,6 +86,7 @@ _SIGS = {
     "psms_solve_helmholtz": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.c_void_p, ctypes.c_void_p]),
     "psms_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diag)]),
+    "psms_pressure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "psms_index_maps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "psms_band_modes": (ctypes.c_int64, [ctypes.c_void_p]),
     "psms_stage_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
@@ -156,9 +158,10 @@ def _check(code: int):
         raise PsmsError(code, lib().psms_last_error().decode())
 
 
-def make_params(n, re, we, ch, pe, dt, s=0.0, precision="fp64", geometry=BOX) -> Params:
+def make_params(n, re, we, ch, pe, dt, s=0.0, precision="fp64", geometry=BOX, cube="grid") -> Params:
     prec = {"fp64": FP64, "mixed": MIXED}[precision] if isinstance(precision, str) else int(precision)
-    return Params(geometry, int(n), prec, 0, float(re), float(we), float(ch), float(pe), float(dt), float(s or 0.0))
+    cb = {"grid": 0, "exact": 1}[cube] if isinstance(cube, str) else int(cube)
+    return Params(geometry, int(n), prec, cb, float(re), float(we), float(ch), float(pe), float(dt), float(s or 0.0))
 
 
 def workspace_bytes(params: Params) -> int:
@@ -174,10 +177,10 @@ def _ptr(t):
 class Solver:
     """One periodic-box NS+CH context on the current GPU and torch stream."""
 
-    def __init__(self, n, re, we, ch, pe, dt, s=0.0, precision="fp64", device="cuda", stream=None):
+    def __init__(self, n, re, we, ch, pe, dt, s=0.0, precision="fp64", device="cuda", stream=None, cube="grid"):
         import torch
         self.torch = torch
-        self.params = make_params(n, re, we, ch, pe, dt, s, precision)
+        self.params = make_params(n, re, we, ch, pe, dt, s, precision, cube=cube)
         self.n = int(n)
         self.precision = precision
         self.device = torch.device(device)
@@ -288,6 +291,13 @@ class Solver:
         _check(lib().psms_diagnostics(self.ctx, ctypes.byref(d)))
         return dict(mean_phi=d.mean_phi, ke=d.ke, grad2=d.grad2, max_div=d.max_div,
                     nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl)
+
+    def pressure(self):
+        """p_hat of the current state, complex128 [n, n, n/2+1]."""
+        n = self.n
+        out = self.torch.empty((n, n, n // 2 + 1), dtype=self.torch.complex128, device=self.device)
+        _check(lib().psms_pressure(self.ctx, _ptr(out)))
+        return out
 
     def index_maps(self):
         m = int(lib().psms_band_modes(self.ctx))
@@ -679,6 +689,9 @@ class Channel:
         _check(lib().psms_channel_get_state(self.h, _ptr(st), _ptr(mn), _ptr(hs) if hs is not None else None,
                                             _ptr(hm) if hm is not None else None))
         return (st, mn, hs, hm) if with_history else (st, mn)
+
+    def set_graphs(self, enable):
+        _check(lib().psms_channel_set_graphs(self.h, 1 if enable else 0))
 
     def diagnostics(self):
         d = Diag()

@@ -30,7 +30,7 @@ def test_workspace_bytes_grows_with_n_and_precision():
 
 
 @pytest.mark.parametrize("field,value", [("re", 0.0), ("we", -1.0), ("ch", float("nan")), ("pe", 0.0),
-                                         ("dt", -1e-3), ("n", 100), ("n", 0), ("precision", 7), ("reserved", 1)])
+                                         ("dt", -1e-3), ("n", 100), ("n", 0), ("precision", 7), ("cube", 2), ("cube", -1)])
 def test_invalid_params_rejected(field, value):
     p = psms.make_params(32, 100, 1, 0.05, 20, 1e-3)
     setattr(p, field, value)

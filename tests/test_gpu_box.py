@@ -376,3 +376,112 @@ def test_diagnostics_between_steps_leave_the_trajectory_unchanged(precision):
     side.synchronize()
     assert d["nstep"] == 2 and d["cfl"] > 0.0
     assert torch.equal(ua[0], ub[0]) and torch.equal(ua[1], ub[1])
+
+
+# ------------------------------------------------------------------ exact cube, pressure
+
+def _solver_cube(p, precision="fp64", stream=None):
+    from paper_2406_01322_amd.psms import Solver
+    return Solver(p["n"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision, cube="exact",
+                  stream=stream)
+
+
+@pytest.mark.parametrize("case", ["single_drop_32", "drops4_48", "drops2_64", "drops3_96"])
+@pytest.mark.parametrize("nprev", [0, 1])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_exact_cube_one_step_parity(case, nprev, precision, tol, record_error):
+    """phi^3 formed on the padded grid (48, 64, 96, 128 points for N = 32, 48, 64, 96)
+    against the oracle's exact cube, one step from the oracle's state."""
+    p, u, phi, _ = _oracle_state(case)
+    prm = box.Params(**p, cube="exact")
+    st = box.run(box.init_state(u, phi, prm), prm, nprev)
+    ref = box.step(st, prm)
+    s = _solver_cube(p, precision)
+    _load(s, st)
+    s.step(1)
+    uh, ph, hist = (_host(t) for t in s.get_state(with_history=True))
+    for i in range(3):
+        assert record_error("u%d" % i, rel_l2(uh[i], ref["uh"][i]), tol) < tol, i
+    assert record_error("phi", rel_l2(ph, ref["ph"]), tol) < tol
+    assert record_error("hphi", rel_l2(hist[3], ref["hphi"]), tol) < tol
+    assert ph[0, 0, 0] == st["ph"][0, 0, 0]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_exact_cube_full_size_128(precision, tol):
+    """The 128^3 sixteen-drop workload with the exact cube (padded grid 192^3)."""
+    p, u, phi, _ = _oracle_state("drops16_128")
+    prm = box.Params(**p, cube="exact")
+    st = box.step(box.init_state(u, phi, prm), prm)
+    ref = box.step(st, prm)
+    s = _solver_cube(p, precision)
+    _load(s, st)
+    s.step(1)
+    uh, ph = (_host(t) for t in s.get_state())
+    for i in range(3):
+        assert rel_l2(uh[i], ref["uh"][i]) < tol, i
+    assert rel_l2(ph, ref["ph"]) < tol
+
+
+def test_exact_cube_graph_replay_matches_eager_steps():
+    p, prm, st = _prepare("drops4_48", 0)
+    eager = _solver_cube(p)
+    eager.set_graphs(False)
+    _load(eager, st)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g = _solver_cube(p, stream=side)
+        _load(g, st)
+    for k in (1, 2, 3):
+        eager.step(k)
+        with torch.cuda.stream(side):
+            g.step(k)
+            a = g.get_state()
+        side.synchronize()
+        b = eager.get_state()
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_exact_cube_is_refused_where_unsupported():
+    from paper_2406_01322_amd import psms
+    from paper_2406_01322_amd.psms import PsmsError
+    with pytest.raises(PsmsError) as e:
+        _solver_cube(_params(256))
+    assert e.value.code == -4
+    prm = psms.make_params(32, 100, 1, 0.05, 20, 1e-3, cube="exact")
+    import ctypes
+    b = ctypes.c_size_t(0)
+    assert psms.lib().psms_batch_workspace_bytes(1, ctypes.byref(prm), ctypes.byref(b)) == -4
+    assert psms.lib().psms_adjoint_workspace_bytes(ctypes.byref(prm), 4, 2, ctypes.byref(b)) == -4
+
+
+@pytest.mark.parametrize("case", ["single_drop_32", "drops4_48", "drops2_64"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_pressure_parity(case, precision, tol, record_error):
+    p, prm, st = _prepare(case, 1)
+    want = box.pressure(st, prm)
+    s = _solver(p, precision)
+    _load(s, st)
+    got = _host(s.pressure())
+    assert record_error("p", rel_l2(got, want), tol) < tol
+    # the step after a pressure evaluation is unchanged
+    s.step(1)
+    uh, ph = (_host(t) for t in s.get_state())
+    ref = box.step(st, prm)
+    assert rel_l2(uh, ref["uh"]) < tol and rel_l2(ph, ref["ph"]) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_laplace_pressure_jump_on_the_gpu(precision):
+    """A resting spherical drop (R = 1.5, Ch = 0.12, We = 2, N = 64): the pressure jump
+    between the drop's centre and the far corner is the Laplace pressure 2 / (We R) to 1%,
+    i.e. the Korteweg force carries surface tension 1/We (eq. kort)."""
+    n, ch, we, R = 64, 0.12, 2.0, 1.5
+    p = dict(n=n, re=100.0, we=we, ch=ch, pe=10.0, dt=1e-3)
+    phi = synth.drops_phi(n, np.array([[np.pi, np.pi, np.pi]]), R, ch)
+    s = _solver(p, precision)
+    s.init_state(_dev(np.zeros((3, n, n, n))), _dev(phi))
+    pr = np.fft.irfftn(_host(s.pressure()), s=(n, n, n), norm="forward")
+    jump = pr[n // 2, n // 2, n // 2] - pr[0, 0, 0]
+    assert abs(jump - 2.0 / (we * R)) < 0.01 * 2.0 / (we * R), jump
