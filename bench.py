@@ -227,6 +227,30 @@ def bench_adjoint(nsteps=50, seg_len=10):
             "backward_over_forward": (t2 - t1) / (t1 - t0)}
 
 
+def bench_exact_cube(steps=50, precision="mixed"):
+    """The 128^3 workload with the exact cube of phi (formed on the padded 192^3 grid)
+    instead of the grid cube: ms per step (graph replay, HIP events)."""
+    import torch
+    from paper_2406_01322_amd import synth
+    from paper_2406_01322_amd.psms import Solver
+    p, u, phi = synth.box_case("drops16_128")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = Solver(p["n"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision, cube="exact",
+                   stream=stream)
+        s.init_state(torch.from_numpy(u).cuda(), torch.from_numpy(phi).cuda())
+        s.step(3)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.step(steps)
+        e1.record(stream)
+        e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"n": p["n"], "padded_grid": 192, "precision": precision, "steps": steps, "ms_per_step": ms,
+            "value": p["n"] ** 3 / (ms * 1e-3), "unit": "grid-points*timesteps/s"}
+
+
 def bench_wall_solve(reps=20):
     """The channel's implicit wall-normal solves (omega_z, w with the influence matrix,
     the two CH Helmholtz problems, u and v) for kx = 0..85, ky = -42..42 (7310 lines) of
@@ -291,6 +315,66 @@ def bench_channel(steps=20, warmup=2, case="chan_256"):
         del c
     out["unit"] = "grid-points*timesteps/s"
     return out
+
+
+def cpu_baseline_threaded(n, p, u, phi, budget_s=10.0):
+    """The same oracle with its transforms on all the host's cores (scipy.fft,
+    workers = the cores this process may use): a second CPU row beside the
+    single-threaded one."""
+    from oracle import box
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    box.set_fft_workers(cores)
+    try:
+        prm = box.Params(**p)
+        st = box.init_state(u, phi, prm)
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            st = box.step(st, prm)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > budget_s or steps >= 20:
+                break
+    finally:
+        box.set_fft_workers(1)
+    return dict(value=n ** 3 * steps / el, unit="grid-points*timesteps/s", cores=cores, kind="oracle",
+                sample="%d FP64 oracle steps of the %d^3 workload after init, transforms by scipy.fft with "
+                       "%d workers, %.1f s" % (steps, n, cores, el))
+
+
+def channel_oracle_timing(case="chan_256"):
+    """One FP64 oracle step of the channel workload from its initial state (every
+    (kx, ky) line's tau problems by dense LU, one stacked numpy solve)."""
+    from oracle import channel_step as cs
+    from paper_2406_01322_amd import synth
+    p, u, v, w, phi = synth.channel_case(case)
+    prm = cs.ChannelParams(**{k: x for k, x in p.items() if k != "single_phase"})
+    st = cs.init_state(u, v, w, phi, prm)
+    t0 = time.perf_counter()
+    cs.step(st, prm)
+    el = time.perf_counter() - t0
+    npts = (p["nc"] + 1) * p["ny"] * p["nx"]
+    return dict(value=npts / el, unit="grid-points*timesteps/s", cores=1, kind="oracle (dense LU)",
+                sample="1 FP64 oracle step of the %d x %d x %d channel from its initial state "
+                       "(wall-normal tau problems by dense LU), %.1f s" % (p["nx"], p["ny"], p["nc"] + 1, el))
+
+
+def channel_model_bytes(nx, ny, nc, mixed):
+    """The step byte model of the channel in the box's convention: 30 physical passes,
+    the FP64 state (omega_z, w, phi on every Chebyshev mode) read twice and written once
+    with its history read and written, 8 right-hand-side fields written and read at
+    the products' Chebyshev cut."""
+    hx, cy = (nx - 1) // 3 + 1, 2 * ((ny - 1) // 3) + 1
+    kz = (2 * nc - 1) // 3
+    P = (nc + 1) * ny * nx
+    w_phys = 4 if mixed else 8
+    return w_phys * 30 * P + 8 * 2 * 20 * hx * cy * (nc + 1) + w_phys * 2 * 16 * hx * cy * (kz + 1)
+
+
+def roofline_entry(nbytes, ms):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "model_bytes_per_step": nbytes, "ms_per_step": ms}
 
 
 def cpu_baseline(n, p, u, phi, budget_s=20.0):
@@ -419,14 +503,33 @@ def main():
     if not args.no_forms:
         out["forms"] = {}
         for name, fn in (("batched", bench_batch), ("adjoint", bench_adjoint), ("channel_wall_solve", bench_wall_solve),
-                         ("channel_step", bench_channel),
+                         ("channel_step", bench_channel), ("box_exact_cube", bench_exact_cube),
                          ("channel_single_phase_step", lambda: bench_channel(10, 2, "chan_sp_256"))):
             out["forms"][name] = fn()
             print("[bench] %s: %s" % (name, {k: v for k, v in out["forms"][name].items() if k != "groups"}),
                   file=sys.stderr, flush=True)
+    # step-level HBM rooflines of the other paths (byte model / step time)
+    out["rooflines"] = {}
+    if "fp64" in res:
+        out["rooflines"]["box_fp64_step"] = roofline_entry(step_model_bytes(n, False), res["fp64"]["ms_per_step"])
+    out["rooflines"]["box_%s_step" % head] = roofline_entry(step_bytes, r["ms_per_step"])
+    forms = out.get("forms", {})
+    if "channel_step" in forms:
+        cf = forms["channel_step"]
+        nx, ny, nz = cf["grid"]
+        for prec in ("mixed", "fp64"):
+            out["rooflines"]["channel_%s_step" % prec] = roofline_entry(
+                channel_model_bytes(nx, ny, nz - 1, prec == "mixed"), cf[prec]["ms_per_step"])
+    if "batched" in forms:
+        bf = forms["batched"]
+        nb = sum(cnt * step_model_bytes(nn, True) for nn, cnt in bf["groups"])
+        out["rooflines"]["batch_mixed_step"] = roofline_entry(nb, bf["ms_per_step"])
     if not args.no_cpu:
         out["cpu_baseline"], kept = cpu_baseline(n, p, u, phi)
+        out["cpu_baseline_threaded"] = cpu_baseline_threaded(n, p, u, phi)
         out["vs_oracle_rel_l2_one_step"] = oracle_error(n, p, kept[0], kept[1])
+        if not args.no_forms:
+            out["cpu_channel_oracle"] = channel_oracle_timing()
     print(json.dumps(out), flush=True)
 
 

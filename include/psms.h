@@ -98,6 +98,8 @@ typedef struct psms_diag {
   int32_t nonfinite; /* number of modes holding a non-finite value */
   int32_t nstep;     /* steps taken since init_state / set_state(nstep) */
   double cfl;        /* dt max_x (|u| + |v| + |w|) / dx, dx = 2 pi / n (physical grid) */
+  double sphi0_re;   /* box: S_phi(k = 0) of the last step before it was set to zero (Sec. 2.2 */
+  double sphi0_im;   /* step ii): every CH term is a divergence, so rounding level; 0 before a step */
 } psms_diag;
 
 typedef struct psms_ctx psms_ctx;

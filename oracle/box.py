@@ -83,13 +83,29 @@ def dealias_mask(n: int) -> np.ndarray:
 # transforms (library primitive: numpy pocketfft)
 # ---------------------------------------------------------------------------
 
+_FFT_WORKERS = 1
+
+
+def set_fft_workers(n: int) -> None:
+    """Transforms by numpy (n = 1, the default) or by scipy.fft with n threads:
+    the same FP64 transforms, used only to time the oracle on several cores."""
+    global _FFT_WORKERS
+    _FFT_WORKERS = max(1, int(n))
+
+
 def fwd(f: np.ndarray) -> np.ndarray:
     """Physical -> spectral over the last three axes, with the 1/N^3 factor."""
+    if _FFT_WORKERS > 1:
+        import scipy.fft
+        return scipy.fft.rfftn(f, axes=(-3, -2, -1), norm="forward", workers=_FFT_WORKERS)
     return np.fft.rfftn(f, axes=(-3, -2, -1), norm="forward")
 
 
 def inv(fh: np.ndarray, n: int) -> np.ndarray:
     """Spectral -> physical over the last three axes, unnormalised sum."""
+    if _FFT_WORKERS > 1:
+        import scipy.fft
+        return scipy.fft.irfftn(fh, s=(n, n, n), axes=(-3, -2, -1), norm="forward", workers=_FFT_WORKERS)
     return np.fft.irfftn(fh, s=(n, n, n), axes=(-3, -2, -1), norm="forward")
 
 

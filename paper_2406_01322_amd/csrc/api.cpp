@@ -428,6 +428,7 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
   c->h_box.hist = c->hist;
   c->h_box.sc = step_coef(c);
   c->h_box.csig = 3.0 / std::sqrt(8.0) * p->ch / p->we;
+  c->h_box.sphi0 = reinterpret_cast<cpx<double>*>(c->diag_out + 6);
   c->box_ab1 = -1;
   for (int i = 0; i < 4; ++i) c->variant[i] = 2;
   c->use_graph = 1;
@@ -442,7 +443,9 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
     t64[m] = cpx<double>{std::cos(a), std::sin(a)};
     t32[m] = cpx<float>{float(t64[m].re), float(t64[m].im)};
   }
-  hipError_t e = hipMemcpyAsync(c->tw64, t64.data(), n * sizeof(cpx<double>), hipMemcpyHostToDevice, c->stream);
+  hipError_t e = hipMemsetAsync(c->diag_out, 0, 8 * sizeof(double), c->stream);   // S_phi(0) before a step: 0
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->tw64, t64.data(), n * sizeof(cpx<double>), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->tw32, t32.data(), n * sizeof(cpx<float>), hipMemcpyHostToDevice, c->stream);
   c->m = lay.m;
   std::vector<cpx<double>> m64(lay.m);
@@ -684,7 +687,7 @@ int psms_diagnostics(psms_ctx* c, psms_diag* h_out) {
     if (e == hipSuccess) e = psms::launch_abs_accum(phys, acc, np, c->p.dt * n / (2.0 * M_PI), k == 0, c->stream);
   }
   if (e == hipSuccess) e = psms::launch_max(acc, np, c->diag, kDiagBlocks, c->diag_out + 5, c->stream);
-  double h[6];
+  double h[8];
   if (e == hipSuccess) e = hipMemcpyAsync(h, c->diag_out, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics");
@@ -695,6 +698,8 @@ int psms_diagnostics(psms_ctx* c, psms_diag* h_out) {
   h_out->nonfinite = int32_t(h[4]);
   h_out->nstep = c->nstep;
   h_out->cfl = h[5];
+  h_out->sphi0_re = h[6];
+  h_out->sphi0_im = h[7];
   return PSMS_OK;
 }
 
@@ -2004,7 +2009,7 @@ int psms_channel_diagnostics(psms_channel* c, psms_diag* h_out) {
   double* part = c->at<double>(L.diag);
   double* part2 = part + 4 * kChanDiagBlocks;
   double* out = part2 + 4 * kChanDiagBlocks;
-  const int nb1 = int(std::min<long long>(kChanDiagBlocks, (g.NL + 255) / 256));
+  const int nb1 = int(std::min<long long>(kChanDiagBlocks, (g.NL + 3) / 4));
   const int nb2 = int(std::min<long long>(kChanDiagBlocks, (g.P + 255) / 256));
   // D w and D phi (the step's scratch: the next step recomputes them), the
   // per-line sums, then u, v, w in FP64 on the collocation grid for the CFL
@@ -2036,6 +2041,8 @@ int psms_channel_diagnostics(psms_channel* c, psms_diag* h_out) {
   h_out->nonfinite = int32_t(h[4]);
   h_out->nstep = c->nstep;
   h_out->cfl = h[5];
+  h_out->sphi0_re = 0.0;   // the channel zeroes no mode of S_phi
+  h_out->sphi0_im = 0.0;
   return PSMS_OK;
 }
 

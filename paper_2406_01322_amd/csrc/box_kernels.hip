@@ -655,6 +655,7 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
         Sp.re += sc.e_coef * k2 * ph.re;
         Sp.im += sc.e_coef * k2 * ph.im;
         if (k2 == 0.0) {
+          if (bx.sphi0) st_global(bx.sphi0, Sp);   // the mean of S_phi, a divergence: rounding level
           Sx = Sy = Sz = Sp = cpx<double>{0.0, 0.0};
         } else {  // Leray projection
           const double ir = 1.0 / k2;

@@ -36,6 +36,7 @@ struct BoxDev {
   cpx<double>* hist;
   StepCoef sc;
   double csig;     // (3 / sqrt 8) Ch / We
+  cpx<double>* sphi0 = nullptr;   // if set, the z stage stores S_phi(0) here before zeroing it
 };
 
 // Batched transform along a strided axis: line l = o * inner + i holds

@@ -115,6 +115,153 @@ __global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx
   }
 }
 
+// The same transform through one FFT of nc points instead of 2 nc (the
+// half-length route to the DCT-I; Sec. 3.2.1 names it as the next step).  With
+// the end points halved, C_k = sum_j w_j x_j cos(pi j k / nc) (w_0 = w_nc = 1/2)
+// is obtained from Z = FFT_nc(y),
+//   y_0 = (x_0 + x_nc) / 2,  y_j = (x_j + x_{nc-j}) / 2 - sin(pi j / nc) (x_j - x_{nc-j}):
+// the even part of y carries the cosines of even order and the odd part, with
+// the sine, the differences of neighbouring odd orders, so
+//   C_{2k} = (Z_k + Z_{nc-k}) / 2,
+//   C_{2k+1} = C_{2k-1} + (i / 2) (Z_k - Z_{nc-k}),  C_1 = sum_j w_j x_j cos(pi j / nc)
+// (complex x: the real and imaginary parts go through the one FFT together).
+// The odd orders are a running sum over k, formed in FP64: each thread of a
+// line sums a contiguous run of k, and the runs' totals give every thread its
+// starting value.  dir = +1: x = f, a_n = 2 C_n / (nc cbar_n); dir = -1:
+// x = cbar a, f_j = C_j.  tw_g: exp(-i pi m / nc), m < 2 nc (or NULL).
+template <typename T, int NC>
+__global__ void __launch_bounds__(1024) k_dct_half(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                                  long long nlines, int dir, long long fstride,
+                                                  const cpx<T>* __restrict__ tw_g, cpx<double>* __restrict__ out64,
+                                                  int kz) {
+  using P = Plan<NC>;
+  using G = CTile<P>;
+  constexpr int E = G::E, L = G::L, LP = L + 1, TT = G::TT;
+  constexpr int RI = first_radix<P, -1>(), RO = last_radix<P, -1>();
+  constexpr int NK = NC / 2 - 1;                 // increments of the odd orders, k = 1 .. NC/2 - 1
+  constexpr int CS = (NK + TT - 1) / TT;         // a thread's run of k
+  static_assert(2 * NC * LP * int(sizeof(cpx<T>)) + 3 * NC * int(sizeof(cpx<T>)) <= 160 * 1024, "LDS");
+  static_assert(TT * L * 2 * 16 <= NC * LP * int(sizeof(cpx<T>)), "partial sums fit one exchange buffer");
+  __shared__ cpx<T> tw2[2 * NC];                 // exp(-i pi m / NC)
+  __shared__ cpx<T> tw[NC];                      // exp(-2 pi i m / NC)
+  __shared__ cpx<T> lds[2][NC * LP];
+  const int tid = threadIdx.x;
+  const int line = tid % L, t = tid / L;
+  in += (long long)blockIdx.y * fstride;
+  out += (long long)blockIdx.y * fstride;
+  if (out64) out64 += (long long)blockIdx.y * fstride;
+  for (int i = tid; i < 2 * NC; i += blockDim.x) {
+    cpx<T> w;
+    if (tw_g) {
+      w = tw_g[i];
+    } else {
+      double s, c;
+      sincospi(-double(i) / double(NC), &s, &c);
+      w = cpx<T>{T(c), T(s)};
+    }
+    tw2[i] = w;
+    if (!(i & 1)) tw[i >> 1] = w;
+  }
+  const long long l = (long long)blockIdx.x * L + line;
+  const bool valid = l < nlines;
+  __syncthreads();
+  // y at the positions the FFT starts from, and this thread's share of C_1
+  cpx<T> v[E];
+  double c1r = 0.0, c1i = 0.0;
+#pragma unroll
+  for (int b = 0; b < E / RI; ++b)
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int j = slot_pos<P, RI>(t, b, r);    // 0 .. NC-1
+      cpx<T> y = {T(0), T(0)};
+      if (valid) {
+        cpx<T> xa = in[(long long)j * nlines + l];
+        cpx<T> xb = in[(long long)(NC - j) * nlines + l];   // x_{NC-j} (x_NC for j = 0)
+        if (dir < 0 && j == 0) {                 // x = cbar a: the end points doubled
+          xa = cpx<T>{T(2) * xa.re, T(2) * xa.im};
+          xb = cpx<T>{T(2) * xb.re, T(2) * xb.im};
+        }
+        const T cj = tw2[j].re, sj = -tw2[j].im;   // cos, sin (pi j / NC)
+        if (j == 0) {
+          y = cpx<T>{T(0.5) * (xa.re + xb.re), T(0.5) * (xa.im + xb.im)};
+          c1r += 0.5 * double(xa.re) - 0.5 * double(xb.re);   // w_0 x_0 cos 0 + w_NC x_NC cos pi
+          c1i += 0.5 * double(xa.im) - 0.5 * double(xb.im);
+        } else {
+          const cpx<T> sm = {T(0.5) * (xa.re + xb.re), T(0.5) * (xa.im + xb.im)};
+          const cpx<T> df = {xa.re - xb.re, xa.im - xb.im};
+          y = cpx<T>{sm.re - sj * df.re, sm.im - sj * df.im};
+          c1r += double(cj) * double(xa.re);
+          c1i += double(cj) * double(xa.im);
+        }
+      }
+      v[b * RI + r] = y;
+    }
+  int par = 0;
+  fft_line<T, P, -1>(v, lds[0], lds[1], par, t, IdxPosMajor{LP, line}, tw);
+  // Z in natural order in lds[0]; the partial sums in lds[1] (as doubles)
+  __syncthreads();
+  const IdxPosMajor idx{LP, line};
+#pragma unroll
+  for (int b = 0; b < E / RO; ++b)
+#pragma unroll
+    for (int r = 0; r < RO; ++r) lds[0][idx(slot_pos<P, RO>(t, b, r))] = v[b * RO + r];
+  double* ps = reinterpret_cast<double*>(lds[1]);     // [2][TT][L] pairs (re, im)
+  ps[2 * (t * L + line)] = c1r;
+  ps[2 * (t * L + line) + 1] = c1i;
+  __syncthreads();
+  double s1r = 0.0, s1i = 0.0;                         // C_1 of the line
+#pragma unroll 4
+  for (int u = 0; u < TT; ++u) {
+    s1r += ps[2 * (u * L + line)];
+    s1i += ps[2 * (u * L + line) + 1];
+  }
+  // this thread's run of increments (i/2)(Z_k - Z_{NC-k}), k in [k0, k1)
+  const int k0 = 1 + t * CS, k1 = (k0 + CS <= NK + 1) ? k0 + CS : NK + 1;
+  double rr = 0.0, ri = 0.0;
+#pragma unroll 2
+  for (int k = k0; k < k1; ++k) {
+    const cpx<T> a = lds[0][idx(k)], c = lds[0][idx(NC - k)];
+    rr += -0.5 * (double(a.im) - double(c.im));
+    ri += 0.5 * (double(a.re) - double(c.re));
+  }
+  ps[2 * TT * L + 2 * (t * L + line)] = rr;
+  ps[2 * TT * L + 2 * (t * L + line) + 1] = ri;
+  __syncthreads();
+  if (!valid) return;
+  auto put = [&](int n, double re, double im) {
+    if (dir > 0) {
+      const double sc = 2.0 / (double(NC) * ((n == 0 || n == NC) ? 2.0 : 1.0));
+      re *= sc;
+      im *= sc;
+    }
+    if (out64)
+      out64[(long long)n * nlines + l] = (n > kz) ? cpx<double>{0.0, 0.0} : cpx<double>{re, im};
+    else
+      out[(long long)n * nlines + l] = cpx<T>{T(re), T(im)};
+  };
+  // even orders
+#pragma unroll 1
+  for (int k = t; k <= NC / 2; k += TT) {
+    const cpx<T> a = lds[0][idx(k)], c = lds[0][idx((NC - k) % NC)];
+    put(2 * k, 0.5 * (double(a.re) + double(c.re)), 0.5 * (double(a.im) + double(c.im)));
+  }
+  // odd orders: C_1 plus the runs before this thread's, then its own run
+  double ar = s1r, ai = s1i;
+#pragma unroll 4
+  for (int u = 0; u < t; ++u) {
+    ar += ps[2 * TT * L + 2 * (u * L + line)];
+    ai += ps[2 * TT * L + 2 * (u * L + line) + 1];
+  }
+  if (t == 0) put(1, ar, ai);
+#pragma unroll 1
+  for (int k = k0; k < k1; ++k) {
+    const cpx<T> a = lds[0][idx(k)], c = lds[0][idx(NC - k)];
+    ar += -0.5 * (double(a.im) - double(c.im));
+    ai += 0.5 * (double(a.re) - double(c.re));
+    put(2 * k + 1, ar, ai);
+  }
+}
+
 // Coefficients of d/dz: b_nc = 0, c_{m} b_{m} = b_{m+2} + 2 (m+1) a_{m+1} for
 // m = nc-1 .. 0 (c_0 = 2, else 1).  The recurrence links m to m+2 only, so the
 // even and odd outputs are two independent chains: one thread per (line,
@@ -204,6 +351,25 @@ __global__ void k_cheb_batch(ChebBatch b, int nc, long long nlines, const double
 // plus the constants top_c, bot_c.  g may be NULL (zero).  xw: nc+1 doubles
 // per line of scratch.
 
+// The coefficients of the tau rows that depend only on the index n:
+// q1 = 1 / (4 n (n - 1)), q2 = 1 / (2 (n^2 - 1)), q3 = 1 / (4 n (n + 1)), n >= 2,
+// evaluated at compile time (correctly rounded, as the run-time division would
+// be) and read with wave-uniform addresses, so no recurrence step divides by them.
+struct TauQ {
+  double q[3][kTauQMax + 1];
+};
+constexpr TauQ make_tau_q() {
+  TauQ t{};
+  for (int n = 2; n <= kTauQMax; ++n) {
+    const double dn = double(n);
+    t.q[0][n] = 1.0 / (4.0 * dn * (dn - 1.0));
+    t.q[1][n] = 1.0 / (2.0 * (dn * dn - 1.0));
+    t.q[2][n] = 1.0 / (4.0 * dn * (dn + 1.0));
+  }
+  return t;
+}
+__constant__ TauQ kTauQ = make_tau_q();
+
 // downward sweep of parity p: a_i = X_i a_{i-1} + Y_i for the indices
 // n = p + 2 i, i = m..1 (X in xw, Y in f)
 __device__ __forceinline__ void helm_down(const cpx<double>* __restrict__ g, cpx<double>* __restrict__ f,
@@ -224,9 +390,7 @@ __device__ __forceinline__ void helm_down(const cpx<double>* __restrict__ g, cpx
     const double cm2 = (n - 2 == 0) ? 2.0 : 1.0;
     const double en = (n <= nc - 2) ? 1.0 : 0.0;
     const double en2 = (n + 2 <= nc - 2) ? 1.0 : 0.0;
-    const double q1 = 1.0 / (4.0 * dn * (dn - 1.0));
-    const double q2 = 1.0 / (2.0 * (dn * dn - 1.0));
-    const double q3 = 1.0 / (4.0 * dn * (dn + 1.0));
+    const double q1 = kTauQ.q[0][n], q2 = kTauQ.q[1][n], q3 = kTauQ.q[2][n];
     const double A = cm2 * be * q1;
     const double B = -(1.0 + en * be * q2);
     const double C = en2 * be * q3;
@@ -365,27 +529,25 @@ __global__ void k_helm_batch(HelmBatch b, int nc) {
 
 // The same problems with the elimination held on chip: one workgroup of 64
 // lines per (problem, parity) (blockIdx.z = parity, uniform in the
-// workgroup), X_i of each chain in registers (the loops over i are unrolled
-// for the compile-time NC, and i > m is skipped uniformly) and Y_i in LDS, so
-// that HBM sees only the right-hand side read and the solution written (32
-// bytes per coefficient instead of 104 through the scratch chains).  The
-// chain's right-hand side entries are first copied into the same LDS rows by
-// 16-byte global_load_lds copies, all in flight at once: each chain is one
-// thread's sequential recurrence and a workgroup is one wavefront, so loads
-// issued inside the recurrence would leave their latency exposed.  Same
-// condition at both walls only (bc 0 or 3); the arithmetic is that of
-// helm_line, in the same order.  With P.wh the w problem's influence
-// correction follows in the second upward sweep (HelmProblem).
+// workgroup), X_i of each chain in registers and Y_i in LDS, so that HBM sees
+// only the right-hand side read and the solution written (32 bytes per
+// coefficient instead of 104 through the scratch chains).  The loops over i
+// are unrolled for the compile-time NC (i > m is skipped uniformly), and the
+// tau-row coefficients come from the compile-time table kTauQ, which leaves one
+// FP64 division per step of the recurrence.  The chain's right-hand side entries are first
+// copied into the LDS rows by 16-byte global_load_lds copies, all in flight at
+// once: each chain is one thread's sequential recurrence and a workgroup is
+// one wavefront, so loads issued inside the recurrence would leave their
+// latency exposed.  Same condition at both walls only (bc 0 or 3); the
+// arithmetic is that of helm_line, in the same order.  With P.wh the w
+// problem's influence correction follows in the second upward sweep
+// (HelmProblem).
 template <int NC>
-__global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
+__device__ __forceinline__ void helm_reg_chain(const HelmProblem& P, cpx<double> (*Ys)[64], int tid, long long l,
+                                               int p) {
   constexpr int MM = NC / 2;                 // longest chain: parity 0, i = 0..MM
-  __shared__ cpx<double> Ys[MM + 1][64];
-  const HelmProblem& P = b.p[blockIdx.y];
-  const int p = blockIdx.z;
-  const int tid = threadIdx.x;
-  const long long l = (long long)blockIdx.x * 64 + tid;
-  const long long nl = P.nlines;
   const int m = (NC - p) / 2;
+  const long long nl = P.nlines;
   const cpx<double>* __restrict__ g = P.g;
   if (g) {
     // entries n = p + 2 i <= NC - 2 of this parity into row i (lane tid's
@@ -426,31 +588,27 @@ __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
   cpx<double> gm = G(p + 2 * m - 2), g0 = G(p + 2 * m), g2 = G(p + 2 * m + 2);
 #pragma unroll
   for (int i = MM; i >= 1; --i) {
-    if (i <= m) {
-      const int n = p + 2 * i;
-      const double dn = double(n);
-      const double cm2 = (n - 2 == 0) ? 2.0 : 1.0;
-      const double en = (n <= NC - 2) ? 1.0 : 0.0;
-      const double en2 = (n + 2 <= NC - 2) ? 1.0 : 0.0;
-      const double q1 = 1.0 / (4.0 * dn * (dn - 1.0));
-      const double q2 = 1.0 / (2.0 * (dn * dn - 1.0));
-      const double q3 = 1.0 / (4.0 * dn * (dn + 1.0));
-      const double A = cm2 * be * q1;
-      const double B = -(1.0 + en * be * q2);
-      const double C = en2 * be * q3;
-      const cpx<double> R = {-cm2 * gm.re * q1 + en * g0.re * q2 - en2 * g2.re * q3,
-                             -cm2 * gm.im * q1 + en * g0.im * q2 - en2 * g2.im * q3};
-      const double den = 1.0 / (B + C * Xn);
-      const double Xv = -A * den;
-      const cpx<double> Y = {(R.re - C * Yn.re) * den, (R.im - C * Yn.im) * den};
-      g2 = g0;
-      g0 = gm;
-      gm = G(n - 4);
-      X[i] = Xv;
-      Ys[i][tid] = Y;
-      Xn = Xv;
-      Yn = Y;
-    }
+    if (i > m) continue;                     // uniform: the odd chain is one shorter
+    const int n = p + 2 * i;
+    const double cm2 = (n - 2 == 0) ? 2.0 : 1.0;
+    const double en = (n <= NC - 2) ? 1.0 : 0.0;
+    const double en2 = (n + 2 <= NC - 2) ? 1.0 : 0.0;
+    const double q1 = kTauQ.q[0][n], q2 = kTauQ.q[1][n], q3 = kTauQ.q[2][n];
+    const double A = cm2 * be * q1;
+    const double B = -(1.0 + en * be * q2);
+    const double C = en2 * be * q3;
+    const cpx<double> R = {-cm2 * gm.re * q1 + en * g0.re * q2 - en2 * g2.re * q3,
+                           -cm2 * gm.im * q1 + en * g0.im * q2 - en2 * g2.im * q3};
+    const double den = 1.0 / (B + C * Xn);
+    const double Xv = -A * den;
+    const cpx<double> Y = {(R.re - C * Yn.re) * den, (R.im - C * Yn.im) * den};
+    g2 = g0;
+    g0 = gm;
+    gm = G(n - 4);
+    X[i] = Xv;
+    Ys[i][tid] = Y;
+    Xn = Xv;
+    Yn = Y;
   }
   // upward sweep 1: a_i = P_i a_0 + Q_i and the boundary row of this parity;
   // with the influence correction also sum n^2 P_i and sum n^2 Q_i
@@ -459,23 +617,22 @@ __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
   cpx<double> Qv = {0.0, 0.0}, SQ = {0.0, 0.0}, SQn = {0.0, 0.0};
 #pragma unroll
   for (int i = 0; i <= MM; ++i) {
-    if (i <= m) {
-      const int n = p + 2 * i;
-      if (i > 0) {
-        const cpx<double> Y = Ys[i][tid];
-        Pc = X[i] * Pc;
-        Qv = cpx<double>{X[i] * Qv.re + Y.re, X[i] * Qv.im + Y.im};
-      }
-      const double n2 = double(n) * double(n);
-      const double w = neu ? n2 : 1.0;
-      SP += w * Pc;
-      SQ.re += w * Qv.re;
-      SQ.im += w * Qv.im;
-      if (infl) {
-        SPn += n2 * Pc;
-        SQn.re += n2 * Qv.re;
-        SQn.im += n2 * Qv.im;
-      }
+    if (i > m) continue;
+    const int n = p + 2 * i;
+    if (i > 0) {
+      const cpx<double> Y = Ys[i][tid];
+      Pc = X[i] * Pc;
+      Qv = cpx<double>{X[i] * Qv.re + Y.re, X[i] * Qv.im + Y.im};
+    }
+    const double n2 = double(n) * double(n);
+    const double w = neu ? n2 : 1.0;
+    SP += w * Pc;
+    SQ.re += w * Qv.re;
+    SQ.im += w * Qv.im;
+    if (infl) {
+      SPn += n2 * Pc;
+      SQn.re += n2 * Qv.re;
+      SQn.im += n2 * Qv.im;
     }
   }
   // a_0, the influence coefficient, then upward sweep 2
@@ -504,12 +661,19 @@ __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
   put(p, a);
 #pragma unroll
   for (int i = 1; i <= MM; ++i) {
-    if (i <= m) {
-      const cpx<double> Y = Ys[i][tid];
-      a = cpx<double>{X[i] * a.re + Y.re, X[i] * a.im + Y.im};
-      put(p + 2 * i, a);
-    }
+    if (i > m) continue;
+    const cpx<double> Y = Ys[i][tid];
+    a = cpx<double>{X[i] * a.re + Y.re, X[i] * a.im + Y.im};
+    put(p + 2 * i, a);
   }
+}
+
+template <int NC>
+__global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
+  __shared__ cpx<double> Ys[NC / 2 + 1][64];
+  const HelmProblem& P = b.p[blockIdx.y];
+  const long long l = (long long)blockIdx.x * 64 + threadIdx.x;
+  helm_reg_chain<NC>(P, Ys, threadIdx.x, l, int(blockIdx.z));
 }
 
 // wh_n = (w_t + w_b)_n (even n) or (w_t - w_b)_n (odd n): the homogeneous
@@ -697,9 +861,20 @@ namespace {
 template <typename T, int N>
 hipError_t dct_n(const cpx<T>* in, cpx<T>* out, long long nlines, int dir, long long fstride, int nfield,
                  const cpx<T>* tw, cpx<double>* out64, int kz, hipStream_t st) {
-  using G = CTile<Plan<N>>;
-  const dim3 grid(unsigned((nlines + G::L - 1) / G::L), unsigned(nfield));
-  k_dct<T, N><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw, out64, kz);
+  // FP64 lines take the nc-point route (measured at nc = 128 on the channel
+  // workload: 56.7 us per launch against 72.1 us for the 2 nc-point FFT); FP32
+  // lines keep the 2 nc-point even extension (40.3 us against 43.4 us: the
+  // FP32 transform is cheaper than the nc-point route's extra loads and
+  // running-sum passes through LDS)
+  if constexpr (N >= 16 && sizeof(T) == 8) {   // nc = N / 2 >= 8
+    using G = CTile<Plan<N / 2>>;
+    const dim3 grid(unsigned((nlines + G::L - 1) / G::L), unsigned(nfield));
+    k_dct_half<T, N / 2><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw, out64, kz);
+  } else {
+    using G = CTile<Plan<N>>;
+    const dim3 grid(unsigned((nlines + G::L - 1) / G::L), unsigned(nfield));
+    k_dct<T, N><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw, out64, kz);
+  }
   return hipGetLastError();
 }
 unsigned blocks(long long n, int bs) {

@@ -9,6 +9,7 @@
 namespace psms {
 
 bool supported_nc(int nc);
+constexpr int kTauQMax = 256;   // largest nc of the tau solves
 
 template <typename T>
 hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, int dir, hipStream_t st);

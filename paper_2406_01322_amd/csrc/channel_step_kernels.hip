@@ -208,70 +208,109 @@ __device__ __forceinline__ void diag_uv(const ChanGeom& g, long long l, long lon
 __device__ __forceinline__ double rdot(cpx<double> a, cpx<double> b) { return a.re * b.re + a.im * b.im; }
 __device__ __forceinline__ bool bad(cpx<double> a) { return !isfinite(a.re) || !isfinite(a.im); }
 
-// One thread per (kx, ky) line; part[4 b + (0..3)] = block sums of the kinetic
-// energy and <|grad phi|^2>, the block max of |i kx u + i ky v + D w|, and the
-// number of non-finite state entries.
-__global__ void k_ch_diag_lines(ChanGeom g, const cpx<double>* __restrict__ om, const cpx<double>* __restrict__ w,
-                                const cpx<double>* __restrict__ phi, const cpx<double>* __restrict__ dw,
-                                const cpx<double>* __restrict__ dphi, const cpx<double>* __restrict__ mean,
-                                const double* __restrict__ kxl, const double* __restrict__ kyl,
-                                double* __restrict__ part) {
-  __shared__ double sh[4][kThreads];
-  double ke = 0.0, gr = 0.0, md = 0.0, nf = 0.0;
+// Four (kx, ky) lines per workgroup of 256 threads, one wavefront per line;
+// part[4 b + (0..3)] = block sums of the kinetic energy and <|grad phi|^2>,
+// the block max of |i kx u + i ky v + D w|, and the number of non-finite state
+// entries.  Each field of a line (u, v, w, phi, D phi) is staged in LDS and its
+// quadratic form sum_{m,n} G_mn Re(conj f_m f_n) is split over the lanes by m
+// (G_mn = 0 unless m and n have one parity).
+constexpr int kDiagNC = 256;   // largest nc
+__global__ void __launch_bounds__(256) k_ch_diag_lines(ChanGeom g, const cpx<double>* __restrict__ om,
+                                                       const cpx<double>* __restrict__ w,
+                                                       const cpx<double>* __restrict__ phi,
+                                                       const cpx<double>* __restrict__ dw,
+                                                       const cpx<double>* __restrict__ dphi,
+                                                       const cpx<double>* __restrict__ mean,
+                                                       const double* __restrict__ kxl, const double* __restrict__ kyl,
+                                                       double* __restrict__ part) {
+  __shared__ double It[2 * kDiagNC + 1];
+  __shared__ cpx<double> F[4][kDiagNC + 1];
+  __shared__ double sh[4][4];
   const int nc = g.nc;
-  PSMS_GRID_LOOP(l, g.NL) {
-    const double kx = kxl[l], ky = kyl[l];
-    // the quadratic forms sum_{m,n} G_mn Re(conj f_m f_n) of u, v, w, phi, D phi
-    double qu = 0.0, qv = 0.0, qw = 0.0, qp = 0.0, qd = 0.0;
-    for (int m = 0; m <= nc; ++m) {
-      const long long im = (long long)m * g.NL + l;
-      cpx<double> um, vm;
-      diag_uv(g, l, m, kx, ky, om, dw, mean, um, vm);
-      const cpx<double> wm = w[im], pm = g.sp ? cpx<double>{0.0, 0.0} : phi[im];
-      const cpx<double> dm = g.sp ? cpx<double>{0.0, 0.0} : dphi[im];
-      const double gmm = 0.5 * (cheb_int(2 * m) + 2.0);
-      qu += gmm * rdot(um, um);
-      qv += gmm * rdot(vm, vm);
-      qw += gmm * rdot(wm, wm);
-      qp += gmm * rdot(pm, pm);
-      qd += gmm * rdot(dm, dm);
-      for (int n = m & 1; n < m; n += 2) {   // pairs of one parity, each counted twice
-        const long long in = (long long)n * g.NL + l;
-        cpx<double> un, vn;
-        diag_uv(g, l, n, kx, ky, om, dw, mean, un, vn);
-        const double gmn = cheb_int(m + n) + cheb_int(m - n);   // 2 G_mn
-        qu += gmn * rdot(um, un);
-        qv += gmn * rdot(vm, vn);
-        qw += gmn * rdot(wm, w[in]);
-        if (!g.sp) {
-          qp += gmn * rdot(pm, phi[in]);
-          qd += gmn * rdot(dm, dphi[in]);
+  const int tid = threadIdx.x, lb = tid >> 6, lane = tid & 63;
+  for (int k2 = tid; k2 <= 2 * nc; k2 += blockDim.x) It[k2] = cheb_int(k2);
+  double ke = 0.0, gr = 0.0, md = 0.0, nf = 0.0;   // this wavefront's line sums (lane 0 keeps them)
+  const long long groups = (g.NL + 3) / 4;
+  for (long long grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    const long long l = grp * 4 + lb;
+    const bool ok = l < g.NL;                      // uniform within the wavefront
+    const double kx = ok ? kxl[l] : 0.0, ky = ok ? kyl[l] : 0.0;
+    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int nfld = g.sp ? 3 : 5;
+    for (int fld = 0; fld < nfld; ++fld) {
+      __syncthreads();                             // It ready / the previous field's reads done
+      if (ok) {
+        for (int n = lane; n <= nc; n += 64) {
+          const long long id = (long long)n * g.NL + l;
+          cpx<double> v;
+          if (fld < 2) {
+            cpx<double> uu, vv;
+            diag_uv(g, l, n, kx, ky, om, dw, mean, uu, vv);
+            v = fld ? vv : uu;
+          } else {
+            v = (fld == 2) ? w[id] : (fld == 3) ? phi[id] : dphi[id];
+          }
+          F[lb][n] = v;
         }
       }
-      // continuity of coefficient m, and the non-finite entries of the state
-      const cpx<double> dv = add(add(ti(kx, um), ti(ky, vm)), dw[im]);
-      md = fmax(md, sqrt(dv.re * dv.re + dv.im * dv.im));
-      nf += (bad(om[im]) ? 1.0 : 0.0) + (bad(w[im]) ? 1.0 : 0.0) + ((!g.sp && bad(phi[im])) ? 1.0 : 0.0);
-      if (l == 0) nf += (bad(mean[2 * m]) ? 1.0 : 0.0) + (bad(mean[2 * m + 1]) ? 1.0 : 0.0);
+      __syncthreads();
+      double acc = 0.0;
+      if (ok) {
+        for (int m = lane; m <= nc; m += 64) {
+          const cpx<double> fm = F[lb][m];
+          double br = 0.0, bi = 0.0;               // (G f)_m
+          for (int n = m & 1; n <= nc; n += 2) {
+            const double gmn = 0.5 * (It[m + n] + It[m > n ? m - n : n - m]);
+            br += gmn * F[lb][n].re;
+            bi += gmn * F[lb][n].im;
+          }
+          acc += fm.re * br + fm.im * bi;
+        }
+      }
+#pragma unroll
+      for (int s = 32; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
+      q[fld] = acc;
     }
-    const double wx = (kx == 0.0) ? 1.0 : 2.0;   // half spectrum: kx > 0 stands for +-kx
-    ke += 0.25 * wx * (qu + qv + qw);            // 1/2 <|u|^2>, <.> in z = (1/2) int dz
-    gr += 0.5 * wx * ((kx * kx + ky * ky) * qp + qd);
+    if (ok) {
+      // continuity and the non-finite entries, coefficient by coefficient
+      for (int n = lane; n <= nc; n += 64) {
+        const long long id = (long long)n * g.NL + l;
+        cpx<double> uu, vv;
+        diag_uv(g, l, n, kx, ky, om, dw, mean, uu, vv);
+        const cpx<double> dv = add(add(ti(kx, uu), ti(ky, vv)), dw[id]);
+        md = fmax(md, sqrt(dv.re * dv.re + dv.im * dv.im));
+        nf += (bad(om[id]) ? 1.0 : 0.0) + (bad(w[id]) ? 1.0 : 0.0) + ((!g.sp && bad(phi[id])) ? 1.0 : 0.0);
+        if (l == 0) nf += (bad(mean[2 * n]) ? 1.0 : 0.0) + (bad(mean[2 * n + 1]) ? 1.0 : 0.0);
+      }
+      const double wx = (kx == 0.0) ? 1.0 : 2.0;  // half spectrum: kx > 0 stands for +-kx
+      ke += 0.25 * wx * (q[0] + q[1] + q[2]);     // 1/2 <|u|^2>, <.> in z = (1/2) int dz
+      gr += 0.5 * wx * ((kx * kx + ky * ky) * q[3] + q[4]);
+    }
   }
-  const int t = threadIdx.x;
-  sh[0][t] = ke; sh[1][t] = gr; sh[2][t] = md; sh[3][t] = nf;
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    md = fmax(md, __shfl_xor(md, s));
+    nf += __shfl_xor(nf, s);
+  }
+  if (lane == 0) {
+    sh[lb][0] = ke;
+    sh[lb][1] = gr;
+    sh[lb][2] = md;
+    sh[lb][3] = nf;
+  }
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      sh[0][t] += sh[0][t + s];
-      sh[1][t] += sh[1][t + s];
-      sh[2][t] = fmax(sh[2][t], sh[2][t + s]);
-      sh[3][t] += sh[3][t + s];
+  if (tid == 0) {
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      a += sh[i][0];
+      b += sh[i][1];
+      c = fmax(c, sh[i][2]);
+      d += sh[i][3];
     }
-    __syncthreads();
-  }
-  if (t == 0) {
-    for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = sh[k][0];
+    part[4 * blockIdx.x + 0] = a;
+    part[4 * blockIdx.x + 1] = b;
+    part[4 * blockIdx.x + 2] = c;
+    part[4 * blockIdx.x + 3] = d;
   }
 }
 
@@ -347,9 +386,10 @@ __global__ void k_ch_diag_final(ChanGeom g, const double* __restrict__ part, int
 hipError_t launch_ch_diag_lines(const ChanGeom& g, const cpx<double>* om, const cpx<double>* w, const cpx<double>* phi,
                                 const cpx<double>* dw, const cpx<double>* dphi, const cpx<double>* mean,
                                 const double* kx, const double* ky, double* part, int max_blocks, hipStream_t st) {
-  long long b = (g.NL + kThreads - 1) / kThreads;
+  if (g.nc > kDiagNC) return hipErrorInvalidValue;
+  long long b = (g.NL + 3) / 4;
   if (b > max_blocks) b = max_blocks;
-  k_ch_diag_lines<<<unsigned(b < 1 ? 1 : b), kThreads, 0, st>>>(g, om, w, phi, dw, dphi, mean, kx, ky, part);
+  k_ch_diag_lines<<<unsigned(b < 1 ? 1 : b), 256, 0, st>>>(g, om, w, phi, dw, dphi, mean, kx, ky, part);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
 class Diag(ctypes.Structure):
     _fields_ = [("mean_phi", ctypes.c_double), ("ke", ctypes.c_double), ("grad2", ctypes.c_double),
                 ("max_div", ctypes.c_double), ("nonfinite", ctypes.c_int32), ("nstep", ctypes.c_int32),
-                ("cfl", ctypes.c_double)]
+                ("cfl", ctypes.c_double), ("sphi0_re", ctypes.c_double), ("sphi0_im", ctypes.c_double)]
 
 
 class WallArgs(ctypes.Structure):
@@ -290,7 +290,8 @@ class Solver:
         d = Diag()
         _check(lib().psms_diagnostics(self.ctx, ctypes.byref(d)))
         return dict(mean_phi=d.mean_phi, ke=d.ke, grad2=d.grad2, max_div=d.max_div,
-                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl)
+                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl,
+                    sphi0=complex(d.sphi0_re, d.sphi0_im))
 
     def pressure(self):
         """p_hat of the current state, complex128 [n, n, n/2+1]."""
@@ -479,7 +480,8 @@ class Batch:
         d = Diag()
         _check(lib().psms_batch_diagnostics(self.h, int(box), ctypes.byref(d)))
         return dict(mean_phi=d.mean_phi, ke=d.ke, grad2=d.grad2, max_div=d.max_div,
-                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl)
+                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl,
+                    sphi0=complex(d.sphi0_re, d.sphi0_im))
 
     def groups(self):
         ng = ctypes.c_int32(0)
@@ -697,4 +699,5 @@ class Channel:
         d = Diag()
         _check(lib().psms_channel_diagnostics(self.h, ctypes.byref(d)))
         return dict(mean_phi=d.mean_phi, ke=d.ke, grad2=d.grad2, max_div=d.max_div,
-                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl)
+                    nonfinite=int(d.nonfinite), nstep=int(d.nstep), cfl=d.cfl,
+                    sphi0=complex(d.sphi0_re, d.sphi0_im))

@@ -485,3 +485,20 @@ def test_laplace_pressure_jump_on_the_gpu(precision):
     pr = np.fft.irfftn(_host(s.pressure()), s=(n, n, n), norm="forward")
     jump = pr[n // 2, n // 2, n // 2] - pr[0, 0, 0]
     assert abs(jump - 2.0 / (we * R)) < 0.01 * 2.0 / (we * R), jump
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_recorded_sphi0_is_at_rounding_level(precision):
+    """The z stage records S_phi(k = 0) before setting it to zero (every CH term is a
+    divergence): like the oracle's record, it sits at the rounding level of S_phi."""
+    p, prm, st = _prepare("drops4_48", 1)
+    _, sphi, sphi0 = box.nonlinear_terms(st["uh"], st["ph"], prm)
+    scale = np.max(np.abs(sphi))
+    s = _solver(p, precision)
+    _load(s, st)
+    assert s.diagnostics()["sphi0"] == 0.0
+    s.step(1)
+    got = s.diagnostics()["sphi0"]
+    bar = (1e-13 if precision == "fp64" else 1e-6) * scale
+    assert abs(sphi0) < 1e-13 * scale
+    assert abs(got) < bar, (got, sphi0, scale)

@@ -529,3 +529,18 @@ def test_pressure_of_the_taylor_green_vortex():
     st = box.init_state(u, -np.ones((n, n, n)), prm)
     p = box.inv(box.pressure(st, prm), n)
     assert np.max(np.abs(p - 0.25 * (np.cos(2 * X) + np.cos(2 * Y)))) < 1e-14
+
+
+def test_threaded_transforms_give_the_same_step():
+    """The multi-core timing mode (scipy.fft with several workers) computes the same step
+    as numpy's transforms, to rounding."""
+    p, u, phi = synth.box_case("single_drop_32")
+    prm = box.Params(**p)
+    a = box.step(box.init_state(u, phi, prm), prm)
+    box.set_fft_workers(4)
+    try:
+        b = box.step(box.init_state(u, phi, prm), prm)
+    finally:
+        box.set_fft_workers(1)
+    assert np.linalg.norm(a["uh"] - b["uh"]) <= 1e-14 * np.linalg.norm(a["uh"])
+    assert np.linalg.norm(a["ph"] - b["ph"]) <= 1e-14 * np.linalg.norm(a["ph"])
