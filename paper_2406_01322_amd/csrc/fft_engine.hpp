@@ -265,6 +265,22 @@ struct IdxLineMajor {
   __device__ __forceinline__ int operator()(int pos) const { return base + pos + 3 * (pos >> 4); }
 };
 
+// Row tiles with an XOR swizzle in place of the padding: element (line, pos)
+// at line * kRowStrideSwz<N> + (pos ^ ((pos >> 3) & 15)).  The XOR changes
+// only the low 4 bits, with bits that it leaves unchanged or can be undone
+// from (bit 3 is XORed with bit 6, bits 0-2 with bits 3-5), so it permutes
+// every block of 16 positions; N must be a multiple of 16.
+template <int N>
+constexpr int kRowStrideSwz = N + 1;
+template <int N, int TT = N>
+struct IdxLineSwz {
+  static_assert(TT <= 64 && 64 % TT == 0, "a row line must lie within one wavefront");
+  static_assert(N % 16 == 0, "the swizzle permutes blocks of 16 positions");
+  static constexpr bool kWaveLocal = true;
+  int base;  // line * kRowStrideSwz<N>
+  __device__ __forceinline__ int operator()(int pos) const { return base + (pos ^ ((pos >> 3) & 15)); }
+};
+
 // Orders the LDS accesses of one wavefront: the LDS executes a wavefront's
 // instructions in issue order, so only the compiler must not move memory
 // operations across this point.
