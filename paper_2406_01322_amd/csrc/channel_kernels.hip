@@ -5,8 +5,9 @@
 //    and imaginary parts at once.  Lines are (kx, ky) pairs, stored
 //    position-major ([n][line]), so the lanes of a wavefront read consecutive
 //    lines and no transpose is needed.
-//  * k_chebd: derivative in coefficient space by the backward recurrence
-//    c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n.
+//  * k_cheb_seg: derivative (and D^2 - k^2) in coefficient space, the
+//    backward recurrence c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n summed piecewise
+//    along each parity chain.
 //  * k_helm: the Chebyshev-tau Helmholtz problem (D^2 - beta) f = g with two
 //    Dirichlet or Neumann boundary rows, in FP64.  Rewriting the tau rows with
 //    the integration recurrence turns each parity (even / odd n) into a
@@ -263,75 +264,119 @@ __global__ void __launch_bounds__(1024) k_dct_half(const cpx<T>* __restrict__ in
 }
 
 // Coefficients of d/dz: b_nc = 0, c_{m} b_{m} = b_{m+2} + 2 (m+1) a_{m+1} for
-// m = nc-1 .. 0 (c_0 = 2, else 1).  The recurrence links m to m+2 only, so the
-// even and odd outputs are two independent chains: one thread per (line,
-// parity).  The loads do not depend on the recurrence; unrolling lets several
-// be in flight.
-__device__ __forceinline__ void chebd_chain(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ d, int nc,
-                                            long long nlines, long long id) {
-  const long long l = id % nlines;
-  const int q = int(id / nlines);
+// m = nc-1 .. 0 (c_0 = 2, else 1); and of D^2 - k^2 through c = D b with
+// b = D a.  Both recurrences link m to m+2 only, so the outputs of each parity
+// form a chain, and along a chain they are suffix sums:
+//   D:       c_m b_m = B_m = sum_{j >= m, j = m mod 2} 2 (j+1) a_{j+1}
+//   D^2:     b_{m+1} = sum_{p >= m+2, p = m mod 2} 2 p a_p,
+//            c_m (D^2 a)_m = sum_{j >= m, j = m mod 2} 2 (j+1) b_{j+1}.
+// A chain of cnt terms (m = top, top-2, ..) is cut into 8 pieces of at most
+// LEN terms; each lane sums its piece, and the pieces' totals are combined by
+// a scan across the lanes.  A wavefront holds the chains of one parity of 8
+// consecutive lines: lane = 8 piece + line, so that for one term the 8 lanes
+// of a piece read 8 consecutive lines (128 contiguous bytes), and each lane
+// issues its piece's loads at once.  (One lane per chain would leave a
+// 256 x 129 line set with fewer wavefronts than SIMDs, each waiting on one
+// load per term.)
+namespace {
+
+__device__ __forceinline__ cpx<double> shfl_up8(cpx<double> v, int pieces) {
+  return cpx<double>{__shfl_up(v.re, 8 * pieces), __shfl_up(v.im, 8 * pieces)};
+}
+// exclusive scan over the 8 pieces of a chain (lanes 8 apart), piece `pc` of this lane
+__device__ __forceinline__ cpx<double> piece_carry(cpx<double> tot, int pc) {
+  cpx<double> inc = tot;
+#pragma unroll
+  for (int d = 1; d < 8; d <<= 1) {
+    const cpx<double> o = shfl_up8(inc, d);
+    if (pc >= d) inc = cadd(inc, o);
+  }
+  const cpx<double> ex = shfl_up8(inc, 1);
+  return pc == 0 ? cpx<double>{0.0, 0.0} : ex;
+}
+
+template <int LEN>
+__global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long long nlines,
+                                                  const double* __restrict__ kx, const double* __restrict__ ky,
+                                                  int lap) {
+  const int lane = threadIdx.x & 63;
+  const int pc = lane >> 3;
+  const long long groups = (nlines + 7) / 8;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= 2 * groups) return;   // whole wavefronts
+  const int q = int(wave / groups);
+  const long long l = (wave % groups) * 8 + (lane & 7);
+  const bool valid = l < nlines;
+  const cpx<double>* __restrict__ a = bt.in[blockIdx.y];
+  cpx<double>* __restrict__ out = bt.out[blockIdx.y];
   const int top = ((nc - q) & 1) ? nc - 1 : nc;   // largest m <= nc of parity q
-  cpx<double> b2 = {0.0, 0.0};                     // b_{m+2}
-#pragma unroll 4
-  for (int m = top; m >= 0; m -= 2) {
-    const cpx<double> am = (m + 1 <= nc) ? a[(long long)(m + 1) * nlines + l] : cpx<double>{0.0, 0.0};
-    const double s = (m == 0) ? 0.5 : 1.0;
-    const cpx<double> bm = {(b2.re + 2.0 * (m + 1) * am.re) * s, (b2.im + 2.0 * (m + 1) * am.im) * s};
-    d[(long long)m * nlines + l] = bm;
-    b2 = bm;
+  const int cnt = top / 2 + 1;                     // terms m = top, top - 2, .., q
+  const int i0 = pc * LEN;
+  const cpx<double> zero = {0.0, 0.0};
+  if (!lap) {
+    cpx<double> x[LEN];
+#pragma unroll
+    for (int k = 0; k < LEN; ++k) {
+      const int m = top - 2 * (i0 + k);
+      x[k] = zero;
+      if (valid && i0 + k < cnt && m + 1 <= nc) {
+        const cpx<double> v = a[(long long)(m + 1) * nlines + l];
+        x[k] = cpx<double>{2.0 * (m + 1) * v.re, 2.0 * (m + 1) * v.im};
+      }
+    }
+#pragma unroll
+    for (int k = 1; k < LEN; ++k) x[k] = cadd(x[k - 1], x[k]);
+    const cpx<double> c = piece_carry(x[LEN - 1], pc);
+#pragma unroll
+    for (int k = 0; k < LEN; ++k) {
+      const int m = top - 2 * (i0 + k);
+      if (valid && i0 + k < cnt) {
+        const double s = (m == 0) ? 0.5 : 1.0;
+        const cpx<double> bm = cadd(c, x[k]);
+        out[(long long)m * nlines + l] = cpx<double>{s * bm.re, s * bm.im};
+      }
+    }
+    return;
+  }
+  const double k2 = (kx && valid) ? kx[l] * kx[l] + ky[l] * ky[l] : 0.0;
+  cpx<double> av[LEN], x[LEN];
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int m = top - 2 * (i0 + k);
+    av[k] = zero;
+    if (valid && i0 + k < cnt) av[k] = a[(long long)m * nlines + l];
+  }
+  // b_{m+1} = sum of 2 p a_p over the chain's earlier terms (p > m): exclusive sums
+  cpx<double> run = zero;
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int m = top - 2 * (i0 + k);
+    x[k] = run;
+    run = cadd(run, cpx<double>{2.0 * m * av[k].re, 2.0 * m * av[k].im});
+  }
+  const cpx<double> c1 = piece_carry(run, pc);
+  // c_m = sum of 2 (j+1) b_{j+1} over j >= m: inclusive sums
+  run = zero;
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int m = top - 2 * (i0 + k);
+    const cpx<double> bm1 = cadd(c1, x[k]);
+    run = cadd(run, cpx<double>{2.0 * (m + 1) * bm1.re, 2.0 * (m + 1) * bm1.im});
+    x[k] = run;
+  }
+  const cpx<double> c2 = piece_carry(run, pc);
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int m = top - 2 * (i0 + k);
+    if (valid && i0 + k < cnt) {
+      const double s = (m == 0) ? 0.5 : 1.0;
+      const cpx<double> cm = cadd(c2, x[k]);
+      out[(long long)m * nlines + l] = cpx<double>{s * cm.re - k2 * av[k].re, s * cm.im - k2 * av[k].im};
+    }
   }
 }
 
-__global__ void k_chebd(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ d, int nc, long long nlines) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= 2 * nlines) return;
-  chebd_chain(a, d, nc, nlines, id);
-}
-
-// out = D^2 a - k^2 a (k^2 = kx^2 + ky^2 of the line, 0 if kx is NULL) in one
-// backward pass: with b = D a and c = D b, c_m = (c_{m+2} + 2(m+1) b_{m+1})/c_m
-// and b_{m+1} = b_{m+3} + 2(m+2) a_{m+2}; the outputs of parity q need b of the
-// other parity and a of parity q, so each (line, parity) is one thread.
-__device__ __forceinline__ void cheb_lap_chain(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ out,
-                                               int nc, long long nlines, const double* __restrict__ kx,
-                                               const double* __restrict__ ky, long long id) {
-  const long long l = id % nlines;
-  const int q = int(id / nlines);
-  const double k2 = kx ? kx[l] * kx[l] + ky[l] * ky[l] : 0.0;
-  const int top = ((nc - q) & 1) ? nc - 1 : nc;
-  cpx<double> b1 = {0.0, 0.0};   // b_{m+3} before the update, b_{m+1} after
-  cpx<double> c2 = {0.0, 0.0};   // c_{m+2}
-  cpx<double> a2 = {0.0, 0.0};   // a_{m+2}
-#pragma unroll 4
-  for (int m = top; m >= 0; m -= 2) {
-    const cpx<double> am = a[(long long)m * nlines + l];
-    b1 = cpx<double>{b1.re + 2.0 * (m + 2) * a2.re, b1.im + 2.0 * (m + 2) * a2.im};   // b_{m+1}
-    const double s = (m == 0) ? 0.5 : 1.0;
-    const cpx<double> cm = {(c2.re + 2.0 * (m + 1) * b1.re) * s, (c2.im + 2.0 * (m + 1) * b1.im) * s};
-    out[(long long)m * nlines + l] = cpx<double>{cm.re - k2 * am.re, cm.im - k2 * am.im};
-    c2 = cm;
-    a2 = am;
-  }
-}
-
-__global__ void k_cheb_lap(const cpx<double>* __restrict__ a, cpx<double>* __restrict__ out, int nc,
-                           long long nlines, const double* __restrict__ kx, const double* __restrict__ ky) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= 2 * nlines) return;
-  cheb_lap_chain(a, out, nc, nlines, kx, ky, id);
-}
-
-// several arrays of the same lines in one launch (blockIdx.y selects the
-// array): D (lap = 0) or D^2 - k^2 (lap = 1)
-__global__ void k_cheb_batch(ChebBatch b, int nc, long long nlines, const double* __restrict__ kx,
-                             const double* __restrict__ ky, int lap) {
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= 2 * nlines) return;
-  const int j = blockIdx.y;
-  if (lap) cheb_lap_chain(b.in[j], b.out[j], nc, nlines, kx, ky, id);
-  else chebd_chain(b.in[j], b.out[j], nc, nlines, id);
-}
+}  // namespace
 
 // Chebyshev-tau Helmholtz solve (D^2 - beta) f = g, one thread per (line,
 // parity).  For n >= 2 the tau rows are equivalent to
@@ -901,23 +946,37 @@ hipError_t launch_dct_fields(int nc, const cpx<T>* in, cpx<T>* out, long long nl
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st) {
-  k_chebd<<<blocks(2 * nlines, 64), 64, 0, st>>>(a, d, nc, nlines);
-  return hipGetLastError();
-}
-
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
                              int lap, hipStream_t st) {
-  if (b.n < 0 || b.n > kChebBatchMax || nlines < 0) return hipErrorInvalidValue;
+  if (b.n < 0 || b.n > kChebBatchMax || nlines < 0 || nc < 1) return hipErrorInvalidValue;
   if (b.n == 0 || nlines == 0) return hipSuccess;
-  k_cheb_batch<<<dim3(blocks(2 * nlines, 64), unsigned(b.n)), 64, 0, st>>>(b, nc, nlines, kx, ky, lap);
-  return hipGetLastError();
+  const int need = (nc / 2 + 1 + 7) / 8;   // terms per piece (8 pieces per chain)
+  const dim3 grid(blocks(2 * ((nlines + 7) / 8) * 64, 256), unsigned(b.n));
+#define PSMS_SEG(LEN) \
+  if (need <= LEN) { \
+    k_cheb_seg<LEN><<<grid, 256, 0, st>>>(b, nc, nlines, kx, ky, lap); \
+    return hipGetLastError(); \
+  }
+  PSMS_SEG(1) PSMS_SEG(2) PSMS_SEG(3) PSMS_SEG(5) PSMS_SEG(9) PSMS_SEG(17)
+#undef PSMS_SEG
+  return hipErrorInvalidValue;   // nc > 270
+}
+
+hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st) {
+  ChebBatch b{};
+  b.n = 1;
+  b.in[0] = a;
+  b.out[0] = d;
+  return launch_cheb_batch(b, nc, nlines, nullptr, nullptr, 0, st);
 }
 
 hipError_t launch_cheb_lap(const cpx<double>* a, cpx<double>* out, int nc, long long nlines, const double* kx,
                            const double* ky, hipStream_t st) {
-  k_cheb_lap<<<blocks(2 * nlines, 64), 64, 0, st>>>(a, out, nc, nlines, kx, ky);
-  return hipGetLastError();
+  ChebBatch b{};
+  b.n = 1;
+  b.in[0] = a;
+  b.out[0] = out;
+  return launch_cheb_batch(b, nc, nlines, kx, ky, 1, st);
 }
 
 hipError_t launch_helm(const cpx<double>* g, cpx<double>* f, double* xw, int nc, long long nlines,
