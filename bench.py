@@ -67,12 +67,12 @@ def step_model_bytes(n, mixed):
     return w_phys * 30 * P + w_state * 2 * 20 * M + w_rhs * 2 * 16 * M
 
 
-def measured_traffic(stage):
+def measured_traffic(stage, precision="mixed"):
     """HBM bytes per launch of a stage kernel from the committed counter record
-    (profiles/box128_mixed_hbm_counters.json), or None if the kernel sources changed
-    since the counters were taken."""
+    (profiles/box128_<precision>_hbm_counters.json), or None if the kernel sources
+    changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "box128_mixed_hbm_counters.json")
+    path = os.path.join(ROOT, "profiles", "box128_%s_hbm_counters.json" % precision)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -371,10 +371,16 @@ def channel_model_bytes(nx, ny, nc, mixed):
     return w_phys * 30 * P + 8 * 2 * 20 * hx * cy * (nc + 1) + w_phys * 2 * 16 * hx * cy * (kz + 1)
 
 
-def roofline_entry(nbytes, ms):
+def roofline_entry(nbytes, ms, traffic=None):
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": None, "model_bytes_per_step": nbytes, "ms_per_step": ms}
+            "traffic": traffic, "model_bytes_per_step": nbytes, "ms_per_step": ms}
+
+
+def step_traffic(precision):
+    """Counted HBM bytes of one box step (the four stage kernels), or None."""
+    t = [measured_traffic(st, precision) for st in STAGES]
+    return None if any(v is None for v in t) else sum(t)
 
 
 def cpu_baseline(n, p, u, phi, budget_s=20.0):
@@ -483,7 +489,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom) if head == "mixed" else None,
+                     "traffic": measured_traffic(dom, head),
                      "algorithmic_bytes_per_launch": sb[dom]},
         "event_ms_per_step": r["event_ms_per_step"],
         "median_of_5": {"ms_per_step": r["median_of_5_ms_per_step"],
@@ -511,8 +517,9 @@ def main():
     # step-level HBM rooflines of the other paths (byte model / step time)
     out["rooflines"] = {}
     if "fp64" in res:
-        out["rooflines"]["box_fp64_step"] = roofline_entry(step_model_bytes(n, False), res["fp64"]["ms_per_step"])
-    out["rooflines"]["box_%s_step" % head] = roofline_entry(step_bytes, r["ms_per_step"])
+        out["rooflines"]["box_fp64_step"] = roofline_entry(step_model_bytes(n, False), res["fp64"]["ms_per_step"],
+                                                           step_traffic("fp64"))
+    out["rooflines"]["box_%s_step" % head] = roofline_entry(step_bytes, r["ms_per_step"], step_traffic(head))
     forms = out.get("forms", {})
     if "channel_step" in forms:
         cf = forms["channel_step"]
