@@ -255,6 +255,9 @@ constexpr int kXstepWaves = (sizeof(T) == 4 && N <= 128 && (N & (N - 1)) == 0) ?
 // row layout; both measured faster at N = 128 (28.8 against 30.5 us).
 template <typename T, int N>
 constexpr bool kXstepWide = kXstepWaves<T, N> == 4 && N >= 64;
+// the swizzled layout alone (FP64 at N = 64, 128)
+template <typename T, int N>
+constexpr bool kXstepSwz = kXstepWide<T, N> || (sizeof(T) == 8 && (N == 64 || N == 128));
 
 // Staging of the x stage's inputs through LDS by direct global->LDS copies.
 // A wavefront transforms LPW = 64 / TT consecutive row pairs, i.e. 2 LPW
@@ -342,7 +345,8 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
   cpx<T>* __restrict__ xout = static_cast<cpx<T>*>(bx.bufb);
   const double csig_d = bx.csig;
   constexpr bool WIDE = kXstepWide<T, N>;
-  constexpr int E = G::E, TT = G::TT, L = G::L, LP = WIDE ? kRowStrideSwz<N> : kRowStride<N>, K = G::K, H = G::H;
+  constexpr bool SWZ = kXstepSwz<T, N>;
+  constexpr int E = G::E, TT = G::TT, L = G::L, LP = SWZ ? kRowStrideSwz<N> : kRowStride<N>, K = G::K, H = G::H;
   constexpr int NFF = WIDE ? 4 : 2;   // products per forward group
   constexpr int RI = first_radix<P, 1>();   // inverse starts with R[NST-1]
   constexpr int RP = last_radix<P, 1>();    // inverse ends / forward starts with R[0]
@@ -359,7 +363,7 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
   build_twiddles<T, P, 1>(twi, [&](int m) { return tw_g[m]; }, tid, int(blockDim.x));
   const long long r0 = ((long long)xcd_tile(blockIdx.x, gridDim.x) * L + line) * 2;
   const bool valid = r0 < ROWS;  // ROWS is even: both rows exist
-  using Idx = std::conditional_t<WIDE, IdxLineSwz<N, TT>, IdxLineMajor<N, TT>>;
+  using Idx = std::conditional_t<SWZ, IdxLineSwz<N, TT>, IdxLineMajor<N, TT>>;
   const Idx idx{line * LP};
   int par = 0;
   __syncthreads();
