@@ -250,9 +250,11 @@ __global__ void __launch_bounds__(256) k_rows_inv(const cpx<T>* __restrict__ in,
 // the compiler is asked for four waves per SIMD.
 template <typename T, int N>
 constexpr int kXstepWaves = (sizeof(T) == 4 && N <= 128 && (N & (N - 1)) == 0) ? 4 : 1;
-// For those plans the products are transformed four at a time (one LDS round
-// trip per exchange for four lines) and the exchanges use the XOR-swizzled
-// row layout; both measured faster at N = 128 (28.8 against 30.5 us).
+// For those plans the fields are transformed four at a time (one LDS round
+// trip per exchange for four lines; the inverse as fields 0-3, then 4-6) and
+// the exchanges use the XOR-swizzled row layout; measured faster at N = 128
+// (products in fours and the swizzle: 30.5 -> 28.8 us; the inverse in fours
+// as well: a further 0.6 us).
 template <typename T, int N>
 constexpr bool kXstepWide = kXstepWaves<T, N> == 4 && N >= 64;
 // the swizzled layout alone (FP64 at N = 64, 128)
@@ -440,6 +442,27 @@ k_xstep(const BoxDev* __restrict__ boxes, int box0, const cpx<T>* __restrict__ t
     load_raw(0, ra[0], rb[0]);
     load_raw(1, ra[1], rb[1]);
   }
+  if constexpr (WIDE) {
+    // four inverse transforms per LDS round trip: fields 0-3, then 4-6
+    static_for<0, 2>([&](auto gi) {
+      constexpr int f0 = decltype(gi)::value * 4;
+      constexpr int nf = f0 == 0 ? 4 : 3;
+      cpx<T> v[nf][E];
+#pragma unroll
+      for (int g = 0; g < nf; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          cpx<T> A, B;
+          load_raw_slot(f0 + g, e, A, B);
+          pack_slot(f0 + g, e, A, B, v[g][e]);
+        }
+      fft_lines<T, P, 1, nf>(v, lds[0], FS, 0, par, t, idx, twi);
+#pragma unroll
+      for (int g = 0; g < nf; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) ph[f0 + g][e] = v[g][e];
+    });
+  } else
 #pragma unroll
   for (int vf = 0; vf < 7; vf += 2) {
     const int nf = (vf + 1 < 7) ? 2 : 1;
