@@ -583,7 +583,9 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
   constexpr int RL = last_radix<P, -1>();    // forward ends / inverse starts with R[NST-1]
   static_assert(RL == first_radix<P, 1>(), "mirrored radix order");
   __shared__ cpx<T> tw[N];
-  __shared__ cpx<T> lds[2][N * LP];
+  // two lines per exchange (one per field of a pair), each with its two
+  // ping-pong buffers: line f, parity par at lds[2 f + par]
+  __shared__ cpx<T> lds[4][N * LP];
   const int tid = threadIdx.x;
   const int line = tid % L, t = tid / L;
   for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
@@ -618,28 +620,25 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
 
   __syncthreads();
   if (do_update) {
-    cpx<T> nx[E];
+    // the forward transforms two products at a time (one barrier per exchange
+    // for both), the next pair's loads in flight while a pair is transformed
+    cpx<T> nx[2][E];
+    auto load_pair = [&](int f0) {
 #pragma unroll
-    for (int b = 0; b < E / RF; ++b)
-#pragma unroll
-      for (int r = 0; r < RF; ++r)
-        nx[b * RF + r] = valid ? ld_global(rhs + (long long)slot_pos<P, RF>(t, b, r) * Q + q) : cpx<T>{T(0), T(0)};
-    // one forward transform per product; the product index is a compile-time
-    // constant in each call, so its accumulation is straight-line code
-    auto fwd_field = [&](auto fc) {
-      constexpr int f = decltype(fc)::value;
-      cpx<T> v[E];
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = nx[e];
-      if constexpr (f < 7) {  // prefetch the next field while this one is transformed
-        const cpx<T>* src = rhs + (long long)(f + 1) * N * Q;
+      for (int g = 0; g < 2; ++g) {
+        const cpx<T>* src = rhs + (long long)(f0 + g) * N * Q;
 #pragma unroll
         for (int b = 0; b < E / RF; ++b)
 #pragma unroll
           for (int r = 0; r < RF; ++r)
-            nx[b * RF + r] = valid ? ld_global(src + (long long)slot_pos<P, RF>(t, b, r) * Q + q) : cpx<T>{T(0), T(0)};
+            nx[g][b * RF + r] = valid ? ld_global(src + (long long)slot_pos<P, RF>(t, b, r) * Q + q) : cpx<T>{T(0), T(0)};
       }
-      fft_line<T, P, -1>(v, lds[0], lds[1], par, t, idx, tw);
+    };
+    load_pair(0);
+    // product f's contribution to the accumulators; f is a compile-time
+    // constant in each call, so the accumulation is straight-line code
+    auto accumulate = [&](auto fc, const cpx<T>* v) {
+      constexpr int f = decltype(fc)::value;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         if (inb[e]) {
@@ -669,15 +668,18 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
         }
       }
     };
-    using std::integral_constant;
-    fwd_field(integral_constant<int, 0>());
-    fwd_field(integral_constant<int, 1>());
-    fwd_field(integral_constant<int, 2>());
-    fwd_field(integral_constant<int, 3>());
-    fwd_field(integral_constant<int, 4>());
-    fwd_field(integral_constant<int, 5>());
-    fwd_field(integral_constant<int, 6>());
-    fwd_field(integral_constant<int, 7>());
+    static_for<0, 4>([&](auto pc) {
+      constexpr int f0 = decltype(pc)::value * 2;
+      cpx<T> v[2][E];
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[g][e] = nx[g][e];
+      if constexpr (f0 + 2 < 8) load_pair(f0 + 2);
+      fft_lines<T, P, -1, 2>(v, lds[0], 2 * N * LP, N * LP, par, t, idx, tw);
+      accumulate(std::integral_constant<int, f0>(), v[0]);
+      accumulate(std::integral_constant<int, f0 + 1>(), v[1]);
+    });
     // spectral update of the owned modes (FP64)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -739,33 +741,37 @@ __global__ void __launch_bounds__(64 << V) k_zstep(const BoxDev* __restrict__ bo
     }
   }
 
-  // z-inverse of u, v, w, phi and i kz phi
-  auto inv_field = [&](auto gc) {
-    constexpr int gf = decltype(gc)::value;
-    cpx<T> v[E];
+  // z-inverse of u, v, w, phi and i kz phi, two fields at a time
+  auto inv_fields = [&](auto gc, auto nc) {
+    constexpr int g0 = decltype(gc)::value, nf = decltype(nc)::value;
+    cpx<T> v[nf][E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      cpx<double> x = {0.0, 0.0};
-      if (inb[e]) {
-        if constexpr (gf < 4) x = acc[gf][e];
-        else x = cpx<double>{-kz[e] * acc[3][e].im, kz[e] * acc[3][e].re};
+    for (int g = 0; g < nf; ++g)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        cpx<double> x = {0.0, 0.0};
+        if (inb[e]) {
+          if (g0 + g < 4) x = acc[g0 + g][e];
+          else x = cpx<double>{-kz[e] * acc[3][e].im, kz[e] * acc[3][e].re};
+        }
+        v[g][e] = to_cpx<T>(x);
       }
-      v[e] = to_cpx<T>(x);
-    }
-    fft_line<T, P, 1>(v, lds[0], lds[1], par, t, idx, tw);
-    cpx<T>* dst = gout + (long long)gf * N * Q;
+    fft_lines<T, P, 1, nf>(v, lds[0], 2 * N * LP, N * LP, par, t, idx, tw);
     if (valid) {
 #pragma unroll
-      for (int b = 0; b < E / RF; ++b)
+      for (int g = 0; g < nf; ++g) {
+        cpx<T>* dst = gout + (long long)(g0 + g) * N * Q;
 #pragma unroll
-        for (int r = 0; r < RF; ++r) st_global(dst + (long long)slot_pos<P, RF>(t, b, r) * Q + q, v[b * RF + r]);
+        for (int b = 0; b < E / RF; ++b)
+#pragma unroll
+          for (int r = 0; r < RF; ++r) st_global(dst + (long long)slot_pos<P, RF>(t, b, r) * Q + q, v[g][b * RF + r]);
+      }
     }
   };
-  inv_field(std::integral_constant<int, 0>());
-  inv_field(std::integral_constant<int, 1>());
-  inv_field(std::integral_constant<int, 2>());
-  inv_field(std::integral_constant<int, 3>());
-  inv_field(std::integral_constant<int, 4>());
+  using std::integral_constant;
+  inv_fields(integral_constant<int, 0>(), integral_constant<int, 2>());
+  inv_fields(integral_constant<int, 2>(), integral_constant<int, 2>());
+  inv_fields(integral_constant<int, 4>(), integral_constant<int, 1>());
 }
 
 // ---------------------------------------------------------------------------
