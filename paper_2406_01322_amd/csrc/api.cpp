@@ -1483,8 +1483,13 @@ struct ChanLayout {
   size_t kx, ky, twx64, twx32, twy64, twy32, twz64, twz32;
   size_t state, mean, hist, hmean;
   size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, lapc, lapphi, lapom, psi, lappsi, G;
-  size_t d2mean, gmean, wt, wb, M, whp, mhp, psip, xi, xw, diag, xdev, total;
+  size_t d2mean, gmean, wt, wb, M, whp, mhp, psip, xi, xw, diag, xdev, fac, total;
+  bool has_fac;   // the step's tau problems read precomputed elimination factors
 };
+
+// the step's six tau problems (omega_z, psi_p, the mean line, xi, w_p, phi)
+// each keep a table of elimination factors, in this order
+enum { kChanFacOm, kChanFacPsi, kChanFacMean, kChanFacXi, kChanFacW, kChanFacPhi, kChanFacCount };
 
 constexpr int kChanDiagBlocks = 1024;   // partial sums of the diagnostics
 
@@ -1558,6 +1563,11 @@ ChanLayout chan_layout(const psms_channel_params& p) {
   take(L.mhp, 2 * size_t(g.NL) * sizeof(double));
   take(L.psip, arr);
   take(L.xi, arr);
+  // elimination factors of the tau problems: kept where the solves stay on
+  // chip (same condition at both walls and a chain length the kernels unroll)
+  const int fsw = p.free_slip & 3;
+  L.has_fac = (fsw == 0 || fsw == 3) && psms::helm_fuses_influence(p.nc);
+  take(L.fac, L.has_fac ? kChanFacCount * psms::helm_factor_doubles(p.nc, g.NL) * sizeof(double) : 0);
   take(L.xw, 4 * nz * size_t(g.NL) * sizeof(double));   // one elimination scratch per batched problem
   take(L.diag, (8 * size_t(kChanDiagBlocks) + 8) * sizeof(double));
   take(L.xdev, sizeof(psms::BoxDev));   // descriptor of the fused x stage
@@ -1806,6 +1816,14 @@ hipError_t chan_step_once(psms_channel* c) {
   b1.p[2] = psms::HelmProblem{C64(L.gmean), C64(L.mean), xw + 2 * xws, 2, c->coef.beta, nullptr, nullptr, fs, z0,
                               z0};                                                                        // U, V
   b1.p[3] = psms::HelmProblem{C64(L.G) + 2 * g.NZL, C64(L.xi), xw + 3 * xws, nl, c->a_fac, kx, ky, 3, z0, z0};  // xi
+  const size_t fd = psms::helm_factor_doubles(nc, nl);
+  const double* fac = L.has_fac ? c->at<double>(L.fac) : nullptr;
+  if (fac) {
+    b1.p[0].fac = fac + kChanFacOm * fd;
+    b1.p[1].fac = fac + kChanFacPsi * fd;
+    b1.p[2].fac = fac + kChanFacMean * fd;
+    b1.p[3].fac = fac + kChanFacXi * fd;   // (not among the np problems in single phase)
+  }
   PSMS_TRY(psms::launch_helm_batch(b1, nc, st));
   psms::HelmBatch b2{};
   b2.np = g.sp ? 1 : 2;
@@ -1817,6 +1835,10 @@ hipError_t chan_step_once(psms_channel* c) {
   if (fused) {
     b2.p[0].wh = c->at<double>(L.whp);
     b2.p[0].mh = c->at<double>(L.mhp);
+  }
+  if (fac) {
+    b2.p[0].fac = fac + kChanFacW * fd;
+    b2.p[1].fac = fac + kChanFacPhi * fd;   // (not among the np problems in single phase)
   }
   PSMS_TRY(psms::launch_helm_batch(b2, nc, st));
   if (!fused)
@@ -1944,6 +1966,29 @@ int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* 
     if (e == hipSuccess)
       e = psms::launch_influence_parity_pre(c->at<cpx<double>>(lay.wt), c->at<cpx<double>>(lay.wb), p->nc, g.NL,
                                             c->at<double>(lay.whp), c->at<double>(lay.mhp), st);
+    // elimination factors of the step's tau problems (their beta + k^2 and
+    // wall conditions are fixed for the context)
+    if (e == hipSuccess && lay.has_fac) {
+      const int fs = p->free_slip & 3;
+      const size_t fd = psms::helm_factor_doubles(p->nc, g.NL);
+      double* fac = c->at<double>(lay.fac);
+      auto prob = [&](double beta, bool lines, int bc) {
+        psms::HelmProblem h{};
+        h.nlines = lines ? g.NL : 2;
+        h.beta_add = beta;
+        h.kx = lines ? kx : nullptr;
+        h.ky = lines ? ky : nullptr;
+        h.bc = bc;
+        return h;
+      };
+      const psms::HelmProblem probs[kChanFacCount] = {prob(c->coef.beta, true, fs), prob(c->coef.beta, true, 0),
+                                                     prob(c->coef.beta, false, fs), prob(c->a_fac, true, 3),
+                                                     prob(0.0, true, 0), prob(c->b_fac, true, 3)};
+      for (int k = 0; k < kChanFacCount && e == hipSuccess; ++k) {
+        if (g.sp && (k == kChanFacXi || k == kChanFacPhi)) continue;   // no phi equation
+        e = psms::launch_helm_factors(probs[k], p->nc, fac + k * fd, st);
+      }
+    }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {

@@ -403,6 +403,7 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
 struct TauQ {
   double q[3][kTauQMax + 1];
 };
+constexpr int kHelmPieces = 8;   // pieces per chain in k_helm_pieces
 constexpr TauQ make_tau_q() {
   TauQ t{};
   for (int n = 2; n <= kTauQMax; ++n) {
@@ -587,13 +588,16 @@ __global__ void k_helm_batch(HelmBatch b, int nc) {
 // arithmetic is that of helm_line, in the same order.  With P.wh the w
 // problem's influence correction follows in the second upward sweep
 // (HelmProblem).
-template <int NC>
+// MODE 2 stores the elimination factors of each chain instead of solving
+// (see k_helm_pieces): fac [2 parities][NC/2 + 1][nlines] pairs of doubles,
+// row i >= 1 (X_i, 1 / (B_i + C_i X_{i+1})), row 0 (sum w_n P_n, sum n^2 P_n).
+template <int NC, int MODE>
 __device__ __forceinline__ void helm_reg_chain(const HelmProblem& P, cpx<double> (*Ys)[64], int tid, long long l,
-                                               int p) {
+                                               int p, double* fac_out = nullptr) {
   constexpr int MM = NC / 2;                 // longest chain: parity 0, i = 0..MM
   const int m = (NC - p) / 2;
   const long long nl = P.nlines;
-  const cpx<double>* __restrict__ g = P.g;
+  const cpx<double>* __restrict__ g = (MODE == 2) ? nullptr : P.g;
   if (g) {
     // entries n = p + 2 i <= NC - 2 of this parity into row i (lane tid's
     // 16 bytes at &Ys[i][tid]); lanes past the last line copy nothing
@@ -619,6 +623,7 @@ __device__ __forceinline__ void helm_reg_chain(const HelmProblem& P, cpx<double>
   const bool plus = (p == 0) != neu;
   const cpx<double> s = plus ? cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)}
                              : cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)};
+  const long long frow = (long long)p * (MM + 1);   // factor row i of this chain at ((frow + i) nl + l) 2
   // entry n of g (zero outside the tau rows); row (n - p) / 2 of Ys until the
   // downward sweep overwrites it with Y (after its last use: the sweep keeps
   // the three entries it needs in registers)
@@ -646,14 +651,19 @@ __device__ __forceinline__ void helm_reg_chain(const HelmProblem& P, cpx<double>
                            -cm2 * gm.im * q1 + en * g0.im * q2 - en2 * g2.im * q3};
     const double den = 1.0 / (B + C * Xn);
     const double Xv = -A * den;
-    const cpx<double> Y = {(R.re - C * Yn.re) * den, (R.im - C * Yn.im) * den};
-    g2 = g0;
-    g0 = gm;
-    gm = G(n - 4);
+    if constexpr (MODE == 2) {
+      fac_out[((frow + i) * nl + l) * 2] = Xv;
+      fac_out[((frow + i) * nl + l) * 2 + 1] = den;
+    } else {
+      const cpx<double> Y = {(R.re - C * Yn.re) * den, (R.im - C * Yn.im) * den};
+      g2 = g0;
+      g0 = gm;
+      gm = G(n - 4);
+      Ys[i][tid] = Y;
+      Yn = Y;
+    }
     X[i] = Xv;
-    Ys[i][tid] = Y;
     Xn = Xv;
-    Yn = Y;
   }
   // upward sweep 1: a_i = P_i a_0 + Q_i and the boundary row of this parity;
   // with the influence correction also sum n^2 P_i and sum n^2 Q_i
@@ -664,21 +674,33 @@ __device__ __forceinline__ void helm_reg_chain(const HelmProblem& P, cpx<double>
   for (int i = 0; i <= MM; ++i) {
     if (i > m) continue;
     const int n = p + 2 * i;
-    if (i > 0) {
-      const cpx<double> Y = Ys[i][tid];
-      Pc = X[i] * Pc;
-      Qv = cpx<double>{X[i] * Qv.re + Y.re, X[i] * Qv.im + Y.im};
-    }
-    const double n2 = double(n) * double(n);
-    const double w = neu ? n2 : 1.0;
-    SP += w * Pc;
-    SQ.re += w * Qv.re;
-    SQ.im += w * Qv.im;
-    if (infl) {
+    if constexpr (MODE == 2) {
+      if (i > 0) Pc = X[i] * Pc;
+      const double n2 = double(n) * double(n);
+      SP += (neu ? n2 : 1.0) * Pc;
       SPn += n2 * Pc;
-      SQn.re += n2 * Qv.re;
-      SQn.im += n2 * Qv.im;
+    } else {
+      if (i > 0) {
+        const cpx<double> Y = Ys[i][tid];
+        Pc = X[i] * Pc;
+        Qv = cpx<double>{X[i] * Qv.re + Y.re, X[i] * Qv.im + Y.im};
+      }
+      const double n2 = double(n) * double(n);
+      const double w = neu ? n2 : 1.0;
+      SP += w * Pc;
+      SQ.re += w * Qv.re;
+      SQ.im += w * Qv.im;
+      if (infl) {
+        SPn += n2 * Pc;
+        SQn.re += n2 * Qv.re;
+        SQn.im += n2 * Qv.im;
+      }
     }
+  }
+  if constexpr (MODE == 2) {
+    fac_out[(frow * nl + l) * 2] = SP;
+    fac_out[(frow * nl + l) * 2 + 1] = SPn;
+    return;
   }
   // a_0, the influence coefficient, then upward sweep 2
   cpx<double> a = {(s.re - SQ.re) / SP, (s.im - SQ.im) / SP};
@@ -718,7 +740,190 @@ __global__ void __launch_bounds__(64) k_helm_batch_reg(HelmBatch b) {
   __shared__ cpx<double> Ys[NC / 2 + 1][64];
   const HelmProblem& P = b.p[blockIdx.y];
   const long long l = (long long)blockIdx.x * 64 + threadIdx.x;
-  helm_reg_chain<NC>(P, Ys, threadIdx.x, l, int(blockIdx.z));
+  helm_reg_chain<NC, 0>(P, Ys, threadIdx.x, l, int(blockIdx.z));
+}
+
+// the factors of one problem (helm_reg_chain, MODE 2)
+template <int NC>
+__global__ void __launch_bounds__(64) k_helm_factors(HelmProblem P, double* fac) {
+  const long long l = (long long)blockIdx.x * 64 + threadIdx.x;
+  helm_reg_chain<NC, 2>(P, nullptr, threadIdx.x, l, int(blockIdx.z), fac);
+}
+
+
+// The tau solves of a batch whose problems carry their elimination factors
+// (P.fac, from helm_reg_chain MODE 2: beta + k^2 and the wall conditions of
+// a context do not change between steps).  With X_i and d_i = 1 / (B_i + C_i
+// X_{i+1}) given, the three sweeps of a chain are first-order linear
+// recurrences:
+//   Y_i = d_i R_i - d_i C_i Y_{i+1}   (i = m .. 1, Y_{m+1} = 0)
+//   Q_i = X_i Q_{i-1} + Y_i           (i = 1 .. m, Q_0 = 0), P_i = X_i P_{i-1}
+//   a_i = P_i a_0 + Q_i,  a_0 = (s - sum w_i Q_i) / sum w_i P_i,
+// so a chain of m + 1 terms is cut into 8 pieces of at most LEN terms: the
+// wavefronts of a workgroup are the pieces of the chains of 64 lines of one
+// parity (lane = line, so each term's load is 1 KB of consecutive lines, and
+// a piece's term indices are the same in every lane), each lane forms its
+// piece's affine maps and its part of the boundary-row sums, the pieces'
+// maps pass through LDS, and each lane composes those of the pieces before
+// its own.  The serial chain of the on-chip kernel (one lane per chain, its
+// loads and divisions in sequence) becomes 8 short ones with every load
+// issued at once.
+template <int NC, int PAR>
+__device__ __forceinline__ void helm_pieces_chain(const HelmProblem& P, double (*sh)[kHelmPieces][64], int pc,
+                                                  int ln, long long l) {
+  constexpr int MM = NC / 2;
+  constexpr int LEN = (MM + 1 + kHelmPieces - 1) / kHelmPieces;
+  constexpr int m = (NC - PAR) / 2;          // chain i = 0..m, n = PAR + 2 i
+  const long long nl = P.nlines;
+  const bool valid = l < nl;
+  const long long lc = valid ? l : 0;         // lanes past the last line read line 0 and store nothing
+  const int i0 = pc * LEN;                    // uniform in the wavefront
+  const bool neu = P.bc == 3;
+  double be = P.beta_add;
+  if (P.kx) be += P.kx[lc] * P.kx[lc] + P.ky[lc] * P.ky[lc];
+  const cpx<double> top = P.top_c, bot = P.bot_c;
+  const bool plus = (PAR == 0) != neu;
+  const cpx<double> s = plus ? cpx<double>{0.5 * (top.re + bot.re), 0.5 * (top.im + bot.im)}
+                             : cpx<double>{0.5 * (top.re - bot.re), 0.5 * (top.im - bot.im)};
+  const double* __restrict__ fac = P.fac + ((long long)PAR * (MM + 1) * nl + lc) * 2;   // row i at 2 i nl
+  const cpx<double>* __restrict__ g = P.g;
+  // the piece's loads, all issued before any use
+  cpx<double> gv[LEN + 2];
+  double Xv[LEN], dv[LEN];
+#pragma unroll
+  for (int k = 0; k < LEN + 2; ++k) {
+    const int i = i0 - 1 + k, n = PAR + 2 * i;
+    gv[k] = (g && i >= 0 && n <= NC - 2) ? g[(long long)n * nl + lc] : cpx<double>{0.0, 0.0};
+  }
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int i = i0 + k;
+    const bool in = i >= 1 && i <= m;
+    Xv[k] = in ? fac[2 * (long long)i * nl] : 0.0;
+    dv[k] = in ? fac[2 * (long long)i * nl + 1] : 0.0;
+  }
+  // 1. Y, downward: Y_i = ay_i Y_in + Y_i(local), Y_in = Y at the first term of the piece above
+  double ay[LEN];
+  cpx<double> Y[LEN];
+  double A = 1.0;
+  cpx<double> B = {0.0, 0.0};
+#pragma unroll
+  for (int k = LEN - 1; k >= 0; --k) {
+    const int i = i0 + k, n = PAR + 2 * i;
+    if (i >= 1 && i <= m) {
+      const double cm2 = (n - 2 == 0) ? 2.0 : 1.0;
+      const double en = (n <= NC - 2) ? 1.0 : 0.0;
+      const double en2 = (n + 2 <= NC - 2) ? 1.0 : 0.0;
+      const double q1 = kTauQ.q[0][n], q2 = kTauQ.q[1][n], q3 = kTauQ.q[2][n];
+      const double C = en2 * be * q3;
+      const cpx<double> gm = gv[k], g0 = gv[k + 1], g2 = gv[k + 2];
+      const cpx<double> R = {-cm2 * gm.re * q1 + en * g0.re * q2 - en2 * g2.re * q3,
+                             -cm2 * gm.im * q1 + en * g0.im * q2 - en2 * g2.im * q3};
+      const double al = -C * dv[k];
+      A = al * A;
+      B = cpx<double>{dv[k] * R.re + al * B.re, dv[k] * R.im + al * B.im};
+    }
+    ay[k] = A;
+    Y[k] = B;
+  }
+  sh[0][pc][ln] = A;
+  sh[1][pc][ln] = B.re;
+  sh[2][pc][ln] = B.im;
+  __syncthreads();
+  cpx<double> yin = {0.0, 0.0};               // the pieces above, applied to Y_{m+1} = 0
+  for (int j = kHelmPieces - 1; j > pc; --j) {
+    const double a = sh[0][j][ln];
+    yin = cpx<double>{a * yin.re + sh[1][j][ln], a * yin.im + sh[2][j][ln]};
+  }
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) Y[k] = cpx<double>{ay[k] * yin.re + Y[k].re, ay[k] * yin.im + Y[k].im};
+  // 2. Q, upward: the piece's map Q_out = aq Q_in + bq, its product of X, and
+  // its parts of sum w_i Q_i and sum n^2 Q_i as linear functions of Q_in
+  double aq = 1.0, pp = 1.0, swa = 0.0, sna = 0.0;
+  cpx<double> bq = {0.0, 0.0}, swb = {0.0, 0.0}, snb = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int i = i0 + k, n = PAR + 2 * i;
+    if (i == 0) {
+      aq = 0.0;                               // Q_0 = 0 whatever comes in
+    } else if (i <= m) {
+      const double n2 = double(n) * double(n);
+      const double w = neu ? n2 : 1.0;
+      aq = Xv[k] * aq;
+      bq = cpx<double>{Xv[k] * bq.re + Y[k].re, Xv[k] * bq.im + Y[k].im};
+      pp = Xv[k] * pp;
+      swa += w * aq;
+      swb = cpx<double>{swb.re + w * bq.re, swb.im + w * bq.im};
+      sna += n2 * aq;
+      snb = cpx<double>{snb.re + n2 * bq.re, snb.im + n2 * bq.im};
+    }
+  }
+  __syncthreads();                            // the Y maps have been read
+  const double mine[10] = {aq, bq.re, bq.im, pp, swa, swb.re, swb.im, sna, snb.re, snb.im};
+#pragma unroll
+  for (int v = 0; v < 10; ++v) sh[v][pc][ln] = mine[v];
+  __syncthreads();
+  // Q_in and the product of X of the pieces below, and the sums over all pieces
+  cpx<double> qv = {0.0, 0.0}, qin = {0.0, 0.0}, SQ = {0.0, 0.0}, SQn = {0.0, 0.0};
+  double pin = 1.0;
+  for (int j = 0; j < kHelmPieces; ++j) {
+    if (j == pc) {
+      qin = qv;
+    }
+    SQ = cpx<double>{SQ.re + sh[4][j][ln] * qv.re + sh[5][j][ln], SQ.im + sh[4][j][ln] * qv.im + sh[6][j][ln]};
+    SQn = cpx<double>{SQn.re + sh[7][j][ln] * qv.re + sh[8][j][ln], SQn.im + sh[7][j][ln] * qv.im + sh[9][j][ln]};
+    const double a = sh[0][j][ln];
+    qv = cpx<double>{a * qv.re + sh[1][j][ln], a * qv.im + sh[2][j][ln]};
+    if (j < pc) pin *= sh[3][j][ln];
+  }
+  // 3. a_0 and the influence coefficient
+  const double SP = fac[0], SPn = fac[1];
+  const cpx<double> a0 = {(s.re - SQ.re) / SP, (s.im - SQ.im) / SP};
+  const bool infl = P.wh != nullptr;
+  cpx<double>* __restrict__ f = P.f;
+  cpx<double> c = {0.0, 0.0};
+  bool zero = false;
+  if (infl) {
+    if (P.kx[lc] == 0.0 && P.ky[lc] == 0.0) {
+      zero = true;                            // no wall-normal velocity on the mean line
+    } else {
+      const double r = -1.0 / P.mh[(long long)PAR * nl + lc];
+      c = cpx<double>{r * (a0.re * SPn + SQn.re), r * (a0.im * SPn + SQn.im)};
+    }
+  }
+  // 4. the piece's coefficients a_i = P_i a_0 + Q_i
+  if (!valid) return;
+  cpx<double> q = qin;
+  double pr = pin;
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int i = i0 + k, n = PAR + 2 * i;
+    if (i > m) continue;
+    if (i == 0) {
+      q = cpx<double>{0.0, 0.0};
+      pr = 1.0;
+    } else {
+      q = cpx<double>{Xv[k] * q.re + Y[k].re, Xv[k] * q.im + Y[k].im};
+      pr = Xv[k] * pr;
+    }
+    cpx<double> v = {pr * a0.re + q.re, pr * a0.im + q.im};
+    if (infl) {
+      const double h = P.wh[(long long)n * nl + l];
+      v = zero ? cpx<double>{0.0, 0.0} : cpx<double>{v.re + c.re * h, v.im + c.im * h};
+    }
+    f[(long long)n * nl + l] = v;
+  }
+}
+
+template <int NC>
+__global__ void __launch_bounds__(64 * kHelmPieces) k_helm_pieces(HelmBatch bt) {
+  __shared__ double sh[10][kHelmPieces][64];
+  const HelmProblem& P = bt.p[blockIdx.y];
+  const int pc = int(threadIdx.x >> 6), ln = int(threadIdx.x & 63);
+  const long long l = (long long)blockIdx.x * 64 + ln;
+  if ((long long)blockIdx.x * 64 >= P.nlines) return;   // the whole workgroup (problems of fewer lines)
+  if (blockIdx.z == 0) helm_pieces_chain<NC, 0>(P, sh, pc, ln, l);
+  else helm_pieces_chain<NC, 1>(P, sh, pc, ln, l);
 }
 
 // wh_n = (w_t + w_b)_n (even n) or (w_t - w_b)_n (odd n): the homogeneous
@@ -1000,6 +1205,21 @@ hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st) {
   const bool reg = same_walls && helm_fuses_influence(nc);
   for (int i = 0; i < b.np; ++i)
     if (b.p[i].wh && (!reg || !b.p[i].kx || !b.p[i].mh)) return hipErrorInvalidValue;
+  // factors: given for every problem of the batch or for none
+  int nfac = 0;
+  for (int i = 0; i < b.np; ++i) nfac += b.p[i].fac ? 1 : 0;
+  if (nfac && (nfac != b.np || !reg)) return hipErrorInvalidValue;
+  if (nfac) {
+    const dim3 grid(blocks(most, 64), unsigned(b.np), 2);
+    switch (nc) {
+#define PSMS_CASE(NC) \
+  case NC: k_helm_pieces<NC><<<grid, 64 * kHelmPieces, 0, st>>>(b); return hipGetLastError();
+      PSMS_CASE(4) PSMS_CASE(6) PSMS_CASE(8) PSMS_CASE(12) PSMS_CASE(16) PSMS_CASE(24) PSMS_CASE(32)
+      PSMS_CASE(48) PSMS_CASE(64) PSMS_CASE(96) PSMS_CASE(128)
+#undef PSMS_CASE
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (same_walls) {
     const dim3 grid(blocks(most, 64), unsigned(b.np), 2);
     switch (nc) {
@@ -1014,6 +1234,23 @@ hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st) {
   k_helm_batch<<<dim3(blocks(2 * most, 64), unsigned(b.np)), 64, 0, st>>>(b, nc);
   return hipGetLastError();
 }
+
+hipError_t launch_helm_factors(const HelmProblem& P, int nc, double* fac, hipStream_t st) {
+  if (!fac || P.nlines < 0 || !(P.bc == 0 || P.bc == 3) || !helm_fuses_influence(nc)) return hipErrorInvalidValue;
+  if (P.nlines == 0) return hipSuccess;
+  const dim3 grid(blocks(P.nlines, 64), 1, 2);
+  switch (nc) {
+#define PSMS_CASE(NC) \
+  case NC: k_helm_factors<NC><<<grid, 64, 0, st>>>(P, fac); return hipGetLastError();
+    PSMS_CASE(4) PSMS_CASE(6) PSMS_CASE(8) PSMS_CASE(12) PSMS_CASE(16) PSMS_CASE(24) PSMS_CASE(32)
+    PSMS_CASE(48) PSMS_CASE(64) PSMS_CASE(96) PSMS_CASE(128)
+#undef PSMS_CASE
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t helm_factor_doubles(int nc, long long nlines) { return size_t(2) * size_t(nc / 2 + 1) * size_t(nlines) * 2; }
 
 bool helm_fuses_influence(int nc) {
   switch (nc) {

@@ -57,6 +57,12 @@ struct HelmProblem {
   // their sums sum n^2 wh_n; f = 0 on the line kx = ky = 0
   const double* wh = nullptr;
   const double* mh = nullptr;
+  // optional (on-chip path only): the elimination factors of the problem's
+  // beta_add + k^2 and wall conditions, from launch_helm_factors
+  // (helm_factor_doubles(nc, nlines) doubles); the problem's beta_add, kx, ky,
+  // bc and nlines must be those the factors were made with.  Given for all
+  // problems of a batch or for none.
+  const double* fac = nullptr;
 };
 struct HelmBatch {
   HelmProblem p[kHelmBatchMax];
@@ -66,6 +72,11 @@ hipError_t launch_helm_batch(const HelmBatch& b, int nc, hipStream_t st);
 // whether launch_helm_batch keeps the chains on chip for this nc (same condition
 // at both walls), the only path that applies HelmProblem::wh
 bool helm_fuses_influence(int nc);
+// the factors of problem P (its g, f, top_c, bot_c and influence fields are
+// not used) for nc with helm_fuses_influence(nc) and the same condition at
+// both walls (bc 0 or 3)
+hipError_t launch_helm_factors(const HelmProblem& P, int nc, double* fac, hipStream_t st);
+size_t helm_factor_doubles(int nc, long long nlines);
 // the parity-split homogeneous solutions of the clamped w problem between two
 // no-slip walls: wh_n = (w_t + w_b)_n for even n, (w_t - w_b)_n for odd n (real),
 // and mh[p][l] = sum_{n = p mod 2} n^2 wh_n
