@@ -313,6 +313,13 @@ typedef struct psms_channel_params {
 } psms_channel_params;
 typedef struct psms_channel psms_channel;
 
+/* Device workspace of a context (owned by the caller, at least the bytes
+ * reported, kept until psms_channel_destroy): the state, history and the
+ * step's intermediates, and what create precomputes once because k^2 and the
+ * time step are fixed: the homogeneous w solutions and their influence data
+ * and, for nc <= 128 with the same condition at both walls, the elimination
+ * factors of the six wall-normal problems (16 (nc/2 + 1) bytes per line and
+ * parity each).  create runs on `stream` and synchronises. */
 int psms_channel_workspace_bytes(const psms_channel_params* p, size_t* bytes);
 int psms_channel_create(psms_channel** out, const psms_channel_params* p, void* d_workspace, size_t bytes,
                         void* stream);
