@@ -1482,7 +1482,7 @@ namespace {
 struct ChanLayout {
   size_t kx, ky, twx64, twx32, twy64, twy32, twz64, twz32;
   size_t state, mean, hist, hmean;
-  size_t dw, dphi, A, A2, B, C, R, D3, S3, Q, DQ, lapc, lapphi, lapom, psi, lappsi, G;
+  size_t dw, dphi, A, A2, B, C, R, D3, DQ, lapc, lapphi, lapom, psi, lappsi, G;
   size_t d2mean, gmean, wt, wb, M, whp, mhp, psip, xi, xw, diag, xdev, fac, total;
   bool has_fac;   // the step's tau problems read precomputed elimination factors
 };
@@ -1545,8 +1545,6 @@ ChanLayout chan_layout(const psms_channel_params& p) {
   take(L.C, 8 * size_t(g.P) * tr);
   take(L.R, 8 * arr);
   take(L.D3, 3 * arr);
-  take(L.S3, 3 * arr);
-  take(L.Q, arr);
   take(L.DQ, arr);
   take(L.lapc, arr);
   take(L.lapphi, arr);
@@ -1766,8 +1764,8 @@ hipError_t chan_step_once(psms_channel* c) {
   cb.in[2] = R + 2 * g.NZL;
   cb.out[2] = D3 + 2 * g.NZL;
   PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0, st));
-  PSMS_TRY(psms::launch_ch_s(g, R, D3, D3 + g.NZL, D3 + 2 * g.NZL, kx, ky, C64(L.S3), C64(L.Q), st));
-  PSMS_TRY(psms::launch_chebd(C64(L.Q), C64(L.DQ), nc, nl, st));
+  psms::ChebQ cq{R, R + g.NZL, R + 3 * g.NZL, D3, D3 + g.NZL};
+  PSMS_TRY(psms::launch_chebd_q(cq, nc, nl, kx, ky, C64(L.DQ), st));
   cb.n = g.sp ? 2 : 4;   // D^2 - k^2 of omega_z, w, c and phi
   cb.in[0] = om;
   cb.out[0] = C64(L.lapom);
@@ -1783,7 +1781,7 @@ hipError_t chan_step_once(psms_channel* c) {
   // 6. Adams-Bashforth, Crank-Nicolson / implicit Euler right-hand sides
   c->coef.ab1 = (c->nstep == 0) ? 1 : 0;
   psms::ChanAssembleArgs aa{};
-  aa.s3 = C64(L.S3);
+  aa.d3 = D3;
   aa.dq = C64(L.DQ);
   aa.R = R;
   aa.lapc = C64(L.lapc);

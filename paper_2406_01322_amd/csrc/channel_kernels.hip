@@ -376,6 +376,55 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
   }
 }
 
+
+// D Q of Q = i kx S_x + i ky S_y, S_x = i kx T_xx + i ky T_xy + D T_xz,
+// S_y = i kx T_xy + i ky T_yy + D T_yz (the horizontal divergence of the
+// stress divergence), with Q formed term by term from its five arrays as it
+// is loaded: the pieced D recurrence of k_cheb_seg.
+template <int LEN>
+__global__ void __launch_bounds__(256) k_cheb_seg_q(ChebQ in, int nc, long long nlines,
+                                                    const double* __restrict__ kxl, const double* __restrict__ kyl,
+                                                    cpx<double>* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int pc = lane >> 3;
+  const long long groups = (nlines + 7) / 8;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= 2 * groups) return;   // whole wavefronts
+  const int q = int(wave / groups);
+  const long long l = (wave % groups) * 8 + (lane & 7);
+  const bool valid = l < nlines;
+  const double kx = valid ? kxl[l] : 0.0, ky = valid ? kyl[l] : 0.0;
+  auto ti = [](double k, cpx<double> a) { return cpx<double>{-k * a.im, k * a.re}; };
+  const int top = ((nc - q) & 1) ? nc - 1 : nc;
+  const int cnt = top / 2 + 1;
+  const int i0 = pc * LEN;
+  cpx<double> x[LEN];
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int m = top - 2 * (i0 + k);
+    x[k] = cpx<double>{0.0, 0.0};
+    if (valid && i0 + k < cnt && m + 1 <= nc) {
+      const long long id = (long long)(m + 1) * nlines + l;
+      const cpx<double> txx = in.txx[id], tyy = in.tyy[id], txy = in.txy[id];
+      const cpx<double> sx = cadd(cadd(ti(kx, txx), ti(ky, txy)), in.dxz[id]);
+      const cpx<double> sy = cadd(cadd(ti(kx, txy), ti(ky, tyy)), in.dyz[id]);
+      const cpx<double> v = cadd(ti(kx, sx), ti(ky, sy));
+      x[k] = cpx<double>{2.0 * (m + 1) * v.re, 2.0 * (m + 1) * v.im};
+    }
+  }
+#pragma unroll
+  for (int k = 1; k < LEN; ++k) x[k] = cadd(x[k - 1], x[k]);
+  const cpx<double> c = piece_carry(x[LEN - 1], pc);
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) {
+    const int m = top - 2 * (i0 + k);
+    if (valid && i0 + k < cnt) {
+      const double sm = (m == 0) ? 0.5 : 1.0;
+      const cpx<double> bm = cadd(c, x[k]);
+      out[(long long)m * nlines + l] = cpx<double>{sm * bm.re, sm * bm.im};
+    }
+  }
+}
 }  // namespace
 
 // Chebyshev-tau Helmholtz solve (D^2 - beta) f = g, one thread per (line,
@@ -1165,6 +1214,22 @@ hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const
   PSMS_SEG(1) PSMS_SEG(2) PSMS_SEG(3) PSMS_SEG(5) PSMS_SEG(9) PSMS_SEG(17)
 #undef PSMS_SEG
   return hipErrorInvalidValue;   // nc > 270
+}
+
+hipError_t launch_chebd_q(const ChebQ& in, int nc, long long nlines, const double* kx, const double* ky,
+                          cpx<double>* out, hipStream_t st) {
+  if (nlines < 0 || nc < 1) return hipErrorInvalidValue;
+  if (nlines == 0) return hipSuccess;
+  const int need = (nc / 2 + 1 + 7) / 8;
+  const dim3 grid(blocks(2 * ((nlines + 7) / 8) * 64, 256));
+#define PSMS_SEG(LEN) \
+  if (need <= LEN) { \
+    k_cheb_seg_q<LEN><<<grid, 256, 0, st>>>(in, nc, nlines, kx, ky, out); \
+    return hipGetLastError(); \
+  }
+  PSMS_SEG(1) PSMS_SEG(2) PSMS_SEG(3) PSMS_SEG(5) PSMS_SEG(9) PSMS_SEG(17)
+#undef PSMS_SEG
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st) {

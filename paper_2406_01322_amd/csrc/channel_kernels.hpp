@@ -30,6 +30,17 @@ struct ChebBatch {
 };
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
                              int lap, hipStream_t st);
+// out = D Q, Q = i kx S_x + i ky S_y formed from T_xx, T_yy, T_xy, D T_xz, D T_yz
+// (S_x = i kx T_xx + i ky T_xy + D T_xz, S_y = i kx T_xy + i ky T_yy + D T_yz)
+struct ChebQ {
+  const cpx<double>* txx;
+  const cpx<double>* tyy;
+  const cpx<double>* txy;
+  const cpx<double>* dxz;
+  const cpx<double>* dyz;
+};
+hipError_t launch_chebd_q(const ChebQ& in, int nc, long long nlines, const double* kx, const double* ky,
+                          cpx<double>* out, hipStream_t st);
 // out = D^2 a - (kx^2 + ky^2) a per line (k^2 = 0 if kx is NULL)
 hipError_t launch_cheb_lap(const cpx<double>* a, cpx<double>* out, int nc, long long nlines, const double* kx,
                            const double* ky, hipStream_t st);

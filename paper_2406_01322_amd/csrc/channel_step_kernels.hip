@@ -94,25 +94,6 @@ __global__ void k_ch_products(ChanGeom g, T* __restrict__ f, T cs) {
   }
 }
 
-__global__ void k_ch_s(ChanGeom g, const cpx<double>* __restrict__ R, const cpx<double>* __restrict__ dxz,
-                       const cpx<double>* __restrict__ dyz, const cpx<double>* __restrict__ dzz,
-                       const double* __restrict__ kxl, const double* __restrict__ kyl, cpx<double>* __restrict__ s3,
-                       cpx<double>* __restrict__ q) {
-  PSMS_GRID_LOOP(id, g.NZL) {
-    const long long l = id % g.NL;
-    const double kx = kxl[l], ky = kyl[l];
-    const cpx<double> txx = R[id], tyy = R[g.NZL + id], txy = R[3 * g.NZL + id];
-    const cpx<double> txz = R[4 * g.NZL + id], tyz = R[5 * g.NZL + id];
-    const cpx<double> sx = add(add(ti(kx, txx), ti(ky, txy)), dxz[id]);
-    const cpx<double> sy = add(add(ti(kx, txy), ti(ky, tyy)), dyz[id]);
-    const cpx<double> sz = add(add(ti(kx, txz), ti(ky, tyz)), dzz[id]);
-    s3[id] = sx;
-    s3[g.NZL + id] = sy;
-    s3[2 * g.NZL + id] = sz;
-    q[id] = add(ti(kx, sx), ti(ky, sy));
-  }
-}
-
 __device__ __forceinline__ cpx<double> ab(cpx<double> h, cpx<double> hp, int ab1) {
   return ab1 ? h : cpx<double>{1.5 * h.re - 0.5 * hp.re, 1.5 * h.im - 0.5 * hp.im};
 }
@@ -122,7 +103,12 @@ __global__ void k_ch_assemble(ChanGeom g, ChanCoef c, ChanAssembleArgs a) {
     const long long l = id % g.NL, n = id / g.NL;
     const double kx = a.kx[l], ky = a.ky[l];
     const double k2 = kx * kx + ky * ky;
-    const cpx<double> sx = a.s3[id], sy = a.s3[g.NZL + id], sz = a.s3[2 * g.NZL + id];
+    // S = div T: S_x = i kx T_xx + i ky T_xy + D T_xz, and likewise
+    const cpx<double> txx = a.R[id], tyy = a.R[g.NZL + id], txy = a.R[3 * g.NZL + id];
+    const cpx<double> txz = a.R[4 * g.NZL + id], tyz = a.R[5 * g.NZL + id];
+    const cpx<double> sx = add(add(ti(kx, txx), ti(ky, txy)), a.d3[id]);
+    const cpx<double> sy = add(add(ti(kx, txy), ti(ky, tyy)), a.d3[g.NZL + id]);
+    const cpx<double> sz = add(add(ti(kx, txz), ti(ky, tyz)), a.d3[2 * g.NZL + id]);
     const cpx<double> h_om = sub(ti(kx, sy), ti(ky, sx));                    // (curl S)_z
     const cpx<double> h_w = sub(scl(-k2, sz), a.dq[id]);                     // lap_h S_z - D(div_h S)
     const cpx<double> e_om = ab(h_om, a.hist[id], c.ab1);
@@ -417,12 +403,6 @@ hipError_t launch_ch_fields(const ChanGeom& g, const cpx<double>* om, const cpx<
 template <typename T>
 hipError_t launch_ch_products(const ChanGeom& g, T* f, double csig, hipStream_t st) {
   k_ch_products<T><<<blocks_for(g.P), kThreads, 0, st>>>(g, f, T(csig));
-  return hipGetLastError();
-}
-hipError_t launch_ch_s(const ChanGeom& g, const cpx<double>* R, const cpx<double>* dxz, const cpx<double>* dyz,
-                       const cpx<double>* dzz, const double* kx, const double* ky, cpx<double>* s3, cpx<double>* q,
-                       hipStream_t st) {
-  k_ch_s<<<blocks_for(g.NZL), kThreads, 0, st>>>(g, R, dxz, dyz, dzz, kx, ky, s3, q);
   return hipGetLastError();
 }
 hipError_t launch_ch_assemble(const ChanGeom& g, const ChanCoef& c, const ChanAssembleArgs& a, hipStream_t st) {

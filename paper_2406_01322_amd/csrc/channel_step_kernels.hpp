@@ -39,17 +39,13 @@ hipError_t launch_ch_fields(const ChanGeom& g, const cpx<double>* om, const cpx<
 // phase 3 in, the 6 components of -u_i u_j out
 template <typename T>
 hipError_t launch_ch_products(const ChanGeom& g, T* f, double csig, hipStream_t st);
-// S_x, S_y, S_z and Q = i kx S_x + i ky S_y from the products and D T_xz, D T_yz, D T_zz
-hipError_t launch_ch_s(const ChanGeom& g, const cpx<double>* R, const cpx<double>* dxz, const cpx<double>* dyz,
-                       const cpx<double>* dzz, const double* kx, const double* ky, cpx<double>* s3, cpx<double>* q,
-                       hipStream_t st);
 // H_omega, H_w, S_phi; Adams-Bashforth with the history (then overwritten);
 // the right-hand sides g_om, g_w, g_phi of the wall-normal solves; the mean
 // lines' H and right-hand sides.
 struct ChanAssembleArgs {
-  const cpx<double>* s3;      // [3][NZL]
-  const cpx<double>* dq;      // D Q
-  const cpx<double>* R;       // products, field 6 = a, 7 = c
+  const cpx<double>* d3;      // [3][NZL] D T_xz, D T_yz, D T_zz (S = div T is formed from them and R)
+  const cpx<double>* dq;      // D Q, Q = i kx S_x + i ky S_y
+  const cpx<double>* R;       // products T_xx T_yy T_zz T_xy T_xz T_yz, field 6 = a, 7 = c
   const cpx<double>* lapc;    // lap c
   const cpx<double>* phi;     // phi^n
   const cpx<double>* lapphi;  // lap phi^n
