@@ -1754,28 +1754,28 @@ hipError_t chan_step_once(psms_channel* c) {
                                          (long long)(nc + 1) * g.ny, 2.0 * M_PI / c->p.lx, st));
     PSMS_TRY(chan_forward_yz<T>(c, c->at<cpx<T>>(L.C), c->at<cpx<T>>(L.A), 8, R));
   }
-  // 5. S = div T, and the wall-normal derivatives the right-hand sides need
+  // 5. the wall-normal derivatives the right-hand sides need, in one launch:
+  // D T_xz, D T_yz, D T_zz and D^2 - k^2 of omega_z, w, c and phi; then D Q
+  // (Q = div_h S, S = div T, formed on the fly)
   cpx<double>* D3 = C64(L.D3);
-  cb.n = 3;   // D T_xz, D T_yz, D T_zz
+  cb.n = g.sp ? 5 : 7;
   cb.in[0] = R + 4 * g.NZL;
   cb.out[0] = D3;
   cb.in[1] = R + 5 * g.NZL;
   cb.out[1] = D3 + g.NZL;
   cb.in[2] = R + 2 * g.NZL;
   cb.out[2] = D3 + 2 * g.NZL;
-  PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0, st));
+  cb.in[3] = om;
+  cb.out[3] = C64(L.lapom);
+  cb.in[4] = w;
+  cb.out[4] = C64(L.psi);
+  cb.in[5] = R + 7 * g.NZL;
+  cb.out[5] = C64(L.lapc);
+  cb.in[6] = phi;
+  cb.out[6] = C64(L.lapphi);
+  PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0x78, st));   // arrays 3.. : D^2 - k^2
   psms::ChebQ cq{R, R + g.NZL, R + 3 * g.NZL, D3, D3 + g.NZL};
   PSMS_TRY(psms::launch_chebd_q(cq, nc, nl, kx, ky, C64(L.DQ), st));
-  cb.n = g.sp ? 2 : 4;   // D^2 - k^2 of omega_z, w, c and phi
-  cb.in[0] = om;
-  cb.out[0] = C64(L.lapom);
-  cb.in[1] = w;
-  cb.out[1] = C64(L.psi);
-  cb.in[2] = R + 7 * g.NZL;
-  cb.out[2] = C64(L.lapc);
-  cb.in[3] = phi;
-  cb.out[3] = C64(L.lapphi);
-  PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 1, st));
   PSMS_TRY(psms::launch_cheb_lap(C64(L.psi), C64(L.lappsi), nc, nl, kx, ky, st));
   PSMS_TRY(psms::launch_cheb_lap(C64(L.mean), C64(L.d2mean), nc, 2, nullptr, nullptr, st));
   // 6. Adams-Bashforth, Crank-Nicolson / implicit Euler right-hand sides

@@ -298,7 +298,8 @@ __device__ __forceinline__ cpx<double> piece_carry(cpx<double> tot, int pc) {
 template <int LEN>
 __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long long nlines,
                                                   const double* __restrict__ kx, const double* __restrict__ ky,
-                                                  int lap) {
+                                                  int lapmask) {
+  const int lap = (lapmask >> blockIdx.y) & 1;   // uniform in the workgroup
   const int lane = threadIdx.x & 63;
   const int pc = lane >> 3;
   const long long groups = (nlines + 7) / 8;
@@ -1201,14 +1202,14 @@ hipError_t launch_dct_fields(int nc, const cpx<T>* in, cpx<T>* out, long long nl
 }
 
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
-                             int lap, hipStream_t st) {
+                             int lapmask, hipStream_t st) {
   if (b.n < 0 || b.n > kChebBatchMax || nlines < 0 || nc < 1) return hipErrorInvalidValue;
   if (b.n == 0 || nlines == 0) return hipSuccess;
   const int need = (nc / 2 + 1 + 7) / 8;   // terms per piece (8 pieces per chain)
   const dim3 grid(blocks(2 * ((nlines + 7) / 8) * 64, 256), unsigned(b.n));
 #define PSMS_SEG(LEN) \
   if (need <= LEN) { \
-    k_cheb_seg<LEN><<<grid, 256, 0, st>>>(b, nc, nlines, kx, ky, lap); \
+    k_cheb_seg<LEN><<<grid, 256, 0, st>>>(b, nc, nlines, kx, ky, lapmask); \
     return hipGetLastError(); \
   }
   PSMS_SEG(1) PSMS_SEG(2) PSMS_SEG(3) PSMS_SEG(5) PSMS_SEG(9) PSMS_SEG(17)

@@ -21,15 +21,15 @@ hipError_t launch_dct_fields(int nc, const cpx<T>* in, cpx<T>* out, long long nl
                              const cpx<T>* tw, int dir, hipStream_t st, cpx<double>* out64 = nullptr, int kz = 0);
 hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st);
 // up to kChebBatchMax arrays of the same lines per launch: out[j] = D in[j]
-// (lap = 0) or D^2 in[j] - k^2 in[j] (lap = 1)
-constexpr int kChebBatchMax = 4;
+// (bit j of lapmask clear) or D^2 in[j] - k^2 in[j] (bit j set)
+constexpr int kChebBatchMax = 8;
 struct ChebBatch {
   const cpx<double>* in[kChebBatchMax];
   cpx<double>* out[kChebBatchMax];
   int n;
 };
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
-                             int lap, hipStream_t st);
+                             int lapmask, hipStream_t st);
 // out = D Q, Q = i kx S_x + i ky S_y formed from T_xx, T_yy, T_xy, D T_xz, D T_yz
 // (S_x = i kx T_xx + i ky T_xy + D T_xz, S_y = i kx T_xy + i ky T_yy + D T_yz)
 struct ChebQ {
