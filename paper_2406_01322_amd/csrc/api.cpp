@@ -1769,6 +1769,7 @@ hipError_t chan_step_once(psms_channel* c) {
   cb.out[3] = C64(L.lapom);
   cb.in[4] = w;
   cb.out[4] = C64(L.psi);
+  cb.out2[4] = C64(L.lappsi);   // and lap psi
   cb.in[5] = R + 7 * g.NZL;
   cb.out[5] = C64(L.lapc);
   cb.in[6] = phi;
@@ -1776,7 +1777,6 @@ hipError_t chan_step_once(psms_channel* c) {
   PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0x78, st));   // arrays 3.. : D^2 - k^2
   psms::ChebQ cq{R, R + g.NZL, R + 3 * g.NZL, D3, D3 + g.NZL};
   PSMS_TRY(psms::launch_chebd_q(cq, nc, nl, kx, ky, C64(L.DQ), st));
-  PSMS_TRY(psms::launch_cheb_lap(C64(L.psi), C64(L.lappsi), nc, nl, kx, ky, st));
   PSMS_TRY(psms::launch_cheb_lap(C64(L.mean), C64(L.d2mean), nc, 2, nullptr, nullptr, st));
   // 6. Adams-Bashforth, Crank-Nicolson / implicit Euler right-hand sides
   c->coef.ab1 = (c->nstep == 0) ? 1 : 0;

@@ -340,39 +340,57 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
     return;
   }
   const double k2 = (kx && valid) ? kx[l] * kx[l] + ky[l] * ky[l] : 0.0;
-  cpx<double> av[LEN], x[LEN];
+  // one D^2 - k^2 pass over the piece's terms in[k] (zero past the chain)
+  auto lap_pass = [&](const cpx<double>* in, cpx<double>* res) {
+    cpx<double> x[LEN];
+    // b_{m+1} = sum of 2 p a_p over the chain's earlier terms (p > m): exclusive sums
+    cpx<double> run = zero;
+#pragma unroll
+    for (int k = 0; k < LEN; ++k) {
+      const int m = top - 2 * (i0 + k);
+      x[k] = run;
+      run = cadd(run, cpx<double>{2.0 * m * in[k].re, 2.0 * m * in[k].im});
+    }
+    const cpx<double> c1 = piece_carry(run, pc);
+    // c_m = sum of 2 (j+1) b_{j+1} over j >= m: inclusive sums
+    run = zero;
+#pragma unroll
+    for (int k = 0; k < LEN; ++k) {
+      const int m = top - 2 * (i0 + k);
+      const cpx<double> bm1 = cadd(c1, x[k]);
+      run = cadd(run, cpx<double>{2.0 * (m + 1) * bm1.re, 2.0 * (m + 1) * bm1.im});
+      x[k] = run;
+    }
+    const cpx<double> c2 = piece_carry(run, pc);
+#pragma unroll
+    for (int k = 0; k < LEN; ++k) {
+      const int m = top - 2 * (i0 + k);
+      const double s = (m == 0) ? 0.5 : 1.0;
+      const cpx<double> cm = cadd(c2, x[k]);
+      res[k] = (i0 + k < cnt) ? cpx<double>{s * cm.re - k2 * in[k].re, s * cm.im - k2 * in[k].im} : zero;
+    }
+  };
+  cpx<double> av[LEN], r1[LEN];
 #pragma unroll
   for (int k = 0; k < LEN; ++k) {
     const int m = top - 2 * (i0 + k);
     av[k] = zero;
     if (valid && i0 + k < cnt) av[k] = a[(long long)m * nlines + l];
   }
-  // b_{m+1} = sum of 2 p a_p over the chain's earlier terms (p > m): exclusive sums
-  cpx<double> run = zero;
+  lap_pass(av, r1);
 #pragma unroll
   for (int k = 0; k < LEN; ++k) {
     const int m = top - 2 * (i0 + k);
-    x[k] = run;
-    run = cadd(run, cpx<double>{2.0 * m * av[k].re, 2.0 * m * av[k].im});
+    if (valid && i0 + k < cnt) out[(long long)m * nlines + l] = r1[k];
   }
-  const cpx<double> c1 = piece_carry(run, pc);
-  // c_m = sum of 2 (j+1) b_{j+1} over j >= m: inclusive sums
-  run = zero;
+  // optionally (D^2 - k^2)^2 as well: the chain of the result is in this wavefront
+  cpx<double>* __restrict__ out2 = bt.out2[blockIdx.y];
+  if (out2) {
+    lap_pass(r1, av);
 #pragma unroll
-  for (int k = 0; k < LEN; ++k) {
-    const int m = top - 2 * (i0 + k);
-    const cpx<double> bm1 = cadd(c1, x[k]);
-    run = cadd(run, cpx<double>{2.0 * (m + 1) * bm1.re, 2.0 * (m + 1) * bm1.im});
-    x[k] = run;
-  }
-  const cpx<double> c2 = piece_carry(run, pc);
-#pragma unroll
-  for (int k = 0; k < LEN; ++k) {
-    const int m = top - 2 * (i0 + k);
-    if (valid && i0 + k < cnt) {
-      const double s = (m == 0) ? 0.5 : 1.0;
-      const cpx<double> cm = cadd(c2, x[k]);
-      out[(long long)m * nlines + l] = cpx<double>{s * cm.re - k2 * av[k].re, s * cm.im - k2 * av[k].im};
+    for (int k = 0; k < LEN; ++k) {
+      const int m = top - 2 * (i0 + k);
+      if (valid && i0 + k < cnt) out2[(long long)m * nlines + l] = av[k];
     }
   }
 }

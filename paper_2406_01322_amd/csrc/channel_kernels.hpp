@@ -26,6 +26,7 @@ constexpr int kChebBatchMax = 8;
 struct ChebBatch {
   const cpx<double>* in[kChebBatchMax];
   cpx<double>* out[kChebBatchMax];
+  cpx<double>* out2[kChebBatchMax];   // D^2 - k^2 arrays: (D^2 - k^2)^2 in[j] as well where non-NULL
   int n;
 };
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
