@@ -1671,13 +1671,16 @@ hipError_t chan_forward(psms_channel* c, const T* phys, cpx<T>* band, int nf, cp
 
 // band [nf][n][line] (T) -> x-spectral [nf][z][y][kx band] (T) in the buffer B:
 // DCT-I, y lines
+// band [nf][n][line] (T; or, with fs, the step's six fields formed from the
+// state as the transform loads them) -> y-expanded [nf][z][y][x-band] (T)
 template <typename T>
-hipError_t chan_inverse_yz(psms_channel* c, const cpx<T>* band, int nf) {
+hipError_t chan_inverse_yz(psms_channel* c, const cpx<T>* band, int nf, const psms::ChanFieldSrc* fs = nullptr) {
   const psms::ChanGeom& g = c->g;
   const long long nz = g.nc + 1;
   cpx<T>* B = c->at<cpx<T>>(c->lay.B);
   cpx<T>* A2 = c->at<cpx<T>>(c->lay.A2);
-  hipError_t e = psms::launch_dct_fields<T>(g.nc, band, A2, g.NL, g.NZL, nf, chan_twz<T>(c), -1, c->stream);
+  hipError_t e = fs ? psms::launch_dct_chfields<T>(g.nc, *fs, A2, g.NZL, chan_twz<T>(c), c->stream)
+                    : psms::launch_dct_fields<T>(g.nc, band, A2, g.NL, g.NZL, nf, chan_twz<T>(c), -1, c->stream);
   if (e != hipSuccess) return e;
   psms::LineArgs la{};
   la.n_in = g.Cy;
@@ -1743,13 +1746,13 @@ hipError_t chan_step_once(psms_channel* c) {
     PSMS_TRY(psms::launch_ch_products<T>(g, c->at<T>(L.C), c->coef.csig, st));
     PSMS_TRY(chan_forward<T>(c, c->at<T>(L.C), c->at<cpx<T>>(L.A), g.nf_out, R));   // FP64, Chebyshev cut
   } else {
-    // two-phase: u, v, w, phi, dy phi, dz phi through the DCT-I and y lines; the
-    // x-inverse, the 8 products and the x-forward in one pass (the box's x stage on
-    // (nc + 1) ny rows; dx phi formed on load), so that no physical field is
-    // stored; then y lines and the DCT-I with the Chebyshev cut (FP64)
-    PSMS_TRY(psms::launch_ch_fields<T>(g, om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky,
-                                       c->at<cpx<T>>(L.A), st, 1));
-    PSMS_TRY(chan_inverse_yz<T>(c, c->at<cpx<T>>(L.A), 6));
+    // two-phase: u, v, w, phi, dy phi, dz phi through the DCT-I (each formed from
+    // the state as the transform loads it) and y lines; the x-inverse, the 8
+    // products and the x-forward in one pass (the box's x stage on (nc + 1) ny
+    // rows; dx phi formed on load), so that no physical field is stored; then y
+    // lines and the DCT-I with the Chebyshev cut (FP64)
+    const psms::ChanFieldSrc fs{om, w, phi, C64(L.dw), C64(L.dphi), C64(L.mean), kx, ky, nl};
+    PSMS_TRY(chan_inverse_yz<T>(c, nullptr, 6, &fs));
     PSMS_TRY(psms::launch_xstage_rows<T>(g.nx, c->at<psms::BoxDev>(L.xdev), chan_tw<T>(c, true),
                                          (long long)(nc + 1) * g.ny, 2.0 * M_PI / c->p.lx, st));
     PSMS_TRY(chan_forward_yz<T>(c, c->at<cpx<T>>(L.C), c->at<cpx<T>>(L.A), 8, R));

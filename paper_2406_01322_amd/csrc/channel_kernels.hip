@@ -47,8 +47,52 @@ struct CTile {
 // out64 (forward only, if not NULL): the coefficients are written in FP64
 // instead, those with n > kz as zero (the products' Chebyshev truncation),
 // so the step needs no separate promotion pass.
-template <typename T, int N>
-__global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+// Where the DCT kernels read their input value of field f, coefficient j, line
+// l: an array [field][n][line] (ArraySrc), or the channel step's fields formed
+// from the FP64 state as they are loaded (ChanFieldSrc: u, v by continuity and
+// the definition of omega_z, w, phi, i ky phi, D phi).
+template <typename T>
+struct ArraySrc {
+  const cpx<T>* in;
+  long long fstride, nlines;
+  __device__ __forceinline__ cpx<T> operator()(int f, long long j, long long l) const {
+    return in[f * fstride + j * nlines + l];
+  }
+};
+template <typename T>
+struct ChanFieldSrcT {
+  ChanFieldSrc s;
+  __device__ __forceinline__ cpx<T> operator()(int f, long long j, long long l) const {
+    const long long id = j * s.nlines + l;
+    cpx<double> x;
+    if (f <= 1) {
+      if (l == 0) {                          // the mean line carries U, V
+        x = s.mean[2 * j + f];
+      } else {
+        const double kx = s.kx[l], ky = s.ky[l];
+        const double ik2 = 1.0 / (kx * kx + ky * ky);
+        const cpx<double> o = s.om[id], d = s.dw[id];
+        const cpx<double> a = (f == 0) ? cpx<double>{kx * d.re + ky * o.re, kx * d.im + ky * o.im}
+                                       : cpx<double>{ky * d.re - kx * o.re, ky * d.im - kx * o.im};
+        x = cpx<double>{ik2 * (-1.0 * a.im), ik2 * (1.0 * a.re)};   // i a / k^2
+      }
+    } else if (f == 2) {
+      x = s.w[id];
+    } else if (f == 3) {
+      x = s.phi[id];
+    } else if (f == 4) {
+      const double ky = s.ky[l];
+      const cpx<double> p = s.phi[id];
+      x = cpx<double>{-ky * p.im, ky * p.re};
+    } else {
+      x = s.dphi[id];
+    }
+    return cpx<T>{T(x.re), T(x.im)};
+  }
+};
+
+template <typename T, int N, class Src>
+__global__ void __launch_bounds__(1024) k_dct(Src src, cpx<T>* __restrict__ out,
                                              long long nlines, int dir, long long fstride,
                                              const cpx<T>* __restrict__ tw_g, cpx<double>* __restrict__ out64,
                                              int kz) {
@@ -60,8 +104,7 @@ __global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx
   __shared__ cpx<T> lds[2][N * LP];
   const int tid = threadIdx.x;
   const int line = tid % L, t = tid / L;
-  in += (long long)blockIdx.y * fstride;   // field blockIdx.y
-  out += (long long)blockIdx.y * fstride;
+  out += (long long)blockIdx.y * fstride;   // field blockIdx.y
   if (out64) out64 += (long long)blockIdx.y * fstride;
   if (tw_g) {
     for (int i = tid; i < N; i += blockDim.x) tw[i] = tw_g[i];
@@ -83,7 +126,7 @@ __global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx
       const int j = (p <= NC) ? p : N - p;
       cpx<T> x = {T(0), T(0)};
       if (valid) {
-        x = in[(long long)j * nlines + l];
+        x = src(int(blockIdx.y), j, l);
         if (dir < 0 && j != 0 && j != NC) {
           x.re *= T(0.5);
           x.im *= T(0.5);
@@ -130,8 +173,8 @@ __global__ void __launch_bounds__(1024) k_dct(const cpx<T>* __restrict__ in, cpx
 // line sums a contiguous run of k, and the runs' totals give every thread its
 // starting value.  dir = +1: x = f, a_n = 2 C_n / (nc cbar_n); dir = -1:
 // x = cbar a, f_j = C_j.  tw_g: exp(-i pi m / nc), m < 2 nc (or NULL).
-template <typename T, int NC>
-__global__ void __launch_bounds__(1024) k_dct_half(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+template <typename T, int NC, class Src>
+__global__ void __launch_bounds__(1024) k_dct_half(Src src, cpx<T>* __restrict__ out,
                                                   long long nlines, int dir, long long fstride,
                                                   const cpx<T>* __restrict__ tw_g, cpx<double>* __restrict__ out64,
                                                   int kz) {
@@ -148,7 +191,6 @@ __global__ void __launch_bounds__(1024) k_dct_half(const cpx<T>* __restrict__ in
   __shared__ cpx<T> lds[2][NC * LP];
   const int tid = threadIdx.x;
   const int line = tid % L, t = tid / L;
-  in += (long long)blockIdx.y * fstride;
   out += (long long)blockIdx.y * fstride;
   if (out64) out64 += (long long)blockIdx.y * fstride;
   for (int i = tid; i < 2 * NC; i += blockDim.x) {
@@ -176,8 +218,8 @@ __global__ void __launch_bounds__(1024) k_dct_half(const cpx<T>* __restrict__ in
       const int j = slot_pos<P, RI>(t, b, r);    // 0 .. NC-1
       cpx<T> y = {T(0), T(0)};
       if (valid) {
-        cpx<T> xa = in[(long long)j * nlines + l];
-        cpx<T> xb = in[(long long)(NC - j) * nlines + l];   // x_{NC-j} (x_NC for j = 0)
+        cpx<T> xa = src(int(blockIdx.y), j, l);
+        cpx<T> xb = src(int(blockIdx.y), NC - j, l);   // x_{NC-j} (x_NC for j = 0)
         if (dir < 0 && j == 0) {                 // x = cbar a: the end points doubled
           xa = cpx<T>{T(2) * xa.re, T(2) * xa.im};
           xb = cpx<T>{T(2) * xb.re, T(2) * xb.im};
@@ -1176,8 +1218,8 @@ bool supported_nc(int nc) {
 }
 
 namespace {
-template <typename T, int N>
-hipError_t dct_n(const cpx<T>* in, cpx<T>* out, long long nlines, int dir, long long fstride, int nfield,
+template <typename T, int N, class Src>
+hipError_t dct_n(const Src& in, cpx<T>* out, long long nlines, int dir, long long fstride, int nfield,
                  const cpx<T>* tw, cpx<double>* out64, int kz, hipStream_t st) {
   // FP64 lines take the nc-point route (measured at nc = 128 on the channel
   // workload: 56.7 us per launch against 72.1 us for the 2 nc-point FFT); FP32
@@ -1187,11 +1229,11 @@ hipError_t dct_n(const cpx<T>* in, cpx<T>* out, long long nlines, int dir, long 
   if constexpr (N >= 16 && sizeof(T) == 8) {   // nc = N / 2 >= 8
     using G = CTile<Plan<N / 2>>;
     const dim3 grid(unsigned((nlines + G::L - 1) / G::L), unsigned(nfield));
-    k_dct_half<T, N / 2><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw, out64, kz);
+    k_dct_half<T, N / 2, Src><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw, out64, kz);
   } else {
     using G = CTile<Plan<N>>;
     const dim3 grid(unsigned((nlines + G::L - 1) / G::L), unsigned(nfield));
-    k_dct<T, N><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw, out64, kz);
+    k_dct<T, N, Src><<<grid, unsigned(G::L * G::TT), 0, st>>>(in, out, nlines, dir, fstride, tw, out64, kz);
   }
   return hipGetLastError();
 }
@@ -1211,13 +1253,31 @@ hipError_t launch_dct_fields(int nc, const cpx<T>* in, cpx<T>* out, long long nl
                              const cpx<T>* tw, int dir, hipStream_t st, cpx<double>* out64, int kz) {
   if (nfield < 1 || nlines == 0) return hipSuccess;
   if (out64 && dir < 0) return hipErrorInvalidValue;
+  const ArraySrc<T> src{in, fstride, nlines};
   switch (2 * nc) {
-#define PSMS_CASE(NN) case NN: return dct_n<T, NN>(in, out, nlines, dir, fstride, nfield, tw, out64, kz, st);
+#define PSMS_CASE(NN) case NN: return dct_n<T, NN>(src, out, nlines, dir, fstride, nfield, tw, out64, kz, st);
     PSMS_FOR_EACH_2NC(PSMS_CASE)
 #undef PSMS_CASE
   }
   return hipErrorInvalidValue;
 }
+
+template <typename T>
+hipError_t launch_dct_chfields(int nc, const ChanFieldSrc& fs, cpx<T>* out, long long fstride, const cpx<T>* tw,
+                               hipStream_t st) {
+  if (fs.nlines == 0) return hipSuccess;
+  const ChanFieldSrcT<T> src{fs};
+  switch (2 * nc) {
+#define PSMS_CASE(NN) case NN: return dct_n<T, NN>(src, out, fs.nlines, -1, fstride, 6, tw, nullptr, 0, st);
+    PSMS_FOR_EACH_2NC(PSMS_CASE)
+#undef PSMS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_dct_chfields<float>(int, const ChanFieldSrc&, cpx<float>*, long long, const cpx<float>*,
+                                               hipStream_t);
+template hipError_t launch_dct_chfields<double>(int, const ChanFieldSrc&, cpx<double>*, long long,
+                                                const cpx<double>*, hipStream_t);
 
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
                              int lapmask, hipStream_t st) {

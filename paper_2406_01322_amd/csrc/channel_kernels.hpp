@@ -19,6 +19,24 @@ hipError_t launch_dct(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, i
 template <typename T>
 hipError_t launch_dct_fields(int nc, const cpx<T>* in, cpx<T>* out, long long nlines, long long fstride, int nfield,
                              const cpx<T>* tw, int dir, hipStream_t st, cpx<double>* out64 = nullptr, int kz = 0);
+// The inverse transform of the channel step's six fields u, v, w, phi, i ky phi,
+// D phi ([6][n][line] out, fstride apart), each value formed from the FP64
+// state as it is loaded (u, v by continuity and the definition of omega_z;
+// the mean line, l = 0, carries U, V from mean [n][2]).
+struct ChanFieldSrc {
+  const cpx<double>* om;
+  const cpx<double>* w;
+  const cpx<double>* phi;
+  const cpx<double>* dw;
+  const cpx<double>* dphi;
+  const cpx<double>* mean;
+  const double* kx;
+  const double* ky;
+  long long nlines;
+};
+template <typename T>
+hipError_t launch_dct_chfields(int nc, const ChanFieldSrc& fs, cpx<T>* out, long long fstride, const cpx<T>* tw,
+                               hipStream_t st);
 hipError_t launch_chebd(const cpx<double>* a, cpx<double>* d, int nc, long long nlines, hipStream_t st);
 // up to kChebBatchMax arrays of the same lines per launch: out[j] = D in[j]
 // (bit j of lapmask clear) or D^2 in[j] - k^2 in[j] (bit j set)
