@@ -1761,7 +1761,7 @@ hipError_t chan_step_once(psms_channel* c) {
   // D T_xz, D T_yz, D T_zz and D^2 - k^2 of omega_z, w, c and phi; then D Q
   // (Q = div_h S, S = div T, formed on the fly)
   cpx<double>* D3 = C64(L.D3);
-  cb.n = g.sp ? 5 : 7;
+  cb.n = g.sp ? 6 : 8;
   cb.in[0] = R + 4 * g.NZL;
   cb.out[0] = D3;
   cb.in[1] = R + 5 * g.NZL;
@@ -1777,10 +1777,14 @@ hipError_t chan_step_once(psms_channel* c) {
   cb.out[5] = C64(L.lapc);
   cb.in[6] = phi;
   cb.out[6] = C64(L.lapphi);
-  PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0x78, st));   // arrays 3.. : D^2 - k^2
+  const int mj = g.sp ? 5 : 7;   // the mean lines U, V ([nc+1][2], k = 0): D^2
+  cb.in[mj] = C64(L.mean);
+  cb.out[mj] = C64(L.d2mean);
+  cb.nl[mj] = 2;
+  cb.nok = 1 << mj;
+  PSMS_TRY(psms::launch_cheb_batch(cb, nc, nl, kx, ky, 0xF8, st));   // arrays 3.. : D^2 - k^2
   psms::ChebQ cq{R, R + g.NZL, R + 3 * g.NZL, D3, D3 + g.NZL};
   PSMS_TRY(psms::launch_chebd_q(cq, nc, nl, kx, ky, C64(L.DQ), st));
-  PSMS_TRY(psms::launch_cheb_lap(C64(L.mean), C64(L.d2mean), nc, 2, nullptr, nullptr, st));
   // 6. Adams-Bashforth, Crank-Nicolson / implicit Euler right-hand sides
   c->coef.ab1 = (c->nstep == 0) ? 1 : 0;
   psms::ChanAssembleArgs aa{};

@@ -342,6 +342,8 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
                                                   const double* __restrict__ kx, const double* __restrict__ ky,
                                                   int lapmask) {
   const int lap = (lapmask >> blockIdx.y) & 1;   // uniform in the workgroup
+  if (bt.nl[blockIdx.y]) nlines = bt.nl[blockIdx.y];
+  if ((bt.nok >> blockIdx.y) & 1) kx = nullptr;
   const int lane = threadIdx.x & 63;
   const int pc = lane >> 3;
   const long long groups = (nlines + 7) / 8;
@@ -1282,6 +1284,8 @@ template hipError_t launch_dct_chfields<double>(int, const ChanFieldSrc&, cpx<do
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
                              int lapmask, hipStream_t st) {
   if (b.n < 0 || b.n > kChebBatchMax || nlines < 0 || nc < 1) return hipErrorInvalidValue;
+  for (int j = 0; j < b.n; ++j)
+    if (b.nl[j] < 0 || b.nl[j] > nlines) return hipErrorInvalidValue;
   if (b.n == 0 || nlines == 0) return hipSuccess;
   const int need = (nc / 2 + 1 + 7) / 8;   // terms per piece (8 pieces per chain)
   const dim3 grid(blocks(2 * ((nlines + 7) / 8) * 64, 256), unsigned(b.n));

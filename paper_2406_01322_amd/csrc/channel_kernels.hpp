@@ -45,6 +45,8 @@ struct ChebBatch {
   const cpx<double>* in[kChebBatchMax];
   cpx<double>* out[kChebBatchMax];
   cpx<double>* out2[kChebBatchMax];   // D^2 - k^2 arrays: (D^2 - k^2)^2 in[j] as well where non-NULL
+  long long nl[kChebBatchMax];        // lines of array j if nonzero (at most the launch's nlines), else nlines
+  int nok;                            // bit j: k^2 = 0 for array j (lines that are not (kx, ky) pairs)
   int n;
 };
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,
