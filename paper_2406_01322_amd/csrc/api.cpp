@@ -1482,7 +1482,7 @@ namespace {
 struct ChanLayout {
   size_t kx, ky, twx64, twx32, twy64, twy32, twz64, twz32;
   size_t state, mean, hist, hmean;
-  size_t dw, dphi, A, A2, B, C, R, D3, DQ, lapc, lapphi, lapom, psi, lappsi, G;
+  size_t dw, dphi, A, A2, B, C, R, D3, DQ, lapc, lapom, lappsi, G;
   size_t d2mean, gmean, wt, wb, M, whp, mhp, psip, xi, xw, diag, xdev, fac, total;
   bool has_fac;   // the step's tau problems read precomputed elimination factors
 };
@@ -1547,9 +1547,7 @@ ChanLayout chan_layout(const psms_channel_params& p) {
   take(L.D3, 3 * arr);
   take(L.DQ, arr);
   take(L.lapc, arr);
-  take(L.lapphi, arr);
   take(L.lapom, arr);
-  take(L.psi, arr);
   take(L.lappsi, arr);
   take(L.G, 3 * arr);
   take(L.d2mean, 2 * nz * c64);
@@ -1758,10 +1756,12 @@ hipError_t chan_step_once(psms_channel* c) {
     PSMS_TRY(chan_forward_yz<T>(c, c->at<cpx<T>>(L.C), c->at<cpx<T>>(L.A), 8, R));
   }
   // 5. the wall-normal derivatives the right-hand sides need, in one launch:
-  // D T_xz, D T_yz, D T_zz and D^2 - k^2 of omega_z, w, c and phi; then D Q
-  // (Q = div_h S, S = div T, formed on the fly)
+  // D T_xz, D T_yz, D T_zz; (D^2 - k^2 + beta) omega_z; (D^2 - k^2 + beta) psi,
+  // psi = (D^2 - k^2) w (its chain is in the same wavefront); D^2 - k^2 of
+  // c / Pe - (1 + s Ch^2) / Pe phi; D^2 of the mean lines; then D Q (Q =
+  // div_h S, S = div T, formed on the fly)
   cpx<double>* D3 = C64(L.D3);
-  cb.n = g.sp ? 6 : 8;
+  cb.n = g.sp ? 6 : 7;
   cb.in[0] = R + 4 * g.NZL;
   cb.out[0] = D3;
   cb.in[1] = R + 5 * g.NZL;
@@ -1770,14 +1770,19 @@ hipError_t chan_step_once(psms_channel* c) {
   cb.out[2] = D3 + 2 * g.NZL;
   cb.in[3] = om;
   cb.out[3] = C64(L.lapom);
+  cb.addb[3] = c->coef.beta;
   cb.in[4] = w;
-  cb.out[4] = C64(L.psi);
-  cb.out2[4] = C64(L.lappsi);   // and lap psi
-  cb.in[5] = R + 7 * g.NZL;
-  cb.out[5] = C64(L.lapc);
-  cb.in[6] = phi;
-  cb.out[6] = C64(L.lapphi);
-  const int mj = g.sp ? 5 : 7;   // the mean lines U, V ([nc+1][2], k = 0): D^2
+  cb.out[4] = nullptr;            // psi itself is not needed
+  cb.out2[4] = C64(L.lappsi);
+  cb.addb2[4] = c->coef.beta;
+  if (!g.sp) {
+    cb.in[5] = R + 7 * g.NZL;
+    cb.in2[5] = phi;
+    cb.w1[5] = c->coef.inv_pe;
+    cb.w2[5] = -c->coef.e_coef;
+    cb.out[5] = C64(L.lapc);
+  }
+  const int mj = g.sp ? 5 : 6;   // the mean lines U, V ([nc+1][2], k = 0): D^2
   cb.in[mj] = C64(L.mean);
   cb.out[mj] = C64(L.d2mean);
   cb.nl[mj] = 2;
@@ -1791,13 +1796,10 @@ hipError_t chan_step_once(psms_channel* c) {
   aa.d3 = D3;
   aa.dq = C64(L.DQ);
   aa.R = R;
-  aa.lapc = C64(L.lapc);
+  aa.lsphi = C64(L.lapc);
   aa.phi = phi;
-  aa.lapphi = C64(L.lapphi);
-  aa.om = om;
-  aa.lapom = C64(L.lapom);
-  aa.psi = C64(L.psi);
-  aa.lappsi = C64(L.lappsi);
+  aa.lom = C64(L.lapom);
+  aa.lpsi = C64(L.lappsi);
   aa.kx = kx;
   aa.ky = ky;
   aa.hist = C64(L.hist);

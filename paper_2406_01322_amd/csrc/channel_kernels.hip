@@ -414,18 +414,30 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
       res[k] = (i0 + k < cnt) ? cpx<double>{s * cm.re - k2 * in[k].re, s * cm.im - k2 * in[k].im} : zero;
     }
   };
+  const cpx<double>* __restrict__ a2 = bt.in2[blockIdx.y];
+  const double w1 = bt.w1[blockIdx.y], w2 = bt.w2[blockIdx.y];
+  const double ab = bt.addb[blockIdx.y], ab2 = bt.addb2[blockIdx.y];
   cpx<double> av[LEN], r1[LEN];
 #pragma unroll
   for (int k = 0; k < LEN; ++k) {
     const int m = top - 2 * (i0 + k);
     av[k] = zero;
-    if (valid && i0 + k < cnt) av[k] = a[(long long)m * nlines + l];
+    if (valid && i0 + k < cnt) {
+      av[k] = a[(long long)m * nlines + l];
+      if (a2) {
+        const cpx<double> b = a2[(long long)m * nlines + l];
+        av[k] = cpx<double>{w1 * av[k].re + w2 * b.re, w1 * av[k].im + w2 * b.im};
+      }
+    }
   }
   lap_pass(av, r1);
+  if (out) {
 #pragma unroll
-  for (int k = 0; k < LEN; ++k) {
-    const int m = top - 2 * (i0 + k);
-    if (valid && i0 + k < cnt) out[(long long)m * nlines + l] = r1[k];
+    for (int k = 0; k < LEN; ++k) {
+      const int m = top - 2 * (i0 + k);
+      if (valid && i0 + k < cnt)
+        out[(long long)m * nlines + l] = cpx<double>{r1[k].re + ab * av[k].re, r1[k].im + ab * av[k].im};
+    }
   }
   // optionally (D^2 - k^2)^2 as well: the chain of the result is in this wavefront
   cpx<double>* __restrict__ out2 = bt.out2[blockIdx.y];
@@ -434,7 +446,8 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
 #pragma unroll
     for (int k = 0; k < LEN; ++k) {
       const int m = top - 2 * (i0 + k);
-      if (valid && i0 + k < cnt) out2[(long long)m * nlines + l] = av[k];
+      if (valid && i0 + k < cnt)
+        out2[(long long)m * nlines + l] = cpx<double>{av[k].re + ab2 * r1[k].re, av[k].im + ab2 * r1[k].im};
     }
   }
 }

@@ -47,6 +47,11 @@ struct ChebBatch {
   cpx<double>* out2[kChebBatchMax];   // D^2 - k^2 arrays: (D^2 - k^2)^2 in[j] as well where non-NULL
   long long nl[kChebBatchMax];        // lines of array j if nonzero (at most the launch's nlines), else nlines
   int nok;                            // bit j: k^2 = 0 for array j (lines that are not (kx, ky) pairs)
+  // D^2 - k^2 arrays only: the input is w1 in + w2 in2 where in2[j] is non-NULL,
+  // out[j] (if non-NULL) receives (D^2 - k^2) x + addb x, out2[j] (D^2 - k^2)^2 x
+  // + addb2 (D^2 - k^2) x
+  const cpx<double>* in2[kChebBatchMax];
+  double w1[kChebBatchMax], w2[kChebBatchMax], addb[kChebBatchMax], addb2[kChebBatchMax];
   int n;
 };
 hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const double* kx, const double* ky,

@@ -116,12 +116,10 @@ __global__ void k_ch_assemble(ChanGeom g, ChanCoef c, ChanAssembleArgs a) {
     a.hist[id] = h_om;
     a.hist[g.NZL + id] = h_w;
     const double r2 = 2.0 * c.re;
-    const cpx<double> om = a.om[id], psi = a.psi[id];
-    a.g[id] = sub(scl(-1.0, add(a.lapom[id], scl(c.beta, om))), scl(r2, e_om));
-    a.g[g.NZL + id] = sub(scl(-1.0, add(a.lappsi[id], scl(c.beta, psi))), scl(r2, e_w));
+    a.g[id] = sub(scl(-1.0, a.lom[id]), scl(r2, e_om));        // -(lap + beta) omega - 2 Re E
+    a.g[g.NZL + id] = sub(scl(-1.0, a.lpsi[id]), scl(r2, e_w));
     if (!g.sp) {
-      const cpx<double> s_phi = add(sub(scl(c.inv_pe, a.lapc[id]), a.R[6 * g.NZL + id]),
-                                    scl(-c.e_coef, a.lapphi[id]));  // -a + lap c / Pe - (1 + s Ch^2)/Pe lap phi
+      const cpx<double> s_phi = sub(a.lsphi[id], a.R[6 * g.NZL + id]);  // -a + lap c / Pe - (1 + s Ch^2)/Pe lap phi
       const cpx<double> e_phi = ab(s_phi, a.hist[2 * g.NZL + id], c.ab1);
       a.hist[2 * g.NZL + id] = s_phi;
       a.g[2 * g.NZL + id] = scl(c.g_phi_scale, add(a.phi[id], scl(c.dt, e_phi)));

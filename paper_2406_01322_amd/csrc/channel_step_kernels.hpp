@@ -46,13 +46,10 @@ struct ChanAssembleArgs {
   const cpx<double>* d3;      // [3][NZL] D T_xz, D T_yz, D T_zz (S = div T is formed from them and R)
   const cpx<double>* dq;      // D Q, Q = i kx S_x + i ky S_y
   const cpx<double>* R;       // products T_xx T_yy T_zz T_xy T_xz T_yz, field 6 = a, 7 = c
-  const cpx<double>* lapc;    // lap c
+  const cpx<double>* lsphi;   // lap (c / Pe - (1 + s Ch^2) / Pe phi^n)
   const cpx<double>* phi;     // phi^n
-  const cpx<double>* lapphi;  // lap phi^n
-  const cpx<double>* om;      // omega^n
-  const cpx<double>* lapom;   // lap omega^n
-  const cpx<double>* psi;     // lap w^n
-  const cpx<double>* lappsi;  // lap psi
+  const cpx<double>* lom;     // lap omega^n + beta omega^n
+  const cpx<double>* lpsi;    // lap psi + beta psi, psi = lap w^n
   const double* kx;
   const double* ky;
   cpx<double>* hist;          // [3][NZL] H_omega, H_w, S_phi of the previous step (in/out)
