@@ -2,18 +2,22 @@
 //
 //  * k_dct: the Chebyshev transform as a DCT-I obtained from the FFT of the
 //    2 nc-point even extension of each line (Sec. 3.2.1), applied to the real
-//    and imaginary parts at once.  Lines are (kx, ky) pairs, stored
-//    position-major ([n][line]), so the lanes of a wavefront read consecutive
-//    lines and no transpose is needed.
-//  * k_cheb_seg: derivative (and D^2 - k^2) in coefficient space, the
-//    backward recurrence c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n summed piecewise
-//    along each parity chain.
+//    and imaginary parts at once; k_dct_half the same through one nc-point
+//    FFT.  Lines are (kx, ky) pairs, stored position-major ([n][line]), so the
+//    lanes of a wavefront read consecutive lines and no transpose is needed.
+//    Both read through a source: an array, or the channel step's fields formed
+//    from the state as they are loaded.
+//  * k_cheb_seg, k_cheb_seg_q: derivative (and D^2 - k^2) in coefficient
+//    space, the backward recurrence c_{n-1} b_{n-1} = b_{n+1} + 2 n a_n summed
+//    piecewise along each parity chain.
 //  * k_helm: the Chebyshev-tau Helmholtz problem (D^2 - beta) f = g with two
 //    Dirichlet or Neumann boundary rows, in FP64.  Rewriting the tau rows with
 //    the integration recurrence turns each parity (even / odd n) into a
 //    tridiagonal system plus one boundary row; it is solved by one downward
 //    elimination sweep and two upward sweeps, one thread per (line, parity)
-//    (the banded wall-normal solves of Sec. 3.2.2).
+//    (the banded wall-normal solves of Sec. 3.2.2).  k_helm_batch_reg keeps a
+//    chain on chip; k_helm_factors stores a context's elimination factors,
+//    from which k_helm_pieces solves each chain in 8 pieces (affine-map scans).
 //  * k_influence, k_uv: the influence-matrix combination that enforces
 //    w' = 0 at the walls, and u, v from continuity and eq. omegadef.
 #include <hip/hip_runtime.h>

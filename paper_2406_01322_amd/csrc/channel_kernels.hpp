@@ -94,11 +94,12 @@ struct HelmProblem {
   // their sums sum n^2 wh_n; f = 0 on the line kx = ky = 0
   const double* wh = nullptr;
   const double* mh = nullptr;
-  // optional (on-chip path only): the elimination factors of the problem's
-  // beta_add + k^2 and wall conditions, from launch_helm_factors
-  // (helm_factor_doubles(nc, nlines) doubles); the problem's beta_add, kx, ky,
-  // bc and nlines must be those the factors were made with.  Given for all
-  // problems of a batch or for none.
+  // optional (nc with helm_fuses_influence(nc), bc 0 or 3): the elimination
+  // factors of the problem's beta_add + k^2 and wall conditions, from
+  // launch_helm_factors (helm_factor_doubles(nc, nlines) doubles); the
+  // problem's beta_add, kx, ky, bc and nlines must be those the factors were
+  // made with.  Given for all problems of a batch or for none; then the batch
+  // is solved in pieces (k_helm_pieces).
   const double* fac = nullptr;
 };
 struct HelmBatch {
