@@ -326,35 +326,37 @@ __global__ void __launch_bounds__(1024) k_dct_half(Src src, cpx<T>* __restrict__
 // load per term.)
 namespace {
 
-__device__ __forceinline__ cpx<double> shfl_up8(cpx<double> v, int pieces) {
-  return cpx<double>{__shfl_up(v.re, 8 * pieces), __shfl_up(v.im, 8 * pieces)};
-}
-// exclusive scan over the 8 pieces of a chain (lanes 8 apart), piece `pc` of this lane
+// exclusive scan over the PC pieces of a chain (lanes 64 / PC apart), piece
+// `pc` of this lane
+template <int PC>
 __device__ __forceinline__ cpx<double> piece_carry(cpx<double> tot, int pc) {
+  constexpr int LPW = 64 / PC;
+  auto up = [](cpx<double> v, int d) { return cpx<double>{__shfl_up(v.re, LPW * d), __shfl_up(v.im, LPW * d)}; };
   cpx<double> inc = tot;
 #pragma unroll
-  for (int d = 1; d < 8; d <<= 1) {
-    const cpx<double> o = shfl_up8(inc, d);
+  for (int d = 1; d < PC; d <<= 1) {
+    const cpx<double> o = up(inc, d);
     if (pc >= d) inc = cadd(inc, o);
   }
-  const cpx<double> ex = shfl_up8(inc, 1);
+  const cpx<double> ex = up(inc, 1);
   return pc == 0 ? cpx<double>{0.0, 0.0} : ex;
 }
 
-template <int LEN>
+template <int LEN, int PC>
 __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long long nlines,
                                                   const double* __restrict__ kx, const double* __restrict__ ky,
                                                   int lapmask) {
+  constexpr int LPW = 64 / PC;   // lines per wavefront
   const int lap = (lapmask >> blockIdx.y) & 1;   // uniform in the workgroup
   if (bt.nl[blockIdx.y]) nlines = bt.nl[blockIdx.y];
   if ((bt.nok >> blockIdx.y) & 1) kx = nullptr;
   const int lane = threadIdx.x & 63;
-  const int pc = lane >> 3;
-  const long long groups = (nlines + 7) / 8;
+  const int pc = lane / LPW;
+  const long long groups = (nlines + LPW - 1) / LPW;
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (wave >= 2 * groups) return;   // whole wavefronts
   const int q = int(wave / groups);
-  const long long l = (wave % groups) * 8 + (lane & 7);
+  const long long l = (wave % groups) * LPW + (lane % LPW);
   const bool valid = l < nlines;
   const cpx<double>* __restrict__ a = bt.in[blockIdx.y];
   cpx<double>* __restrict__ out = bt.out[blockIdx.y];
@@ -375,7 +377,7 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
     }
 #pragma unroll
     for (int k = 1; k < LEN; ++k) x[k] = cadd(x[k - 1], x[k]);
-    const cpx<double> c = piece_carry(x[LEN - 1], pc);
+    const cpx<double> c = piece_carry<PC>(x[LEN - 1], pc);
 #pragma unroll
     for (int k = 0; k < LEN; ++k) {
       const int m = top - 2 * (i0 + k);
@@ -399,7 +401,7 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
       x[k] = run;
       run = cadd(run, cpx<double>{2.0 * m * in[k].re, 2.0 * m * in[k].im});
     }
-    const cpx<double> c1 = piece_carry(run, pc);
+    const cpx<double> c1 = piece_carry<PC>(run, pc);
     // c_m = sum of 2 (j+1) b_{j+1} over j >= m: inclusive sums
     run = zero;
 #pragma unroll
@@ -409,7 +411,7 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
       run = cadd(run, cpx<double>{2.0 * (m + 1) * bm1.re, 2.0 * (m + 1) * bm1.im});
       x[k] = run;
     }
-    const cpx<double> c2 = piece_carry(run, pc);
+    const cpx<double> c2 = piece_carry<PC>(run, pc);
 #pragma unroll
     for (int k = 0; k < LEN; ++k) {
       const int m = top - 2 * (i0 + k);
@@ -461,17 +463,18 @@ __global__ void __launch_bounds__(256) k_cheb_seg(ChebBatch bt, int nc, long lon
 // S_y = i kx T_xy + i ky T_yy + D T_yz (the horizontal divergence of the
 // stress divergence), with Q formed term by term from its five arrays as it
 // is loaded: the pieced D recurrence of k_cheb_seg.
-template <int LEN>
+template <int LEN, int PC>
 __global__ void __launch_bounds__(256) k_cheb_seg_q(ChebQ in, int nc, long long nlines,
                                                     const double* __restrict__ kxl, const double* __restrict__ kyl,
                                                     cpx<double>* __restrict__ out) {
+  constexpr int LPW = 64 / PC;   // lines per wavefront
   const int lane = threadIdx.x & 63;
-  const int pc = lane >> 3;
-  const long long groups = (nlines + 7) / 8;
+  const int pc = lane / LPW;
+  const long long groups = (nlines + LPW - 1) / LPW;
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (wave >= 2 * groups) return;   // whole wavefronts
   const int q = int(wave / groups);
-  const long long l = (wave % groups) * 8 + (lane & 7);
+  const long long l = (wave % groups) * LPW + (lane % LPW);
   const bool valid = l < nlines;
   const double kx = valid ? kxl[l] : 0.0, ky = valid ? kyl[l] : 0.0;
   auto ti = [](double k, cpx<double> a) { return cpx<double>{-k * a.im, k * a.re}; };
@@ -494,7 +497,7 @@ __global__ void __launch_bounds__(256) k_cheb_seg_q(ChebQ in, int nc, long long 
   }
 #pragma unroll
   for (int k = 1; k < LEN; ++k) x[k] = cadd(x[k - 1], x[k]);
-  const cpx<double> c = piece_carry(x[LEN - 1], pc);
+  const cpx<double> c = piece_carry<PC>(x[LEN - 1], pc);
 #pragma unroll
   for (int k = 0; k < LEN; ++k) {
     const int m = top - 2 * (i0 + k);
@@ -1304,16 +1307,20 @@ hipError_t launch_cheb_batch(const ChebBatch& b, int nc, long long nlines, const
   for (int j = 0; j < b.n; ++j)
     if (b.nl[j] < 0 || b.nl[j] > nlines) return hipErrorInvalidValue;
   if (b.n == 0 || nlines == 0) return hipSuccess;
-  const int need = (nc / 2 + 1 + 7) / 8;   // terms per piece (8 pieces per chain)
-  const dim3 grid(blocks(2 * ((nlines + 7) / 8) * 64, 256), unsigned(b.n));
-#define PSMS_SEG(LEN) \
-  if (need <= LEN) { \
-    k_cheb_seg<LEN><<<grid, 256, 0, st>>>(b, nc, nlines, kx, ky, lapmask); \
+  // 8 pieces per chain (8 lines a wavefront) up to 9 terms a piece, else 16
+  // pieces (4 lines a wavefront), which keeps the longest chains (nc = 256) at
+  // 9 terms a piece and off the register limit
+  const int need = (nc / 2 + 1 + 7) / 8;
+  const int pcs = need <= 9 ? 8 : 16;
+  const dim3 grid(blocks(2 * ((nlines + 64 / pcs - 1) / (64 / pcs)) * 64, 256), unsigned(b.n));
+#define PSMS_SEG(LEN, PCS) \
+  if (pcs == PCS && (nc / 2 + PCS) / PCS <= LEN) { \
+    k_cheb_seg<LEN, PCS><<<grid, 256, 0, st>>>(b, nc, nlines, kx, ky, lapmask); \
     return hipGetLastError(); \
   }
-  PSMS_SEG(1) PSMS_SEG(2) PSMS_SEG(3) PSMS_SEG(5) PSMS_SEG(9) PSMS_SEG(17)
+  PSMS_SEG(1, 8) PSMS_SEG(2, 8) PSMS_SEG(3, 8) PSMS_SEG(5, 8) PSMS_SEG(9, 8) PSMS_SEG(9, 16)
 #undef PSMS_SEG
-  return hipErrorInvalidValue;   // nc > 270
+  return hipErrorInvalidValue;   // nc > 287
 }
 
 hipError_t launch_chebd_q(const ChebQ& in, int nc, long long nlines, const double* kx, const double* ky,
@@ -1321,13 +1328,14 @@ hipError_t launch_chebd_q(const ChebQ& in, int nc, long long nlines, const doubl
   if (nlines < 0 || nc < 1) return hipErrorInvalidValue;
   if (nlines == 0) return hipSuccess;
   const int need = (nc / 2 + 1 + 7) / 8;
-  const dim3 grid(blocks(2 * ((nlines + 7) / 8) * 64, 256));
-#define PSMS_SEG(LEN) \
-  if (need <= LEN) { \
-    k_cheb_seg_q<LEN><<<grid, 256, 0, st>>>(in, nc, nlines, kx, ky, out); \
+  const int pcs = need <= 9 ? 8 : 16;   // as in launch_cheb_batch
+  const dim3 grid(blocks(2 * ((nlines + 64 / pcs - 1) / (64 / pcs)) * 64, 256));
+#define PSMS_SEG(LEN, PCS) \
+  if (pcs == PCS && (nc / 2 + PCS) / PCS <= LEN) { \
+    k_cheb_seg_q<LEN, PCS><<<grid, 256, 0, st>>>(in, nc, nlines, kx, ky, out); \
     return hipGetLastError(); \
   }
-  PSMS_SEG(1) PSMS_SEG(2) PSMS_SEG(3) PSMS_SEG(5) PSMS_SEG(9) PSMS_SEG(17)
+  PSMS_SEG(1, 8) PSMS_SEG(2, 8) PSMS_SEG(3, 8) PSMS_SEG(5, 8) PSMS_SEG(9, 8) PSMS_SEG(9, 16)
 #undef PSMS_SEG
   return hipErrorInvalidValue;
 }
