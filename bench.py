@@ -84,17 +84,39 @@ def measured_traffic(stage, precision="mixed"):
     return rec["hbm_bytes_per_launch"].get(stage)
 
 
+SETTLE_MS = 40.0
+
+
+def settle(step, stream, ms=SETTLE_MS, chunk=25):
+    """Advance the workload `chunk` steps at a time until `ms` of wall time have passed,
+    before the warm-up steps of a timed leg.  From idle, the GPU's clocks ramp over
+    about 20 ms of load and the step time with them (128^3 MIXED step, 5-step regions
+    from a cold start: 0.089-0.098 ms over the first 7 ms, 0.0815 ms from 20 ms on);
+    the steps run here are reported (`settle_steps`) and not counted as warm-up."""
+    import torch
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        step(chunk)
+        done += chunk
+        stream.synchronize()
+        if (time.perf_counter() - t0) * 1e3 >= ms:
+            return done
+
+
 def run_gpu(precision, n, p, u, phi, steps, warmup):
-    """Time `steps` steps replayed from the step's hipGraph (HIP events bracketing the
-    region on the library's stream, plus the wall clock), then the same number of steps
-    launched eagerly with an event around every kernel for the per-kernel durations."""
+    """Time `steps` steps (the step's four kernels launched directly, which measured
+    faster than replaying a captured hipGraph of them; HIP events bracketing the region
+    on the library's stream, plus the wall clock), then the same number of steps with an
+    event around every kernel for the per-kernel durations."""
     import torch
     from paper_2406_01322_amd.psms import Solver
-    stream = torch.cuda.Stream()       # a capturable stream: steps replay a hipGraph
+    stream = torch.cuda.Stream()       # the library's stream (not the legacy default one)
     with torch.cuda.stream(stream):
         s = Solver(n, p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision)
         s.init_state(torch.from_numpy(u).cuda(), torch.from_numpy(phi).cuda())
-        s.step(max(warmup, 2))
+        nset = settle(s.step, stream)
+        s.step(warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -120,7 +142,7 @@ def run_gpu(precision, n, p, u, phi, steps, warmup):
     wall = t1 - t0
     med = sorted(reps + [ev_ms / steps])[2]
     return dict(wall=wall, ms_per_step=1e3 * wall / steps, value=n ** 3 * steps / wall,
-                event_ms_per_step=ev_ms / steps, median_of_5_ms_per_step=med,
+                event_ms_per_step=ev_ms / steps, median_of_5_ms_per_step=med, settle_steps=nset,
                 stage_ms=dict(zip(STAGES, ms)), diag=d)
 
 
@@ -173,8 +195,8 @@ def copy_peak(nbytes=1 << 30, reps=10):
 
 def bench_batch(steps=100, nbox=96):
     """The batched form: 96 independent boxes, N drawn from {32, 48, 64, 96}, 1-8 drops,
-    Re ~ U[50, 400], We ~ U[0.5, 5], MIXED; workgroup sizes autotuned; after the first
-    step every step is one hipGraph replay.  Timed with HIP events on the batch stream."""
+    Re ~ U[50, 400], We ~ U[0.5, 5], MIXED; workgroup sizes autotuned; each stage is one
+    launch per group of equal N.  Timed with HIP events on the batch stream."""
     import torch
     from paper_2406_01322_amd import synth
     from paper_2406_01322_amd.psms import Batch
@@ -183,7 +205,8 @@ def bench_batch(steps=100, nbox=96):
     tune = b.autotune(reps=3)
     for i, (p, u, phi) in enumerate(cases):
         b.init_state(i, torch.from_numpy(u), torch.from_numpy(phi))
-    b.step(2)                                   # AB1 step, graph capture
+    b.step(2)                                   # AB1 step and one AB2 step
+    nset = settle(b.step, b.stream)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(b.stream)
@@ -195,7 +218,7 @@ def bench_batch(steps=100, nbox=96):
     bad = [i for i in range(nbox) if b.diagnostics(i)["nonfinite"]]
     if bad:
         raise RuntimeError("batched boxes went non-finite: %s" % bad)
-    return {"boxes": nbox, "groups": b.groups(), "total_points": pts, "steps": steps,
+    return {"boxes": nbox, "groups": b.groups(), "total_points": pts, "steps": steps, "settle_steps": nset,
             "ms_per_step": ms / steps, "value": pts * steps / (ms * 1e-3), "unit": "grid-points*timesteps/s",
             "variants": {k: v["variants"] for k, v in tune["groups"].items()}}
 
@@ -229,7 +252,7 @@ def bench_adjoint(nsteps=50, seg_len=10):
 
 def bench_exact_cube(steps=50, precision="mixed"):
     """The 128^3 workload with the exact cube of phi (formed on the padded 192^3 grid)
-    instead of the grid cube: ms per step (graph replay, HIP events)."""
+    instead of the grid cube: ms per step (HIP events)."""
     import torch
     from paper_2406_01322_amd import synth
     from paper_2406_01322_amd.psms import Solver
@@ -240,6 +263,7 @@ def bench_exact_cube(steps=50, precision="mixed"):
                    stream=stream)
         s.init_state(torch.from_numpy(u).cuda(), torch.from_numpy(phi).cuda())
         s.step(3)
+        nset = settle(s.step, stream)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -247,7 +271,8 @@ def bench_exact_cube(steps=50, precision="mixed"):
         e1.record(stream)
         e1.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    return {"n": p["n"], "padded_grid": 192, "precision": precision, "steps": steps, "ms_per_step": ms,
+    return {"n": p["n"], "padded_grid": 192, "precision": precision, "steps": steps, "settle_steps": nset,
+            "ms_per_step": ms,
             "value": p["n"] ** 3 / (ms * 1e-3), "unit": "grid-points*timesteps/s"}
 
 
@@ -295,13 +320,14 @@ def bench_channel(steps=20, warmup=2, case="chan_256"):
     out = {"grid": [p["nx"], p["ny"], p["nc"] + 1], "points": npts, "steps": steps, "single_phase": sp}
     f = [torch.from_numpy(x).cuda() for x in ((u, v, w) if sp else (u, v, w, phi))]
     del u, v, w, phi
-    stream = torch.cuda.Stream()       # a capturable stream: steps after the first replay a hipGraph
+    stream = torch.cuda.Stream()       # the library's stream (not the legacy default one)
     torch.cuda.synchronize()
     for prec in ("mixed", "fp64"):
         with torch.cuda.stream(stream):
             c = psms.Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=prec,
                              lx=p["lx"], ly=p["ly"], single_phase=sp, stream=stream)
             c.init_state(*f)
+            nset = settle(c.step, stream, chunk=5)
             c.step(warmup)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -310,7 +336,10 @@ def bench_channel(steps=20, warmup=2, case="chan_256"):
             e1.record(stream)
             e1.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        out[prec] = {"ms_per_step": ms, "value": npts / (ms * 1e-3)}
+        d = c.diagnostics()
+        if d["nonfinite"]:
+            raise RuntimeError("channel %s run produced a bad state: %s" % (prec, d))
+        out[prec] = {"ms_per_step": ms, "value": npts / (ms * 1e-3), "settle_steps": nset}
         c.close()
         del c
     out["unit"] = "grid-points*timesteps/s"
@@ -494,6 +523,9 @@ def main():
         "event_ms_per_step": r["event_ms_per_step"],
         "median_of_5": {"ms_per_step": r["median_of_5_ms_per_step"],
                         "value": n ** 3 / (r["median_of_5_ms_per_step"] * 1e-3)},
+        "settle": {"ms": SETTLE_MS, "steps": r["settle_steps"],
+                   "note": "steps run for SETTLE_MS of wall time before the warm-up steps, so that the "
+                           "timed steps run at the clocks the GPU holds under sustained load"},
         "stage_ms": r["stage_ms"],
         "stage_gbs": {k: sb[k] / (r["stage_ms"][k] * 1e-3) / 1e9 for k in STAGES},
         "copy_peak_gbs": copy_peak(),

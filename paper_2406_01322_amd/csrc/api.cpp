@@ -431,7 +431,7 @@ int psms_create(psms_ctx** out, const psms_params* p, void* d_workspace, size_t 
   c->h_box.sphi0 = reinterpret_cast<cpx<double>*>(c->diag_out + 6);
   c->box_ab1 = -1;
   for (int i = 0; i < 4; ++i) c->variant[i] = 2;
-  c->use_graph = 1;
+  c->use_graph = 0;      // eager launches unless psms_set_graphs enables the replay
   c->graph_ok = 0;
 
   // Twiddles exp(-2 pi i m / n) in FP64, rounded once to FP32 for MIXED.
@@ -1597,7 +1597,7 @@ struct psms_channel {
   psms::ChanCoef coef;
   ChanLayout lay;
   psms::BoxDev h_xdev;   // host copy of the x-stage descriptor (source of its upload)
-  int use_graph = 1;     // replay a captured step after the first (needs a non-NULL stream)
+  int use_graph = 0;     // replay a captured step after the first (psms_channel_set_graphs; needs a non-NULL stream)
   int graph_ok = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;

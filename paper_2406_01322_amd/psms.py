@@ -415,7 +415,7 @@ class Batch:
 
     params: list of dicts with n, re, we, ch, pe, dt (and optionally s).  All
     boxes share `precision`.  The batch runs on `stream` (default: a new
-    torch stream, which graph capture needs; use it with torch.cuda.stream).
+    torch stream, which graph capture needs (step(use_graph=True)); use it with torch.cuda.stream).
     """
 
     def __init__(self, params, precision="mixed", device="cuda", stream=None):
@@ -463,7 +463,7 @@ class Batch:
         _check(lib().psms_batch_init_state(self.h, int(box), _ptr(u), _ptr(phi)))
         self.stream.synchronize()
 
-    def step(self, nsteps=1, use_graph=True):
+    def step(self, nsteps=1, use_graph=False):
         _check(lib().psms_batch_step(self.h, int(nsteps), 1 if use_graph else 0))
 
     def get_state(self, box):

@@ -344,6 +344,7 @@ def test_graph_replay_matches_eager_steps():
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         g = _solver(p)
+        g.set_graphs(True)
         _load(g, st)
     for k in (1, 2, 3):
         eager.step(k)
@@ -356,18 +357,21 @@ def test_graph_replay_matches_eager_steps():
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("graphs", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_diagnostics_between_steps_leave_the_trajectory_unchanged(precision):
+def test_diagnostics_between_steps_leave_the_trajectory_unchanged(precision, graphs):
     """psms_diagnostics reuses the step's scratch for the CFL transforms; the next
     step must rebuild its input (bitwise the same trajectory, eager and graph)."""
     p, prm, st = _prepare("drops4_48", 0)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         a = _solver(p, precision)
+        a.set_graphs(graphs)
         _load(a, st)
         a.step(4)
         ua = a.get_state()
         b = _solver(p, precision)
+        b.set_graphs(graphs)
         _load(b, st)
         b.step(2)
         d = b.diagnostics()
@@ -431,6 +435,7 @@ def test_exact_cube_graph_replay_matches_eager_steps():
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         g = _solver_cube(p, stream=side)
+        g.set_graphs(True)
         _load(g, st)
     for k in (1, 2, 3):
         eager.step(k)

@@ -468,6 +468,7 @@ def test_channel_graph_replay_matches_eager_steps(precision, single_phase):
     with torch.cuda.stream(side):
         g = Channel(p["nx"], p["ny"], p["nc"], p["re"], p["we"], p["ch"], p["pe"], p["dt"], precision=precision,
                     lx=p["lx"], ly=p["ly"], single_phase=single_phase, stream=side)
+        g.set_graphs(True)
         g.init_state(*fields)
     for k in (1, 2, 3):
         eager.step(k)
