@@ -316,14 +316,14 @@ __global__ void __launch_bounds__(1024) k_dct_half(Src src, cpx<T>* __restrict__
 //   D:       c_m b_m = B_m = sum_{j >= m, j = m mod 2} 2 (j+1) a_{j+1}
 //   D^2:     b_{m+1} = sum_{p >= m+2, p = m mod 2} 2 p a_p,
 //            c_m (D^2 a)_m = sum_{j >= m, j = m mod 2} 2 (j+1) b_{j+1}.
-// A chain of cnt terms (m = top, top-2, ..) is cut into 8 pieces of at most
-// LEN terms; each lane sums its piece, and the pieces' totals are combined by
-// a scan across the lanes.  A wavefront holds the chains of one parity of 8
-// consecutive lines: lane = 8 piece + line, so that for one term the 8 lanes
-// of a piece read 8 consecutive lines (128 contiguous bytes), and each lane
-// issues its piece's loads at once.  (One lane per chain would leave a
-// 256 x 129 line set with fewer wavefronts than SIMDs, each waiting on one
-// load per term.)
+// A chain of cnt terms (m = top, top-2, ..) is cut into PC pieces (8, or 16
+// for the longest chains) of at most LEN terms; each lane sums its piece, and
+// the pieces' totals are combined by a scan across the lanes.  A wavefront
+// holds the chains of one parity of 64 / PC consecutive lines: lane =
+// (64 / PC) piece + line, so that for one term the lanes of a piece read
+// consecutive lines (128 or 64 contiguous bytes), and each lane issues its
+// piece's loads at once.  (One lane per chain would leave a 256 x 129 line set
+// with fewer wavefronts than SIMDs, each waiting on one load per term.)
 namespace {
 
 // exclusive scan over the PC pieces of a chain (lanes 64 / PC apart), piece
