@@ -93,7 +93,6 @@ def settle(step, stream, ms=SETTLE_MS, chunk=25):
     about 20 ms of load and the step time with them (128^3 MIXED step, 5-step regions
     from a cold start: 0.089-0.098 ms over the first 7 ms, 0.0815 ms from 20 ms on);
     the steps run here are reported (`settle_steps`) and not counted as warm-up."""
-    import torch
     t0 = time.perf_counter()
     done = 0
     while True:
