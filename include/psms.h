@@ -181,8 +181,8 @@ int psms_index_maps(psms_ctx* c, int32_t* d_out);
  * context's stream around each of the step's kernels, synchronises, and
  * writes the average duration in milliseconds of each stage to h_ms[0..3]:
  * y-inverse, x stage with products, y-forward, z stage with the update.
- * The steps are launched eagerly (events between kernels), never from a
- * graph: the kernels are the ones psms_step replays. */
+ * The steps are launched directly (events between kernels), never from a
+ * graph: the kernels are the ones psms_step launches. */
 int psms_stage_times(psms_ctx* c, int32_t nsteps, double* h_ms);
 
 /* ---------------------------------------------------------------------------
