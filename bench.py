@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 METRIC = "grid-points·timesteps/s for NS+CH step (FP64 vs mixed) + % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 STAGES = ["y_inverse", "x_products", "y_forward", "z_update"]
-KERNELS = {"y_inverse": "k_lines<inverse>", "x_products": "k_xstep", "y_forward": "k_lines<forward>",
+KERNELS = {"y_inverse": "k_ystep<+1>", "x_products": "k_xstep", "y_forward": "k_ystep<-1>",
            "z_update": "k_zstep"}
 
 
