@@ -411,6 +411,23 @@ def step_traffic(precision):
     return None if any(v is None for v in t) else sum(t)
 
 
+def channel_traffic(precision):
+    """Counted HBM bytes of one 256 x 128 x 129 channel step from the committed counter
+    record (profiles/channel256_hbm_counters.json), or None if the sources it was taken
+    with have changed."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "channel256_hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_step"].get(precision)
+
+
 def cpu_baseline(n, p, u, phi, budget_s=20.0):
     """The FP64 oracle on the host: init, then as many steps as fit in ~budget_s.
     Also returns the oracle's states after its first and second steps, from which the
@@ -468,6 +485,9 @@ def main():
                     help="skip the batched, adjoint, channel wall-solve and channel-step measurements")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first copy a buffer of this many MiB 3 times (HBM counter calibration)")
+    ap.add_argument("--channel-only", action="store_true",
+                    help="measure only the 256 x 128 x 129 channel step (--steps timed after --warmup, "
+                         "both precisions) and print its JSON record (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -483,6 +503,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.channel_only:
+        print(json.dumps(bench_channel(args.steps, args.warmup)), flush=True)
+        return
     name = "drops16_128"
     p, u, phi = synth.box_case(name)
     n = p["n"]
@@ -557,7 +580,8 @@ def main():
         nx, ny, nz = cf["grid"]
         for prec in ("mixed", "fp64"):
             out["rooflines"]["channel_%s_step" % prec] = roofline_entry(
-                channel_model_bytes(nx, ny, nz - 1, prec == "mixed"), cf[prec]["ms_per_step"])
+                channel_model_bytes(nx, ny, nz - 1, prec == "mixed"), cf[prec]["ms_per_step"],
+                channel_traffic(prec) if (nx, ny, nz) == (256, 128, 129) else None)
     if "batched" in forms:
         bf = forms["batched"]
         nb = sum(cnt * step_model_bytes(nn, True) for nn, cnt in bf["groups"])
